@@ -1,0 +1,249 @@
+/*
+ * rv.h -- C ABI of librv, a per-barrier-interval SIMT data-race checker for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (arXiv 2503.08946):
+ *   The paper models a GPU kernel as integer sets: a Domain of statement
+ *   instances, Read and Write access relations from instances to array
+ *   elements, and a Schedule that orders the instances (Section 2.1, steps
+ *   1-5; Appendix listings).  Its check intersects the read/write relations
+ *   with the happens-before order to find RaW, WaW and WaR pairs (Section 2.1
+ *   step 6).  A data race is one thread writing data another thread still
+ *   uses (Abstract; Section 1).
+ *
+ *   librv evaluates that model concretely for a SIMT launch.  For every
+ *   barrier interval (the accesses of a block between two barriers) it
+ *   expands each thread's accesses into records (location, instance id,
+ *   read/write) and reports every location that two different threads touch
+ *   in the same interval with at least one write, with a canonical witness
+ *   pair.  Records are grouped by location with a radix sort and reduced by
+ *   a segmented scan on the GPU; nothing runs on the CPU but planning.
+ *
+ * Conventions
+ *   - Every function returns rv_status: RV_OK (0) or a negative code; on an
+ *     error, outputs are left untouched and rv_last_error(ctx) holds a
+ *     message.  Nothing throws across this interface.
+ *   - A context belongs to one device and one HIP stream.  Calls on one
+ *     context must be serialised by the caller; several contexts may share a
+ *     device.
+ *   - Pointers in rv_kernel_desc are host memory owned by the caller and are
+ *     copied by rv_load_kernel_desc.  The workspace passed to rv_ctx_create
+ *     is device memory owned by the caller and must outlive the context.
+ *   - The library allocates small device tables of its own (per kernel: the
+ *     plan; per context: result slots) with hipMalloc.
+ */
+#ifndef RV_H
+#define RV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rv_status;
+enum {
+    RV_OK = 0,
+    RV_ERR_INVALID = -1,      /* malformed description or argument */
+    RV_ERR_UNSUPPORTED = -2,  /* launch z-dimension > 1, or a feature outside this interface */
+    RV_ERR_KEY_BITS = -3,     /* an interval's location space does not fit 31 bits */
+    RV_ERR_RANGE = -4,        /* an affine value may leave int32 over the iteration box */
+    RV_ERR_OOB = -5,          /* an element index left [0, dim) (found on the GPU) */
+    RV_ERR_TOO_LARGE = -6,    /* >= 2^32 instances in one interval, or workspace too small */
+    RV_ERR_BUDGET = -7,       /* a job exceeds a server's memory budget */
+    RV_ERR_DEVICE = -8,       /* a HIP call failed (message carried) */
+    RV_ERR_STATE = -9         /* call not valid in the object's current state */
+};
+
+/* Variables an affine form ranges over. */
+enum {
+    RV_V_TX = 0, RV_V_TY, RV_V_BX, RV_V_BY,   /* threadIdx.x/y, blockIdx.x/y */
+    RV_V_K,                                   /* repetition variable of the enclosing segment */
+    RV_V_L0, RV_V_L1, RV_V_L2,                /* the access's loop variables */
+    RV_V_AUX0, RV_V_AUX1,                     /* auxiliary floor-div / mod terms */
+    RV_NV
+};
+enum { RV_SHARED = 0, RV_GLOBAL = 1 };
+enum { RV_AUX_NONE = 0, RV_AUX_FLOORDIV = 1, RV_AUX_EMOD = 2 };
+
+/* ----------------------------------------------------------- description
+ * The concrete counterpart of the paper's Domain / Read / Write / Schedule
+ * (Section 2.1 steps 2-5; Section 2 lists what must be recovered from a
+ * kernel: thread and block ids, barriers, shared allocations, indices into
+ * arrays, reads and writes).
+ */
+typedef struct { int32_t block[3]; int32_t grid[3]; } rv_launch;     /* [2] must be 1 */
+
+/* An array is a set of elements addressed by a row-major index; arrays never
+ * alias (Section 1: each variable is an array, a set of its index values). */
+typedef struct {
+    int32_t space;            /* RV_SHARED: one copy per block; RV_GLOBAL: one per launch */
+    int32_t ndim;             /* 1..3 */
+    int64_t dim[3];           /* extents >= 1; product < 2^31 */
+} rv_array;
+
+typedef struct { int32_t coef[RV_NV]; int32_t c0; } rv_affine;   /* value = c0 + sum coef[v]*v */
+
+/* aux = floor(e / d) or the Euclidean e mod d (result in [0, d)); e may not
+ * use RV_V_AUX0/1 (Presburger quasi-affine terms, as in the paper's j % 32). */
+typedef struct { int32_t kind; int32_t d; rv_affine e; } rv_aux;
+
+/* One array access per point of the loop box [lo, hi) (nloops <= 3),
+ * executed when every guard is >= 0 (a conjunction of affine constraints,
+ * the paper's Domain restrictions).  idx[d] is the index along dim d. */
+typedef struct {
+    int32_t array;
+    int32_t is_write;
+    int32_t nloops;
+    int32_t loop_lo[3], loop_hi[3];
+    rv_aux aux[2];
+    rv_affine idx[3];
+    int32_t guard_begin, guard_count;        /* range in rv_kernel_desc.guards */
+} rv_access;
+
+typedef struct { rv_affine g; } rv_guard;   /* holds iff g >= 0 */
+
+/* A run of accesses ("code section"); barrier_after != 0 ends it with a
+ * block-wide barrier.  Barriers are block-uniform. */
+typedef struct { int32_t access_begin, access_count, barrier_after; } rv_phase;
+
+/* A run of phases executed repeat times; RV_V_K = k_base + repetition.  The
+ * order of segments, repetitions and phases is the schedule. */
+typedef struct { int32_t phase_begin, phase_count, repeat, k_base; } rv_segment;
+
+typedef struct {
+    rv_launch launch;
+    const rv_array *arrays;     int32_t n_arrays;
+    const rv_access *accesses;  int32_t n_accesses;
+    const rv_guard *guards;     int32_t n_guards;
+    const rv_phase *phases;     int32_t n_phases;
+    const rv_segment *segments; int32_t n_segments;
+} rv_kernel_desc;
+
+/* ---------------------------------------------------------------- results */
+/* One side of a witness: which instance made the access.  loop[] holds the
+ * loop variables' values (0 for unused loops). */
+typedef struct {
+    uint32_t block;        /* blockIdx.y * gridDim.x + blockIdx.x */
+    uint32_t tid;          /* threadIdx.y * blockDim.x + threadIdx.x */
+    uint32_t dyn_phase;    /* index of the executed phase (segments x repeats x phases, in order) */
+    uint32_t access;       /* index into rv_kernel_desc.accesses */
+    int32_t loop[3];
+    int32_t is_write;
+} rv_side;
+
+/* A conflicting location and its canonical pair: `first` is the write with
+ * the smallest instance id; `second` is the smallest-id record of the
+ * location when its thread differs from first's, else the largest-id record.
+ * Instance ids order by (global thread, dynamic phase, access, loop index). */
+typedef struct {
+    uint32_t interval;     /* barrier interval (barriers executed before the access) */
+    int32_t space;         /* RV_SHARED / RV_GLOBAL */
+    int32_t array;
+    uint32_t block;        /* the block owning the shared copy; 0 for global arrays */
+    int64_t address;       /* row-major element index */
+    rv_side first, second;
+} rv_witness;
+
+typedef struct {
+    uint64_t n_records;    /* records emitted (instances whose guards hold) */
+    uint64_t n_conflicts;  /* conflicting locations */
+    int32_t has_witness;
+    int32_t reserved;
+    rv_witness witness;    /* the smallest conflicting location in (interval, space, block, array, address) order */
+} rv_result;
+
+/* Per-stage GPU time, accumulated while timing is enabled (HIP events on the
+ * context's stream around each launch). */
+enum { RV_STAGE_FILL = 0, RV_STAGE_COUNT, RV_STAGE_SCAN, RV_STAGE_EXPAND, RV_STAGE_SORT_SCAN,
+       RV_STAGE_FINISH, RV_NSTAGE };
+typedef struct { double ms[RV_NSTAGE]; uint64_t launches[RV_NSTAGE]; } rv_timing;
+
+/* Static facts about a loaded kernel. */
+typedef struct {
+    uint64_t n_instances;      /* thread x access x loop-point instances before guards */
+    uint32_t n_intervals;
+    uint32_t n_subintervals;   /* key-range passes (an interval with a large location space gets several) */
+    uint32_t n_chunks;         /* workspace-sized groups of passes */
+    uint32_t n_buckets;        /* location buckets over all passes */
+    uint64_t max_interval_instances;
+} rv_kernel_info;
+
+/* A decoded record (debugging and expansion-parity tests). */
+typedef struct {
+    uint32_t interval;
+    int32_t space;
+    uint32_t block;        /* owning block if shared, else 0 */
+    int32_t array;
+    int64_t address;
+    uint32_t gthread, dyn_phase, access, lidx;   /* instance id (lidx: row-major loop index) */
+    int32_t loop[3];
+    int32_t is_write;
+} rv_record;
+
+typedef struct rv_ctx rv_ctx;
+typedef struct rv_kernel rv_kernel;
+
+/* ------------------------------------------------------------- functions */
+
+/* Check a description on the host only (no device).  Returns RV_OK or the
+ * code rv_load_kernel_desc would return for a malformed / unsupported /
+ * out-of-range description; a message is written to msg (cap bytes, always
+ * NUL-terminated when cap > 0). */
+rv_status rv_validate_desc(const rv_kernel_desc *desc, char *msg, size_t cap);
+
+/* Create a context on `device` (hipSetDevice numbering) issuing work on
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  `workspace` is
+ * device memory of `workspace_bytes` (>= 64 MiB) holding the records of one
+ * chunk; larger workspaces allow larger chunks (fewer passes). */
+rv_status rv_ctx_create(rv_ctx **out, int device, void *hip_stream, void *workspace,
+                        size_t workspace_bytes);
+rv_status rv_ctx_destroy(rv_ctx *ctx);
+/* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
+const char *rv_last_error(const rv_ctx *ctx);
+
+/* Validate and plan a description, upload its tables; *out is owned by the
+ * library until rv_free_kernel.  The description is deep-copied. */
+rv_status rv_load_kernel_desc(rv_ctx *ctx, const rv_kernel_desc *desc, rv_kernel **out);
+rv_status rv_free_kernel(rv_ctx *ctx, rv_kernel *k);
+rv_status rv_kernel_get_info(rv_ctx *ctx, const rv_kernel *k, rv_kernel_info *out);
+
+/* Run the check; blocks until the result is on the host (one stream sync).
+ * A kernel with no records gives n_conflicts = 0 and has_witness = 0.
+ * RV_ERR_OOB names the smallest out-of-bounds instance in rv_last_error. */
+rv_status rv_check(rv_ctx *ctx, rv_kernel *k, rv_result *out);
+
+/* Check n kernels together: their passes share the same launches (the
+ * batched pipeline); out[i] is bit-identical to rv_check(ks[i]).  Returns
+ * the first error; kernels before it have valid results. */
+rv_status rv_check_batch(rv_ctx *ctx, rv_kernel *const *ks, size_t n, rv_result *out);
+
+/* Witnesses of k with list index in [first_index, first_index + cap), in
+ * location order; *n_out = number written.  Re-runs the check in collect
+ * mode (the result is deterministic, so windows are consistent). */
+rv_status rv_get_witnesses(rv_ctx *ctx, rv_kernel *k, uint64_t first_index, rv_witness *out,
+                           size_t cap, size_t *n_out);
+
+/* Records of one barrier interval as the expansion wrote them (sorted = 0)
+ * or after the per-bucket sort (sorted = 1: location order; requires every
+ * bucket to fit one on-chip slice, else RV_ERR_UNSUPPORTED).  *n_out is the
+ * number of records; at most cap are written. */
+rv_status rv_debug_records(rv_ctx *ctx, rv_kernel *k, uint32_t interval, int sorted,
+                           rv_record *out, size_t cap, size_t *n_out);
+
+/* Per-stage GPU timing (HIP events around each launch; adds one event pair
+ * per launch).  enable = 0 stops timing; rv_get_timing copies and, if
+ * reset != 0, clears the accumulators. */
+rv_status rv_set_timing(rv_ctx *ctx, int enable);
+rv_status rv_get_timing(rv_ctx *ctx, rv_timing *out, int reset);
+
+/* Host-side self test of the library's integer helpers (division by
+ * invariant integers, key layout); returns RV_OK or RV_ERR_STATE with a
+ * message in msg. */
+rv_status rv_selftest(char *msg, size_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RV_H */

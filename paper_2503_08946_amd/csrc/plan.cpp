@@ -1,0 +1,447 @@
+// Host planner: validates a description, expands its schedule into dynamic
+// phases and barrier intervals, lays out each interval's location space and
+// splits the work into key-range passes and workspace-sized chunks.
+//
+// Schedule and intervals: the paper orders code sections by schedule vectors
+// and derives happens-before from that order (Section 2.1 step 5; the Before
+// relation of the appendix listings).  In a SIMT block only a barrier orders
+// the accesses of different threads, so the unit of the check is the barrier
+// interval: interval(d) = number of barriers executed before dynamic phase d.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "rv_internal.h"
+
+namespace rv {
+
+Magic make_magic(uint32_t d) {
+    Magic g{};
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) l++;
+    // m = floor(2^32 * (2^l - d) / d) + 1 ; fits 32 bits for d <= 2^31
+    uint64_t m = ((((uint64_t)1 << l) - d) << 32) / d + 1;
+    g.m = (uint32_t)m;
+    g.s1 = l ? 1u : 0u;
+    g.s2 = l ? l - 1 : 0u;
+    g.d = d;
+    return g;
+}
+
+static std::string fmt(const char *f, long long a = 0, long long b = 0, long long c = 0) {
+    char buf[256];
+    snprintf(buf, sizeof buf, f, a, b, c);
+    return buf;
+}
+
+rv_status validate(const rv_kernel_desc *d, std::string &msg) {
+    if (!d) { msg = "null description"; return RV_ERR_INVALID; }
+    const rv_launch &L = d->launch;
+    for (int i = 0; i < 2; i++)
+        if (L.block[i] < 1 || L.grid[i] < 1) { msg = "launch dimensions must be >= 1"; return RV_ERR_INVALID; }
+    if (L.block[2] < 1 || L.grid[2] < 1) { msg = "launch z dimension must be 1"; return RV_ERR_INVALID; }
+    if (L.block[2] > 1 || L.grid[2] > 1) { msg = "launch z dimension > 1 is not supported"; return RV_ERR_UNSUPPORTED; }
+    if (d->n_arrays < 0 || d->n_accesses < 0 || d->n_guards < 0 || d->n_phases < 0 || d->n_segments < 0) {
+        msg = "negative count"; return RV_ERR_INVALID;
+    }
+    if ((d->n_arrays && !d->arrays) || (d->n_accesses && !d->accesses) || (d->n_guards && !d->guards) ||
+        (d->n_phases && !d->phases) || (d->n_segments && !d->segments)) {
+        msg = "null table with a nonzero count"; return RV_ERR_INVALID;
+    }
+    for (int i = 0; i < d->n_arrays; i++) {
+        const rv_array &a = d->arrays[i];
+        if (a.space != RV_SHARED && a.space != RV_GLOBAL) { msg = fmt("array %lld: bad space", i); return RV_ERR_INVALID; }
+        if (a.ndim < 1 || a.ndim > 3) { msg = fmt("array %lld: ndim must be 1..3", i); return RV_ERR_INVALID; }
+        long double n = 1;
+        for (int j = 0; j < a.ndim; j++) {
+            if (a.dim[j] < 1) { msg = fmt("array %lld: dims must be >= 1", i); return RV_ERR_INVALID; }
+            n *= (long double)a.dim[j];
+        }
+        if (n >= 2147483648.0L) { msg = fmt("array %lld: more than 2^31-1 elements", i); return RV_ERR_KEY_BITS; }
+    }
+    for (int i = 0; i < d->n_accesses; i++) {
+        const rv_access &a = d->accesses[i];
+        if (a.array < 0 || a.array >= d->n_arrays) { msg = fmt("access %lld: bad array", i); return RV_ERR_INVALID; }
+        if (a.nloops < 0 || a.nloops > 3) { msg = fmt("access %lld: nloops must be 0..3", i); return RV_ERR_INVALID; }
+        for (int l = 0; l < a.nloops; l++)
+            if (a.loop_lo[l] > a.loop_hi[l]) { msg = fmt("access %lld: loop %lld has lo > hi", i, l); return RV_ERR_INVALID; }
+        for (int x = 0; x < 2; x++) {
+            const rv_aux &u = a.aux[x];
+            if (u.kind < RV_AUX_NONE || u.kind > RV_AUX_EMOD) { msg = fmt("access %lld: bad aux kind", i); return RV_ERR_INVALID; }
+            if (u.kind != RV_AUX_NONE && u.d < 1) { msg = fmt("access %lld: aux divisor must be >= 1", i); return RV_ERR_INVALID; }
+            if (u.e.coef[RV_V_AUX0] || u.e.coef[RV_V_AUX1]) {
+                msg = fmt("access %lld: an aux numerator may not use aux variables", i); return RV_ERR_INVALID;
+            }
+        }
+        if (a.guard_begin < 0 || a.guard_count < 0 || (int64_t)a.guard_begin + a.guard_count > d->n_guards) {
+            msg = fmt("access %lld: bad guard range", i); return RV_ERR_INVALID;
+        }
+    }
+    for (int i = 0; i < d->n_phases; i++) {
+        const rv_phase &p = d->phases[i];
+        if (p.access_begin < 0 || p.access_count < 0 || (int64_t)p.access_begin + p.access_count > d->n_accesses) {
+            msg = fmt("phase %lld: bad access range", i); return RV_ERR_INVALID;
+        }
+    }
+    for (int i = 0; i < d->n_segments; i++) {
+        const rv_segment &s = d->segments[i];
+        if (s.phase_begin < 0 || s.phase_count < 0 || (int64_t)s.phase_begin + s.phase_count > d->n_phases) {
+            msg = fmt("segment %lld: bad phase range", i); return RV_ERR_INVALID;
+        }
+        if (s.repeat < 1) { msg = fmt("segment %lld: repeat must be >= 1", i); return RV_ERR_INVALID; }
+    }
+    return RV_OK;
+}
+
+static uint64_t arr_size(const rv_array &a) {
+    uint64_t n = 1;
+    for (int j = 0; j < a.ndim; j++) n *= (uint64_t)a.dim[j];
+    return n;
+}
+
+// Upper bound of |value| of an affine row over the iteration box.
+static long double row_bound(const int32_t *row, const long double *vmax) {
+    long double b = std::fabs((long double)row[C_C0]);
+    for (int v = 0; v < C_C0; v++) b += std::fabs((long double)row[v]) * vmax[v];
+    return b;
+}
+
+rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::string &msg) {
+    rv_status st = validate(d, msg);
+    if (st) return st;
+    k.launch = d->launch;
+    k.arrays.assign(d->arrays, d->arrays + d->n_arrays);
+    k.accesses.assign(d->accesses, d->accesses + d->n_accesses);
+    k.guards.assign(d->guards, d->guards + d->n_guards);
+    k.phases.assign(d->phases, d->phases + d->n_phases);
+    k.segments.assign(d->segments, d->segments + d->n_segments);
+    k.target = target > 0 ? target : DEFAULT_TARGET;
+
+    const uint64_t bdx = d->launch.block[0], bdy = d->launch.block[1];
+    const uint64_t gdx = d->launch.grid[0], gdy = d->launch.grid[1];
+    const uint64_t tpb = bdx * bdy, nblocks = gdx * gdy, nthreads = tpb * nblocks;
+    if (nthreads >= (1ull << 31)) { msg = "more than 2^31 threads"; return RV_ERR_TOO_LARGE; }
+    k.kc.bdx = (uint32_t)bdx; k.kc.bdy = (uint32_t)bdy; k.kc.gdx = (uint32_t)gdx; k.kc.gdy = (uint32_t)gdy;
+    k.kc.tpb = (uint32_t)tpb; k.kc.nthreads = (uint32_t)nthreads; k.kc.nblocks = (uint32_t)nblocks;
+    k.kc.mg_tpb = make_magic((uint32_t)tpb);
+    k.kc.mg_bdx = make_magic((uint32_t)bdx);
+    k.kc.mg_gdx = make_magic((uint32_t)gdx);
+
+    // ---- dynamic phases and barrier intervals
+    uint64_t ndyn = 0;
+    for (auto &s : k.segments) ndyn += (uint64_t)s.repeat * s.phase_count;
+    if (ndyn >= (1ull << 31)) { msg = "too many dynamic phases"; return RV_ERR_TOO_LARGE; }
+    k.dyn_phase.clear(); k.dyn_k.clear(); k.dyn_interval.clear();
+    uint32_t barriers = 0;
+    for (auto &s : k.segments)
+        for (int r = 0; r < s.repeat; r++)
+            for (int j = 0; j < s.phase_count; j++) {
+                uint32_t ph = s.phase_begin + j;
+                k.dyn_phase.push_back(ph);
+                k.dyn_k.push_back(s.k_base + r);
+                k.dyn_interval.push_back(barriers);
+                if (k.phases[ph].barrier_after) barriers++;
+            }
+    k.n_intervals = k.dyn_phase.empty() ? 0 : k.dyn_interval.back() + 1;
+
+    // ---- per interval: entries, layout, ranges, buckets
+    k.entries.clear(); k.hentries.clear(); k.guard_rows.clear(); k.entry_items.clear();
+    k.intervals.assign(k.n_intervals, IntervalPlan());
+    k.subs.clear();
+    k.n_instances = 0; k.max_interval_instances = 0; k.n_buckets = 0;
+    uint32_t d0 = 0;
+    for (uint32_t iv = 0; iv < k.n_intervals; iv++) {
+        IntervalPlan &I = k.intervals[iv];
+        uint32_t d1 = d0;
+        while (d1 < k.dyn_phase.size() && k.dyn_interval[d1] == iv) d1++;
+        I.dphase_begin = d0; I.dphase_end = d1;
+        I.entry_begin = (uint32_t)k.entries.size();
+        I.arr_off.assign(k.arrays.size(), -1);
+        // touched arrays
+        std::vector<char> touched(k.arrays.size(), 0);
+        for (uint32_t dd = d0; dd < d1; dd++) {
+            const rv_phase &ph = k.phases[k.dyn_phase[dd]];
+            for (int a = ph.access_begin; a < ph.access_begin + ph.access_count; a++) touched[k.accesses[a].array] = 1;
+        }
+        uint64_t S = 0, G = 0;
+        for (size_t a = 0; a < k.arrays.size(); a++)
+            if (touched[a] && k.arrays[a].space == RV_SHARED) { I.arr_off[a] = (int64_t)S; S += arr_size(k.arrays[a]); }
+        for (size_t a = 0; a < k.arrays.size(); a++)
+            if (touched[a] && k.arrays[a].space == RV_GLOBAL) { I.arr_off[a] = (int64_t)G; G += arr_size(k.arrays[a]); }
+        I.S = S;
+        I.K = nblocks * S + G;
+        if (I.K >= (1ull << 31)) {
+            msg = fmt("interval %lld: %lld locations do not fit a 31-bit key", iv, (long long)I.K);
+            return RV_ERR_KEY_BITS;
+        }
+        // entries
+        uint64_t M = 0;
+        for (uint32_t dd = d0; dd < d1; dd++) {
+            const rv_phase &ph = k.phases[k.dyn_phase[dd]];
+            const int32_t kval = k.dyn_k[dd];
+            for (int a = ph.access_begin; a < ph.access_begin + ph.access_count; a++) {
+                const rv_access &ac = k.accesses[a];
+                const rv_array &ar = k.arrays[ac.array];
+                DevEntry E{};
+                uint64_t box = 1;
+                for (int l = 0; l < 3; l++) {
+                    if (l < ac.nloops) {
+                        E.lo[l] = ac.loop_lo[l];
+                        E.ext[l] = (uint32_t)((int64_t)ac.loop_hi[l] - ac.loop_lo[l]);
+                    } else {
+                        E.lo[l] = 0;
+                        E.ext[l] = 1;
+                    }
+                    box *= E.ext[l];
+                }
+                if (box >= (1ull << 32)) { msg = fmt("access %lld: loop box too large", a); return RV_ERR_TOO_LARGE; }
+                E.nloops = ac.nloops;
+                E.box = (uint32_t)box;
+                E.off = (uint32_t)M;   // checked below through P
+                E.rw = ac.is_write ? 1u : 0u;
+                for (int j = 0; j < 3; j++) E.dim[j] = j < ar.ndim ? (uint32_t)ar.dim[j] : 1u;
+                if (ar.space == RV_SHARED) { E.loc_mul = (uint32_t)S; E.loc_base = (uint32_t)I.arr_off[ac.array]; }
+                else { E.loc_mul = 0; E.loc_base = (uint32_t)(nblocks * S + I.arr_off[ac.array]); }
+                // value bounds of the variables over the box
+                long double vmax[NC] = {0};
+                vmax[C_TX] = (long double)(bdx - 1); vmax[C_TY] = (long double)(bdy - 1);
+                vmax[C_BX] = (long double)(gdx - 1); vmax[C_BY] = (long double)(gdy - 1);
+                for (int l = 0; l < ac.nloops; l++)
+                    if (E.ext[l] > 0)
+                        vmax[C_L0 + l] = std::max(std::fabs((long double)ac.loop_lo[l]),
+                                                  std::fabs((long double)ac.loop_hi[l] - 1));
+                auto fold = [&](const rv_affine &f, int32_t *row, bool &ok) {
+                    int64_t c0 = (int64_t)f.c0 + (int64_t)f.coef[RV_V_K] * kval;
+                    ok = c0 >= INT32_MIN && c0 <= INT32_MAX;
+                    row[C_TX] = f.coef[RV_V_TX]; row[C_TY] = f.coef[RV_V_TY];
+                    row[C_BX] = f.coef[RV_V_BX]; row[C_BY] = f.coef[RV_V_BY];
+                    row[C_L0] = f.coef[RV_V_L0]; row[C_L1] = f.coef[RV_V_L1]; row[C_L2] = f.coef[RV_V_L2];
+                    row[C_A0] = f.coef[RV_V_AUX0]; row[C_A1] = f.coef[RV_V_AUX1];
+                    row[C_C0] = (int32_t)c0;
+                };
+                const long double LIM = 2147483647.0L;
+                bool ok = true;
+                for (int x = 0; x < 2; x++) {
+                    const rv_aux &u = ac.aux[x];
+                    E.aux_kind[x] = u.kind;
+                    if (u.kind == RV_AUX_NONE) { E.aux_mg[x] = make_magic(1); continue; }
+                    fold(u.e, E.row[3 + x], ok);
+                    long double b = row_bound(E.row[3 + x], vmax);
+                    if (!ok || b > LIM) { msg = fmt("access %lld: aux term may leave int32", a); return RV_ERR_RANGE; }
+                    E.aux_mg[x] = make_magic((uint32_t)u.d);
+                    vmax[C_A0 + x] = u.kind == RV_AUX_FLOORDIV ? b / (long double)u.d + 1 : (long double)(u.d - 1);
+                }
+                for (int j = 0; j < ar.ndim; j++) {
+                    fold(ac.idx[j], E.row[j], ok);
+                    if (!ok || row_bound(E.row[j], vmax) > LIM) {
+                        msg = fmt("access %lld: index %lld may leave int32", a, j); return RV_ERR_RANGE;
+                    }
+                }
+                E.guard_begin = (uint32_t)(k.guard_rows.size() / NC);
+                E.guard_count = (uint32_t)ac.guard_count;
+                for (int g = ac.guard_begin; g < ac.guard_begin + ac.guard_count; g++) {
+                    int32_t row[NC];
+                    fold(k.guards[g].g, row, ok);
+                    if (!ok || row_bound(row, vmax) > LIM) { msg = fmt("access %lld: guard may leave int32", a); return RV_ERR_RANGE; }
+                    k.guard_rows.insert(k.guard_rows.end(), row, row + NC);
+                }
+                // work items: lch loop points x gt threads per lane
+                if (E.box > 0) {
+                    E.lch = std::min<uint32_t>(E.box, RPL);
+                    E.gt = RPL / E.lch;
+                    E.n_lchunks = (E.box + E.lch - 1) / E.lch;
+                } else {
+                    E.lch = 1; E.gt = 1; E.n_lchunks = 0;
+                }
+                M += box;
+                k.entries.push_back(E);
+                k.hentries.push_back(HostEntry{dd, (uint32_t)a, kval});
+            }
+        }
+        I.entry_count = (uint32_t)k.entries.size() - I.entry_begin;
+        I.M = M;
+        I.P = M * nthreads;
+        if (I.P >= (1ull << 32)) {
+            msg = fmt("interval %lld: %lld instances (must be < 2^32)", iv, (long long)I.P);
+            return RV_ERR_TOO_LARGE;
+        }
+        k.n_instances += I.P;
+        k.max_interval_instances = std::max(k.max_interval_instances, I.P);
+        // entry work-item prefix
+        I.items_begin = (uint32_t)k.entry_items.size();
+        uint64_t items = 0;
+        for (uint32_t e = 0; e < I.entry_count; e++) {
+            DevEntry &E = k.entries[I.entry_begin + e];
+            k.entry_items.push_back((uint32_t)items);
+            uint64_t per = (uint64_t)EXP_WG * E.gt;
+            uint64_t gtiles = (nthreads + per - 1) / per;
+            items += (uint64_t)E.n_lchunks * gtiles;
+        }
+        k.entry_items.push_back((uint32_t)items);
+        if (items >= (1ull << 31)) { msg = "too many work items"; return RV_ERR_TOO_LARGE; }
+        I.items = (uint32_t)items;
+        // buckets: aim for `target` records per bucket on average
+        if (I.P > 0 && I.K > 0) {
+            long double ratio = (long double)k.target * (long double)I.K / (long double)I.P;
+            int s = ratio >= 1 ? (int)std::floor(std::log2((double)ratio)) : 0;
+            s = std::max(0, std::min(SMAX, s));
+            I.s = (uint32_t)s;
+            uint64_t span = (uint64_t)NBMAX << s;   // locations per pass
+            I.nsub = (uint32_t)((I.K + span - 1) / span);
+            I.nb = (uint32_t)((I.K + (1ull << s) - 1) >> s);
+            for (uint32_t q = 0; q < I.nsub; q++) {
+                SubPlan sp{};
+                sp.interval = iv;
+                sp.klo = (uint32_t)(q * span);
+                sp.khi = (uint32_t)std::min<uint64_t>(I.K, (q + 1) * span);
+                sp.s = (uint32_t)s;
+                sp.nb = (uint32_t)(((uint64_t)sp.khi - sp.klo + (1ull << s) - 1) >> s);
+                k.n_buckets += sp.nb;
+                k.subs.push_back(sp);
+            }
+        }
+        d0 = d1;
+    }
+    return RV_OK;
+}
+
+WorkspaceLayout layout_workspace(size_t bytes) {
+    WorkspaceLayout L{};
+    const size_t reserve = 1 << 20;
+    if (bytes < reserve + (size_t)TILE * 8 * 4) return L;
+    // records : buckets = 8 B : 16 B per 256 records
+    size_t R = (size_t)(((long double)(bytes - reserve)) / (8.0L + 16.0L / 256.0L));
+    R = std::min<size_t>(R, (size_t)0xFFF00000u);
+    size_t BC = std::max<size_t>(1 << 16, R / 256);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = al(R * 8);
+    L.off_counts = off; off = al(off + BC * 4);
+    L.off_starts = off; off = al(off + BC * 4);
+    L.off_cursor = off; off = al(off + BC * 4);
+    L.off_conf = off; off = al(off + BC * 4);
+    L.off_bsum = off; off = al(off + scan_bsum_words(BC) * 4);
+    if (off > bytes) {   // shrink the record area to fit exactly
+        size_t over = off - bytes;
+        size_t dr = (over + 7) / 8 + 64;
+        if (dr >= R) return WorkspaceLayout{};
+        R -= dr;
+        off = al(R * 8);
+        L.off_counts = off; off = al(off + BC * 4);
+        L.off_starts = off; off = al(off + BC * 4);
+        L.off_cursor = off; off = al(off + BC * 4);
+        L.off_conf = off; off = al(off + BC * 4);
+        L.off_bsum = off; off = al(off + scan_bsum_words(BC) * 4);
+    }
+    L.cap_records = R;
+    L.cap_buckets = BC;
+    L.bytes = off;
+    return L;
+}
+
+rv_status plan_chunks(rv_kernel &k, const WorkspaceLayout &L, std::string &msg) {
+    k.chunks.clear();
+    ChunkPlan cur{0, 0, 0, 0, 0};
+    for (uint32_t i = 0; i < k.subs.size(); i++) {
+        const SubPlan &sp = k.subs[i];
+        const IntervalPlan &I = k.intervals[sp.interval];
+        if (I.P > L.cap_records || sp.nb > L.cap_buckets) {
+            msg = fmt("interval %lld needs %lld records of workspace; the workspace holds %lld",
+                      sp.interval, (long long)I.P, (long long)L.cap_records);
+            return RV_ERR_TOO_LARGE;
+        }
+        if (cur.sub_end > cur.sub_begin &&
+            (cur.records_bound + I.P > L.cap_records || cur.buckets + sp.nb > L.cap_buckets ||
+             cur.items + I.items >= (1ull << 31))) {
+            k.chunks.push_back(cur);
+            cur = ChunkPlan{i, i, 0, 0, 0};
+        }
+        cur.sub_end = i + 1;
+        cur.records_bound += I.P;
+        cur.buckets += sp.nb;
+        cur.items += I.items;
+    }
+    if (cur.sub_end > cur.sub_begin) k.chunks.push_back(cur);
+    return RV_OK;
+}
+
+void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0, std::vector<DevSub> &out,
+                  uint64_t &items, uint64_t &buckets) {
+    for (uint32_t i = sb; i < se; i++) {
+        const SubPlan &sp = k.subs[i];
+        const IntervalPlan &I = k.intervals[sp.interval];
+        DevSub D{};
+        D.entries = k.d_entries + I.entry_begin;
+        D.guards = k.d_guards;
+        D.entry_items = k.d_entry_items + I.items_begin;
+        D.kc = k.d_kc;
+        D.n_entries = I.entry_count;
+        D.item_begin = (uint32_t)items;
+        D.bucket_begin = (uint32_t)buckets;
+        D.nb = sp.nb;
+        D.s = sp.s;
+        D.klo = sp.klo;
+        D.khi = sp.khi;
+        D.M = (uint32_t)I.M;
+        D.mgM = make_magic((uint32_t)I.M);
+        D.interval = sp.interval;
+        D.res = res0 + (i - sb);
+        items += I.items;
+        buckets += sp.nb;
+        out.push_back(D);
+    }
+}
+
+void decode_instance(const rv_kernel &k, uint32_t interval, uint32_t id, rv_side &side, uint32_t &gthread,
+                     uint32_t &lidx) {
+    const IntervalPlan &I = k.intervals[interval];
+    gthread = (uint32_t)(id / I.M);
+    uint32_t r = (uint32_t)(id % I.M);
+    // entries are in increasing offset order
+    uint32_t lo = I.entry_begin, hi = I.entry_begin + I.entry_count;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) / 2;
+        if (k.entries[mid].off <= r) lo = mid; else hi = mid;
+    }
+    while (lo + 1 < I.entry_begin + I.entry_count && k.entries[lo].box == 0) lo++;
+    const DevEntry &E = k.entries[lo];
+    lidx = r - E.off;
+    side.block = gthread / k.kc.tpb;
+    side.tid = gthread % k.kc.tpb;
+    side.dyn_phase = k.hentries[lo].dphase;
+    side.access = k.hentries[lo].access;
+    uint32_t rem = lidx;
+    int32_t lv[3] = {0, 0, 0};
+    for (int l = (int)E.nloops - 1; l >= 0; l--) {
+        lv[l] = E.lo[l] + (int32_t)(rem % E.ext[l]);
+        rem /= E.ext[l];
+    }
+    side.loop[0] = lv[0]; side.loop[1] = lv[1]; side.loop[2] = lv[2];
+    side.is_write = (int32_t)E.rw;
+}
+
+void decode_location(const rv_kernel &k, uint32_t interval, uint32_t loc, int32_t &space, int32_t &array,
+                     uint32_t &block, int64_t &address) {
+    const IntervalPlan &I = k.intervals[interval];
+    uint64_t shared_end = (uint64_t)k.kc.nblocks * I.S;
+    uint64_t rem;
+    if (loc < shared_end) {
+        space = RV_SHARED;
+        block = (uint32_t)(loc / I.S);
+        rem = loc % I.S;
+    } else {
+        space = RV_GLOBAL;
+        block = 0;
+        rem = loc - shared_end;
+    }
+    array = -1;
+    address = 0;
+    for (size_t a = 0; a < k.arrays.size(); a++) {
+        if (I.arr_off[a] < 0 || k.arrays[a].space != space) continue;
+        uint64_t off = (uint64_t)I.arr_off[a], n = arr_size(k.arrays[a]);
+        if (rem >= off && rem < off + n) { array = (int32_t)a; address = (int64_t)(rem - off); break; }
+    }
+}
+
+}  // namespace rv

@@ -1,0 +1,242 @@
+// Internal types of librv shared by the host planner (plan.cpp, api.cpp) and
+// the gfx950 kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "rv.h"
+
+namespace rv {
+
+// ---------------------------------------------------------------- tuning
+constexpr int EXP_WG = 256;              // expansion workgroup (4 waves)
+constexpr int RPL = 16;                  // records per lane per work item
+constexpr int TILE = EXP_WG * RPL;       // records per expansion work item
+constexpr int NBMAX = 4096;              // location buckets per key-range pass
+constexpr int SMAX = 9;                  // a bucket spans at most 2^SMAX locations
+constexpr int BKT_WG = 512;              // sort + scan workgroup (8 waves)
+constexpr int BKT_RPL = 16;              // records per lane in one on-chip slice
+constexpr int CAP = BKT_WG * BKT_RPL;    // records per on-chip slice
+constexpr int DEFAULT_TARGET = 4096;     // planner: mean records per bucket
+
+static_assert((1 << SMAX) <= BKT_WG, "one bucket location per sort+scan thread");
+
+// ------------------------------------------- division by invariant integers
+// floor(n / d) for 32-bit n and a divisor d >= 1 fixed at plan time:
+// t = mulhi(n, m); q = (t + ((n - t) >> s1)) >> s2 with l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1), s2 = max(l - 1, 0)
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, section 4).
+struct Magic {
+    uint32_t m, s1, s2, d;
+};
+
+__host__ __device__ inline uint32_t udiv(uint32_t n, Magic g) {
+    uint32_t t = (uint32_t)(((uint64_t)n * g.m) >> 32);
+    return (t + ((n - t) >> g.s1)) >> g.s2;
+}
+
+// floor division of a signed value: for n < 0, floor(n / d) = -(floor((-n-1)/d) + 1) = ~floor(~n / d).
+__host__ __device__ inline int32_t fdiv(int32_t n, Magic g) {
+    uint32_t u = n >= 0 ? (uint32_t)n : ~(uint32_t)n;
+    uint32_t q = udiv(u, g);
+    return n >= 0 ? (int32_t)q : (int32_t)~q;
+}
+
+// Euclidean remainder in [0, d).
+__host__ __device__ inline int32_t emod(int32_t n, Magic g) {
+    return n - (int32_t)g.d * fdiv(n, g);
+}
+
+Magic make_magic(uint32_t d);
+
+// --------------------------------------------------------- device tables
+// Coefficient slots of a device row; the segment variable k is folded into
+// the constant because every entry belongs to one dynamic phase.
+enum { C_TX = 0, C_TY, C_BX, C_BY, C_L0, C_L1, C_L2, C_A0, C_A1, C_C0, NC };
+
+// One (dynamic phase, access) pair of one barrier interval.
+struct DevEntry {
+    int32_t row[5][NC];        // idx dim 0..2, aux0 numerator, aux1 numerator
+    int32_t aux_kind[2];
+    Magic aux_mg[2];
+    uint32_t dim[3];           // unused dims hold 1 (their rows are zero)
+    int32_t lo[3];             // unused loops: lo 0, ext 1
+    uint32_t ext[3];
+    uint32_t nloops;
+    uint32_t box;              // loop points per thread
+    uint32_t off;              // first instance offset inside the interval's per-thread range
+    uint32_t loc_mul;          // location = block * loc_mul + loc_base + flat
+    uint32_t loc_base;
+    uint32_t rw;
+    uint32_t guard_begin;      // rows (NC int32 each) in the kernel's guard table
+    uint32_t guard_count;
+    uint32_t lch;              // loop points per lane per work item
+    uint32_t gt;               // threads per lane per work item
+    uint32_t n_lchunks;        // work items along the loop box
+};
+
+struct DevKernel {
+    uint32_t bdx, bdy, gdx, gdy, tpb, nthreads, nblocks, pad;
+    Magic mg_tpb, mg_bdx, mg_gdx;
+};
+
+// One key-range pass over one interval (a "sub-interval").  Begin offsets are
+// relative to the chunk the pass runs in.
+struct DevSub {
+    const DevEntry *entries;
+    const int32_t *guards;
+    const uint32_t *entry_items;   // exclusive prefix of work items per entry (n_entries + 1)
+    const DevKernel *kc;
+    uint32_t n_entries;
+    uint32_t item_begin;
+    uint32_t bucket_begin;
+    uint32_t nb;                   // buckets
+    uint32_t s;                    // bucket = (loc - klo) >> s
+    uint32_t klo, khi;             // location range of the pass
+    uint32_t M;                    // instances per thread in the interval
+    Magic mgM;
+    uint32_t interval;
+    uint32_t res;                  // result slot
+};
+
+// Per-pass result slot (device).
+struct SubResult {
+    unsigned long long records;
+    unsigned long long conflicts;
+    unsigned long long oob;        // (interval << 32) | instance id; ~0 when none
+    uint32_t first_bucket;         // chunk-relative; ~0 when none
+    uint32_t pad;
+    uint32_t w[4];                 // location, first id, second id, second is_write
+};
+static_assert(sizeof(SubResult) == 48, "SubResult layout");
+
+// Device witness of the collect mode: the SubResult-style words plus the pass.
+struct DevWitness {
+    uint32_t w[4];
+    uint32_t sub;
+    uint32_t pad[3];
+};
+
+// ------------------------------------------------------------ host plan
+struct HostEntry {
+    uint32_t dphase, access;
+    int32_t kval;
+};
+
+struct IntervalPlan {
+    uint32_t entry_begin = 0, entry_count = 0;
+    uint64_t M = 0;                // instances per thread
+    uint64_t P = 0;                // instances (nthreads * M)
+    uint64_t K = 0;                // locations
+    uint64_t S = 0;                // shared elements per block in this interval's layout
+    std::vector<int64_t> arr_off;  // per array: offset in its region, -1 when untouched
+    uint32_t s = 0, nb = 0, nsub = 0;
+    uint32_t items = 0;
+    uint32_t items_begin = 0;      // offset into KernelPlan::entry_items
+    uint32_t dphase_begin = 0, dphase_end = 0;
+};
+
+struct SubPlan {
+    uint32_t interval;
+    uint32_t klo, khi, s, nb;
+};
+
+struct ChunkPlan {
+    uint32_t sub_begin, sub_end;
+    uint64_t items, buckets, records_bound;
+};
+
+struct WorkspaceLayout {
+    size_t cap_records = 0;        // records per chunk
+    size_t cap_buckets = 0;        // buckets per chunk
+    size_t off_counts = 0, off_starts = 0, off_cursor = 0, off_conf = 0, off_bsum = 0;
+    size_t bytes = 0;
+};
+
+}  // namespace rv
+
+// The opaque handles of rv.h.
+struct rv_kernel {
+    // copied description
+    rv_launch launch{};
+    std::vector<rv_array> arrays;
+    std::vector<rv_access> accesses;
+    std::vector<rv_guard> guards;
+    std::vector<rv_phase> phases;
+    std::vector<rv_segment> segments;
+    // schedule
+    std::vector<uint32_t> dyn_phase;
+    std::vector<int32_t> dyn_k;
+    std::vector<uint32_t> dyn_interval;
+    uint32_t n_intervals = 0;
+    // plan
+    rv::DevKernel kc{};
+    std::vector<rv::DevEntry> entries;
+    std::vector<rv::HostEntry> hentries;
+    std::vector<int32_t> guard_rows;
+    std::vector<uint32_t> entry_items;
+    std::vector<rv::IntervalPlan> intervals;
+    std::vector<rv::SubPlan> subs;
+    std::vector<rv::ChunkPlan> chunks;
+    uint64_t n_instances = 0;
+    uint64_t max_interval_instances = 0;
+    uint64_t n_buckets = 0;
+    int target = rv::DEFAULT_TARGET;
+    // device copies
+    void *d_mem = nullptr;
+    rv::DevKernel *d_kc = nullptr;
+    rv::DevEntry *d_entries = nullptr;
+    int32_t *d_guards = nullptr;
+    uint32_t *d_entry_items = nullptr;
+    rv::DevSub *d_subs = nullptr;   // all passes, begins relative to this kernel's own chunks
+    std::vector<rv::DevSub> h_subs;
+    rv_ctx *owner = nullptr;
+};
+
+namespace rv {
+
+// plan.cpp
+rv_status validate(const rv_kernel_desc *d, std::string &msg);
+rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::string &msg);
+WorkspaceLayout layout_workspace(size_t bytes);
+rv_status plan_chunks(rv_kernel &k, const WorkspaceLayout &L, std::string &msg);
+// Append DevSub entries for passes [sb, se) of k.  Item and bucket begins
+// continue from *items / *buckets (relative to the chunk); pass i gets result
+// slot res0 + (i - sb).
+void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0,
+                  std::vector<DevSub> &out, uint64_t &items, uint64_t &buckets);
+// Decode helpers (host)
+void decode_instance(const rv_kernel &k, uint32_t interval, uint32_t id, rv_side &side,
+                     uint32_t &gthread, uint32_t &lidx);
+void decode_location(const rv_kernel &k, uint32_t interval, uint32_t loc, int32_t &space,
+                     int32_t &array, uint32_t &block, int64_t &address);
+
+// kernels.hip launchers (all asynchronous on `st`)
+struct Timer;
+void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
+void launch_init_results(SubResult *r, size_t n, hipStream_t st);
+void launch_hist(const DevSub *subs, uint32_t nsub, uint64_t items, uint32_t *counts, SubResult *res,
+                 hipStream_t st);
+void launch_scan(const uint32_t *in, uint32_t *starts, uint32_t *cursor, uint32_t *bsum, size_t n,
+                 hipStream_t st);
+void launch_scatter(const DevSub *subs, uint32_t nsub, uint64_t items, unsigned long long *rec,
+                    uint32_t *cursor, hipStream_t st);
+void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
+                   const uint32_t *starts, const uint32_t *counts, uint32_t *conf, int debug_sorted,
+                   hipStream_t st);
+void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf,
+                   SubResult *res, hipStream_t st);
+void launch_first(const DevSub *subs, uint32_t nsub, const unsigned long long *rec,
+                  const uint32_t *starts, SubResult *res, hipStream_t st);
+void launch_gather(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const unsigned long long *rec,
+                   const uint32_t *starts, const uint32_t *conf, const uint32_t *wpos,
+                   unsigned long long base, unsigned long long lo, unsigned long long hi,
+                   DevWitness *out, hipStream_t st);
+size_t scan_bsum_words(size_t n);
+
+}  // namespace rv

@@ -1,0 +1,392 @@
+"""ctypes binding of librv (include/rv.h).
+
+Argument marshalling only: every step of the check runs in librv's gfx950
+kernels.  There is no CPU path; if librv.so is missing or no GPU is present,
+the calls fail.  PyTorch is used for one thing: allocating the device
+workspace and naming the current HIP stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librv.so")
+
+RV_NV = 10
+STATUS = {0: "RV_OK", -1: "RV_ERR_INVALID", -2: "RV_ERR_UNSUPPORTED", -3: "RV_ERR_KEY_BITS",
+          -4: "RV_ERR_RANGE", -5: "RV_ERR_OOB", -6: "RV_ERR_TOO_LARGE", -7: "RV_ERR_BUDGET",
+          -8: "RV_ERR_DEVICE", -9: "RV_ERR_STATE"}
+STAGES = ("fill", "count", "scan", "expand", "sort_scan", "finish")
+
+
+class RVError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+# ----------------------------------------------------------- C structures
+i32, i64, u32, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+
+
+class rv_launch(ctypes.Structure):
+    _fields_ = [("block", i32 * 3), ("grid", i32 * 3)]
+
+
+class rv_array(ctypes.Structure):
+    _fields_ = [("space", i32), ("ndim", i32), ("dim", i64 * 3)]
+
+
+class rv_affine(ctypes.Structure):
+    _fields_ = [("coef", i32 * RV_NV), ("c0", i32)]
+
+
+class rv_aux(ctypes.Structure):
+    _fields_ = [("kind", i32), ("d", i32), ("e", rv_affine)]
+
+
+class rv_access(ctypes.Structure):
+    _fields_ = [("array", i32), ("is_write", i32), ("nloops", i32), ("loop_lo", i32 * 3),
+                ("loop_hi", i32 * 3), ("aux", rv_aux * 2), ("idx", rv_affine * 3),
+                ("guard_begin", i32), ("guard_count", i32)]
+
+
+class rv_guard(ctypes.Structure):
+    _fields_ = [("g", rv_affine)]
+
+
+class rv_phase(ctypes.Structure):
+    _fields_ = [("access_begin", i32), ("access_count", i32), ("barrier_after", i32)]
+
+
+class rv_segment(ctypes.Structure):
+    _fields_ = [("phase_begin", i32), ("phase_count", i32), ("repeat", i32), ("k_base", i32)]
+
+
+class rv_kernel_desc(ctypes.Structure):
+    _fields_ = [("launch", rv_launch),
+                ("arrays", ctypes.POINTER(rv_array)), ("n_arrays", i32),
+                ("accesses", ctypes.POINTER(rv_access)), ("n_accesses", i32),
+                ("guards", ctypes.POINTER(rv_guard)), ("n_guards", i32),
+                ("phases", ctypes.POINTER(rv_phase)), ("n_phases", i32),
+                ("segments", ctypes.POINTER(rv_segment)), ("n_segments", i32)]
+
+
+class rv_side(ctypes.Structure):
+    _fields_ = [("block", u32), ("tid", u32), ("dyn_phase", u32), ("access", u32),
+                ("loop", i32 * 3), ("is_write", i32)]
+
+
+class rv_witness(ctypes.Structure):
+    _fields_ = [("interval", u32), ("space", i32), ("array", i32), ("block", u32),
+                ("address", i64), ("first", rv_side), ("second", rv_side)]
+
+
+class rv_result(ctypes.Structure):
+    _fields_ = [("n_records", u64), ("n_conflicts", u64), ("has_witness", i32),
+                ("reserved", i32), ("witness", rv_witness)]
+
+
+class rv_timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 6), ("launches", u64 * 6)]
+
+
+class rv_kernel_info(ctypes.Structure):
+    _fields_ = [("n_instances", u64), ("n_intervals", u32), ("n_subintervals", u32),
+                ("n_chunks", u32), ("n_buckets", u32), ("max_interval_instances", u64)]
+
+
+class rv_record(ctypes.Structure):
+    _fields_ = [("interval", u32), ("space", i32), ("block", u32), ("array", i32), ("address", i64),
+                ("gthread", u32), ("dyn_phase", u32), ("access", u32), ("lidx", u32),
+                ("loop", i32 * 3), ("is_write", i32)]
+
+
+# --------------------------------------------------------------- library
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"librv.so is not built ({LIB_PATH}); run __graft_entry__.build() "
+                               "or python -m paper_2503_08946_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, V, S = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t
+        sig = {
+            "rv_validate_desc": [P(rv_kernel_desc), ctypes.c_char_p, S],
+            "rv_ctx_create": [P(V), ctypes.c_int, V, V, S],
+            "rv_ctx_destroy": [V],
+            "rv_load_kernel_desc": [V, P(rv_kernel_desc), P(V)],
+            "rv_free_kernel": [V, V],
+            "rv_kernel_get_info": [V, V, P(rv_kernel_info)],
+            "rv_check": [V, V, P(rv_result)],
+            "rv_check_batch": [V, P(V), S, P(rv_result)],
+            "rv_get_witnesses": [V, V, u64, P(rv_witness), S, P(S)],
+            "rv_debug_records": [V, V, u32, ctypes.c_int, P(rv_record), S, P(S)],
+            "rv_set_timing": [V, ctypes.c_int],
+            "rv_get_timing": [V, P(rv_timing), ctypes.c_int],
+            "rv_selftest": [ctypes.c_char_p, S],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = i32
+        L.rv_last_error.argtypes = [V]
+        L.rv_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("rv_validate_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_error", "rv_load_kernel_desc",
+            "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_get_witnesses",
+            "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest")
+
+
+# -------------------------------------------------------------- marshalling
+def _affine(a, out: rv_affine):
+    for v in range(RV_NV):
+        out.coef[v] = int(a[v])
+    out.c0 = int(a[RV_NV])
+
+
+class Marshalled:
+    """A description laid out as the C structures of rv.h (owns the arrays)."""
+
+    def __init__(self, desc):
+        arrays = (rv_array * max(1, len(desc.arrays)))()
+        for i, a in enumerate(desc.arrays):
+            arrays[i].space = int(a.space)
+            arrays[i].ndim = len(a.dims)
+            for j in range(3):
+                arrays[i].dim[j] = int(a.dims[j]) if j < len(a.dims) else 1
+        guards_list = []
+        accesses = (rv_access * max(1, len(desc.accesses)))()
+        for i, ac in enumerate(desc.accesses):
+            c = accesses[i]
+            c.array = int(ac.array)
+            c.is_write = int(bool(ac.is_write))
+            c.nloops = len(ac.loops)
+            for l, (lo, hi) in enumerate(ac.loops):
+                c.loop_lo[l] = int(lo)
+                c.loop_hi[l] = int(hi)
+            for x in range(2):
+                c.aux[x].kind = int(ac.aux[x].kind)
+                c.aux[x].d = int(ac.aux[x].d)
+                _affine(ac.aux[x].e, c.aux[x].e)
+            for d in range(len(ac.idx)):
+                _affine(ac.idx[d], c.idx[d])
+            c.guard_begin = len(guards_list)
+            c.guard_count = len(ac.guards)
+            guards_list.extend(ac.guards)
+        guards = (rv_guard * max(1, len(guards_list)))()
+        for i, g in enumerate(guards_list):
+            _affine(g, guards[i].g)
+        phases = (rv_phase * max(1, len(desc.phases)))()
+        for i, p in enumerate(desc.phases):
+            phases[i].access_begin = int(p.access_begin)
+            phases[i].access_count = int(p.access_count)
+            phases[i].barrier_after = int(bool(p.barrier_after))
+        segs = (rv_segment * max(1, len(desc.segments)))()
+        for i, s in enumerate(desc.segments):
+            segs[i].phase_begin = int(s.phase_begin)
+            segs[i].phase_count = int(s.phase_count)
+            segs[i].repeat = int(s.repeat)
+            segs[i].k_base = int(s.k_base)
+        d = rv_kernel_desc()
+        d.launch.block[0], d.launch.block[1], d.launch.block[2] = int(desc.block[0]), int(desc.block[1]), 1
+        d.launch.grid[0], d.launch.grid[1], d.launch.grid[2] = int(desc.grid[0]), int(desc.grid[1]), 1
+        d.arrays, d.n_arrays = arrays, len(desc.arrays)
+        d.accesses, d.n_accesses = accesses, len(desc.accesses)
+        d.guards, d.n_guards = guards, len(guards_list)
+        d.phases, d.n_phases = phases, len(desc.phases)
+        d.segments, d.n_segments = segs, len(desc.segments)
+        self._keep = (arrays, accesses, guards, phases, segs)
+        self.desc = d
+
+
+# ------------------------------------------------------------ Python types
+@dataclass
+class Side:
+    block: int
+    tid: int
+    dphase: int
+    access: int
+    loop: tuple
+    is_write: int
+
+
+@dataclass
+class Witness:
+    interval: int
+    space: int
+    array: int
+    address: int
+    block: int
+    first: Side
+    second: Side
+
+    def key(self):
+        return (self.interval, self.space, self.block, self.array, self.address)
+
+
+@dataclass
+class Result:
+    n_records: int
+    n_conflicts: int
+    witness: Optional[Witness]
+
+
+def _side(s: rv_side) -> Side:
+    return Side(s.block, s.tid, s.dyn_phase, s.access, tuple(s.loop), s.is_write)
+
+
+def _witness(w: rv_witness) -> Witness:
+    return Witness(w.interval, w.space, w.array, w.address, w.block, _side(w.first), _side(w.second))
+
+
+def _result(r: rv_result) -> Result:
+    return Result(r.n_records, r.n_conflicts, _witness(r.witness) if r.has_witness else None)
+
+
+def validate(desc) -> tuple:
+    """Host-only validation: (status, message)."""
+    m = Marshalled(desc)
+    buf = ctypes.create_string_buffer(512)
+    st = lib().rv_validate_desc(ctypes.byref(m.desc), buf, 512)
+    return st, buf.value.decode()
+
+
+def selftest() -> tuple:
+    buf = ctypes.create_string_buffer(256)
+    st = lib().rv_selftest(buf, 256)
+    return st, buf.value.decode()
+
+
+class Kernel:
+    def __init__(self, ctx: "Context", handle: ctypes.c_void_p, desc):
+        self.ctx = ctx
+        self.handle = handle
+        self.desc = desc
+
+    def info(self) -> rv_kernel_info:
+        out = rv_kernel_info()
+        self.ctx._call(lib().rv_kernel_get_info, self.ctx.handle, self.handle, ctypes.byref(out))
+        return out
+
+    def free(self):
+        if self.handle:
+            lib().rv_free_kernel(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle and self.ctx.handle:
+                self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A librv context on one device with a caller-owned workspace.
+
+    ``workspace``: a torch uint8 CUDA tensor, or None to allocate
+    ``workspace_bytes`` with torch.  ``stream``: a torch.cuda.Stream or None
+    for the current stream."""
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 1 << 30, workspace=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("librv needs a GPU: torch.cuda.is_available() is False")
+        self.device = device
+        if workspace is None:
+            workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        self.workspace = workspace
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        st = lib().rv_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel())
+        if st:
+            raise RVError(st, "rv_ctx_create failed")
+        self.handle = h
+
+    def _call(self, f, *args):
+        st = f(*args)
+        if st:
+            raise RVError(st, lib().rv_last_error(self.handle).decode())
+        return st
+
+    def close(self):
+        if self.handle:
+            lib().rv_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- API
+    def load(self, desc) -> Kernel:
+        m = Marshalled(desc)
+        h = ctypes.c_void_p()
+        self._call(lib().rv_load_kernel_desc, self.handle, ctypes.byref(m.desc), ctypes.byref(h))
+        return Kernel(self, h, desc)
+
+    def check(self, k: Kernel) -> Result:
+        out = rv_result()
+        self._call(lib().rv_check, self.handle, k.handle, ctypes.byref(out))
+        return _result(out)
+
+    def check_batch(self, ks: Sequence[Kernel]) -> List[Result]:
+        n = len(ks)
+        arr = (ctypes.c_void_p * max(1, n))(*[k.handle for k in ks])
+        out = (rv_result * max(1, n))()
+        self._call(lib().rv_check_batch, self.handle, arr, n, out)
+        return [_result(out[i]) for i in range(n)]
+
+    def witnesses(self, k: Kernel, first: int = 0, cap: int = 1 << 16) -> List[Witness]:
+        buf = (rv_witness * max(1, cap))()
+        n = ctypes.c_size_t()
+        self._call(lib().rv_get_witnesses, self.handle, k.handle, first, buf, cap, ctypes.byref(n))
+        return [_witness(buf[i]) for i in range(n.value)]
+
+    def debug_records(self, k: Kernel, interval: int, sorted: bool = False, cap: Optional[int] = None):
+        """Records of one interval as an int64 array with columns
+        (interval, space, block, array, address, gthread, dyn_phase, access,
+        lidx, loop0, loop1, loop2, is_write)."""
+        if cap is None:
+            cap = int(k.info().max_interval_instances)
+        buf = (rv_record * max(1, cap))()
+        n = ctypes.c_size_t()
+        self._call(lib().rv_debug_records, self.handle, k.handle, interval, int(sorted), buf, cap,
+                   ctypes.byref(n))
+        m = min(n.value, cap)
+        raw = np.frombuffer(buf, dtype=np.dtype([
+            ("interval", "<u4"), ("space", "<i4"), ("block", "<u4"), ("array", "<i4"), ("address", "<i8"),
+            ("gthread", "<u4"), ("dyn_phase", "<u4"), ("access", "<u4"), ("lidx", "<u4"),
+            ("loop", "<i4", (3,)), ("is_write", "<i4")]))[:m]
+        out = np.empty((m, 13), dtype=np.int64)
+        for j, name in enumerate(("interval", "space", "block", "array", "address", "gthread", "dyn_phase",
+                                  "access", "lidx")):
+            out[:, j] = raw[name]
+        out[:, 9:12] = raw["loop"]
+        out[:, 12] = raw["is_write"]
+        return out
+
+    def set_timing(self, on: bool):
+        self._call(lib().rv_set_timing, self.handle, int(on))
+
+    def timing(self, reset: bool = True) -> dict:
+        t = rv_timing()
+        self._call(lib().rv_get_timing, self.handle, ctypes.byref(t), int(reset))
+        return {name: (t.ms[i], t.launches[i]) for i, name in enumerate(STAGES)}

@@ -1,0 +1,102 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+declared in include/rv.h, its integer helpers pass their self test and the
+host validator returns the documented codes.  No compute call needs a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2503_08946_amd as rv
+from workloads import kernels as K
+from workloads import random_affine as RA
+from workloads.desc import AUX_EMOD, AUX_FLOORDIV, GLOBAL, SHARED, Aux, Builder, aff, rw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:rv_status|const char \*)\s*(rv_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = rv.lib()
+    declared = _declared()
+    assert len(declared) >= 14
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(rv.EXPORTED) == declared
+
+
+def test_host_selftest():
+    st, msg = rv.selftest()
+    assert st == 0, msg
+
+
+@pytest.mark.parametrize("desc", [K.tiny_fixed(), K.tree_reduction(3), K.tiled_matmul(16, 64, 5),
+                                  K.polynomial_product(), K.gespmm_crc(), K.half_index_global()],
+                         ids=lambda d: d.name)
+def test_validate_ok(desc):
+    assert rv.validate(desc) == (0, "")
+
+
+def test_validate_batch_kernels_ok():
+    for d in RA.batch_kernels(seed=4, count=64):
+        assert rv.validate(d)[0] == 0, d.name
+
+
+def _one(access, arrays=((SHARED, (8,)),), block=(8, 1), grid=(1, 1)):
+    b = Builder(block, grid)
+    for sp, dims in arrays:
+        b.array(sp, dims)
+    p = b.phase([access], False)
+    b.segment([p])
+    return b.build()
+
+
+def test_validate_errors():
+    ok = _one(rw(0, True, aff(tx=1)))
+    assert rv.validate(ok)[0] == 0
+    # bad array index
+    assert rv.validate(_one(rw(3, True, aff(tx=1))))[0] == -1
+    # aux divisor < 1
+    assert rv.validate(_one(rw(0, True, aff(aux0=1), aux=(Aux(AUX_FLOORDIV, 0, aff(tx=1)), Aux()))))[0] == -1
+    # aux numerator uses an aux variable
+    assert rv.validate(_one(rw(0, True, aff(aux0=1), aux=(Aux(AUX_EMOD, 4, aff(aux1=1)), Aux()))))[0] == -1
+    # loop lo > hi
+    assert rv.validate(_one(rw(0, True, aff(tx=1), loops=((3, 1),))))[0] == -1
+    # value range: coefficient * tid may leave int32
+    st, msg = rv.validate(_one(rw(0, True, aff(tx=1 << 29)), block=(8, 1)))
+    assert st == -4, msg
+    # location space beyond 31 bits
+    st, _ = rv.validate(_one(rw(0, True, aff(tx=1)), arrays=((GLOBAL, (1 << 30,)), (GLOBAL, (1 << 30,))),
+                              block=(8, 1)).replace(
+        accesses=[rw(0, True, aff(tx=1)), rw(1, True, aff(tx=1))],
+        phases=[__import__("workloads").Phase(0, 2, False)]))
+    assert st == -3
+    # too many instances in one interval
+    big = _one(rw(0, False, aff(0), loops=((0, 1 << 16), (0, 1 << 10))), block=(32, 32), grid=(4, 1))
+    assert rv.validate(big)[0] == -6
+    # empty description is valid (no records)
+    empty = Builder((1, 1), (1, 1)).build()
+    assert rv.validate(empty)[0] == 0
+
+
+def test_validate_z_dimension_unsupported():
+    m = rv.Marshalled(K.tiny_fixed())
+    m.desc.launch.block[2] = 2
+    buf = ctypes.create_string_buffer(256)
+    assert rv.lib().rv_validate_desc(ctypes.byref(m.desc), buf, 256) == -2
+    m.desc.launch.block[2] = 0
+    assert rv.lib().rv_validate_desc(ctypes.byref(m.desc), buf, 256) == -1
+
+
+def test_context_needs_gpu_or_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        rv.Context(0, 64 << 20)

@@ -1,0 +1,257 @@
+"""GPU parity: the HIP checker against the CPU oracle, bit-exact.
+
+Every test runs librv through its C ABI (the ctypes binding) on cuda:0 and
+compares counts, records and canonical witnesses with ``oracle`` on the same
+seeded descriptions."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import kernels as K
+from workloads import random_affine as RA
+from workloads.desc import AUX_EMOD, AUX_FLOORDIV, GLOBAL, SHARED, Aux, Builder, aff, rw
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2503_08946_amd as rv
+    c = rv.Context(0, workspace_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def _wkey(w):
+    return (w.interval, w.space, w.block, w.array, w.address,
+            (w.first.block, w.first.tid, w.first.dphase, w.first.access, tuple(w.first.loop), w.first.is_write),
+            (w.second.block, w.second.tid, w.second.dphase, w.second.access, tuple(w.second.loop),
+             w.second.is_write))
+
+
+def compare(ctx, desc, max_list=1 << 16, list_all=True):
+    say(f"[parity] {desc.name} instances={desc.instances_upper_bound()}")
+    o = oracle.check(desc, max_witnesses=max_list)
+    assert o.status == 0
+    k = ctx.load(desc)
+    g = ctx.check(k)
+    assert g.n_records == o.n_records
+    assert g.n_conflicts == o.n_conflicts
+    if o.n_conflicts:
+        assert g.witness is not None
+        assert _wkey(g.witness) == _wkey(o.witnesses[0])
+    else:
+        assert g.witness is None
+    if list_all and o.n_conflicts:
+        n = min(o.n_conflicts, max_list)
+        ws = ctx.witnesses(k, 0, n)
+        assert [_wkey(w) for w in ws] == [_wkey(w) for w in o.witnesses[:n]]
+    return k, g, o
+
+
+# ----------------------------------------------------------------- pins
+@pytest.mark.parametrize("name", ["tiny_fixed", "polynomial_product", "stride1_shared", "stride1_global",
+                                  "half_index_shared", "half_index_global", "gespmm_crc"])
+def test_pin_kernels(ctx, name):
+    compare(ctx, getattr(K, name)())
+
+
+@pytest.mark.parametrize("mid,trail", [(True, True), (False, True), (True, False), (False, False)])
+def test_gespmm_variants(ctx, mid, trail):
+    compare(ctx, K.gespmm_crc(M=8, N=96, T=4, K=3, middle_barrier=mid, trailing_barrier=trail))
+
+
+def test_tiny_random(ctx):
+    for d in K.tiny_random(seed=1, count=32):
+        compare(ctx, d)
+
+
+@pytest.mark.parametrize("k", [-1] + list(range(10)))
+def test_tree_reduction_full_size(ctx, k):
+    _, g, o = compare(ctx, K.tree_reduction(k))
+    assert g.n_records == 392832
+    assert g.n_conflicts == (128 * (256 >> k) if 0 <= k <= 8 else 0)
+
+
+@pytest.mark.parametrize("d", [-1, 0, 1, 6, 7])
+def test_matmul_small(ctx, d):
+    compare(ctx, K.tiled_matmul(grid=2, k_iters=4, drop_dynamic=d))
+
+
+@pytest.mark.parametrize("s", ["load", "compute"])
+def test_matmul_static(ctx, s):
+    compare(ctx, K.tiled_matmul(grid=3, k_iters=3, drop_static=s))
+
+
+# ------------------------------------------------------ expansion / sort
+@pytest.mark.parametrize("desc", [K.tiny_fixed(), K.tree_reduction(2, block=256, grid=6),
+                                  K.tiled_matmul(grid=2, k_iters=2, drop_dynamic=1),
+                                  K.gespmm_crc(), K.polynomial_product(48)], ids=lambda d: d.name)
+def test_expansion_record_multiset(ctx, desc):
+    k = ctx.load(desc)
+    for iv in range(oracle.n_intervals(desc)):
+        say(f"[expand] {desc.name} interval {iv}")
+        ref = oracle.records(desc, iv)
+        got = ctx.debug_records(k, iv, sorted=False)
+        # (interval, space, block, array, address, gthread, dphase, access, lidx, loops, rw)
+        a = ref[np.lexsort(ref.T[::-1])]
+        b = got[np.lexsort(got.T[::-1])]
+        assert a.shape == b.shape
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("desc", [K.tiny_fixed(), K.tree_reduction(4, block=512, grid=3),
+                                  K.tiled_matmul(grid=2, k_iters=2), K.half_index_global(block=256, grid=8)],
+                         ids=lambda d: d.name)
+def test_sort_output_is_sorted_permutation(ctx, desc):
+    k = ctx.load(desc)
+    for iv in range(oracle.n_intervals(desc)):
+        say(f"[sort] {desc.name} interval {iv}")
+        got = ctx.debug_records(k, iv, sorted=True)
+        ref = oracle.records(desc, iv)
+        loc = got[:, 1:5]
+        # location order: (space, block, array, address) non-decreasing
+        lk = [tuple(r) for r in loc]
+        assert lk == sorted(lk)
+        a = ref[np.lexsort(ref.T[::-1])]
+        b = got[np.lexsort(got.T[::-1])]
+        assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------- edge cases
+def test_empty_kernel(ctx):
+    b = Builder((4, 1), (1, 1), "empty")
+    b.array(SHARED, (4,))
+    k = ctx.load(b.build())
+    r = ctx.check(k)
+    assert (r.n_records, r.n_conflicts, r.witness) == (0, 0, None)
+
+
+def test_zero_trip_loops_and_false_guards(ctx):
+    b = Builder((16, 2), (2, 1), "degenerate")
+    s = b.array(SHARED, (40,))
+    p = b.phase([rw(s, True, aff(tx=1), loops=((3, 3),)),                 # empty loop
+                 rw(s, True, aff(0), guards=(aff(-1),)),                  # guard never holds
+                 rw(s, False, aff(tx=1, l0=1), loops=((0, 2),))], False)
+    b.segment([p])
+    compare(ctx, b.build())
+
+
+def test_single_thread(ctx):
+    b = Builder((1, 1), (1, 1), "one-thread")
+    g = b.array(GLOBAL, (8,))
+    p = b.phase([rw(g, True, aff(l0=1), loops=((0, 8),)), rw(g, False, aff(l0=1), loops=((0, 8),))], False)
+    b.segment([p])
+    k, r, _ = compare(ctx, b.build())
+    assert r.n_conflicts == 0
+
+
+def test_out_of_bounds_reports_smallest_instance(ctx):
+    import paper_2503_08946_amd as rv
+    b = Builder((8, 1), (2, 1), "oob")
+    s = b.array(SHARED, (8,))
+    p0 = b.phase([rw(s, True, aff(tx=1))], True)
+    p1 = b.phase([rw(s, False, aff(0, tx=1)), rw(s, False, aff(5, tx=1))], False)
+    b.segment([p0, p1])
+    desc = b.build()
+    o = oracle.check(desc)
+    assert o.status == -5
+    k = ctx.load(desc)
+    with pytest.raises(rv.RVError) as e:
+        ctx.check(k)
+    assert e.value.status == -5
+    # oracle: (interval 1, gthread 3, dyn phase 1, access 2, loop index 0)
+    assert "interval 1, block 0, thread 3, dynamic phase 1, access 2" in e.value.message
+
+
+def test_hot_location_exceeds_one_slice(ctx):
+    # every thread of 64 blocks x 256 reads g[0] 4 times and thread 7 of block 3 writes it:
+    # one location with 65537 records, far above one on-chip slice
+    b = Builder((256, 1), (64, 1), "hot-location")
+    g = b.array(GLOBAL, (4,))
+    who = 3 * 256 + 7
+    # the guard pair pins tx + 256*bx == who (>= and <=)
+    p = b.phase([rw(g, False, aff(0), loops=((0, 4),)),
+                 rw(g, True, aff(0), guards=(aff(-who, tx=1, bx=256), aff(who, tx=-1, bx=-256)))], False)
+    b.segment([p])
+    k, r, o = compare(ctx, b.build())
+    assert r.n_records == 64 * 256 * 4 + 1 and r.n_conflicts == 1
+
+
+def test_key_range_passes(ctx):
+    # a 3M-element global array touched sparsely: the interval's location space
+    # needs more than one key-range pass
+    b = Builder((64, 1), (32, 1), "wide-global")
+    g = b.array(GLOBAL, (3 << 20,))
+    p = b.phase([rw(g, True, aff(tx=1, bx=98304)),
+                 rw(g, False, aff(7, tx=1, bx=98304)),
+                 rw(g, True, aff(3 << 19, tx=2)),
+                 rw(g, False, aff(3 << 19, tx=1))], False)
+    b.segment([p])
+    desc = b.build()
+    k = ctx.load(desc)
+    assert k.info().n_subintervals >= 2
+    compare(ctx, desc)
+
+
+def test_many_chunks_small_workspace():
+    import paper_2503_08946_amd as rv
+    c = rv.Context(0, workspace_bytes=64 << 20)
+    desc = K.tiled_matmul(grid=4, k_iters=8, drop_dynamic=5)
+    k = c.load(desc)
+    assert k.info().n_chunks > 1
+    compare(c, desc)
+    c.close()
+
+
+# -------------------------------------------------------------- batches
+def test_batch_equals_single(ctx):
+    descs = [K.tiny_fixed(), K.tree_reduction(3, block=256, grid=4), K.gespmm_crc(middle_barrier=False),
+             K.tiled_matmul(grid=2, k_iters=2, drop_dynamic=2)] + K.tiny_random(seed=9, count=12)
+    descs += RA.batch_kernels(seed=4, count=24)
+    ks = [ctx.load(d) for d in descs]
+    single = [ctx.check(k) for k in ks]
+    batch = ctx.check_batch(ks)
+    for d, s, bt in zip(descs, single, batch):
+        say(f"[batch] {d.name}")
+        assert (s.n_records, s.n_conflicts) == (bt.n_records, bt.n_conflicts)
+        assert (s.witness is None) == (bt.witness is None)
+        if s.witness:
+            assert _wkey(s.witness) == _wkey(bt.witness)
+    for d in descs[:20]:
+        o = oracle.check(d, max_witnesses=1)
+        s = single[descs.index(d)]
+        assert (s.n_records, s.n_conflicts) == (o.n_records, o.n_conflicts)
+
+
+def test_batched_workload_sample(ctx):
+    # the batched workload's first kernels (seed 4), all of them checked against the oracle
+    descs = RA.batch_kernels(seed=4, count=48)
+    ks = [ctx.load(d) for d in descs]
+    res = ctx.check_batch(ks)
+    for d, r in zip(descs, res):
+        say(f"[batch-c4] {d.name} {r.n_records}")
+        o = oracle.check(d, max_witnesses=1)
+        assert (r.n_records, r.n_conflicts) == (o.n_records, o.n_conflicts)
+        if o.n_conflicts:
+            assert _wkey(r.witness) == _wkey(o.witnesses[0])
+
+
+def test_witness_windows(ctx):
+    desc = K.tree_reduction(1)
+    k = ctx.load(desc)
+    o = oracle.check(desc, max_witnesses=1 << 15)
+    full = ctx.witnesses(k, 0, 1 << 15)
+    assert len(full) == o.n_conflicts == 16384
+    mid = ctx.witnesses(k, 1000, 77)
+    assert [_wkey(w) for w in mid] == [_wkey(w) for w in full[1000:1077]]
+    tail = ctx.witnesses(k, 16380, 100)
+    assert len(tail) == 4
