@@ -13,6 +13,7 @@ using namespace rv;
 
 struct rv_ctx {
     int device = 0;
+    unsigned ncu = 256;             // compute units of the device (persistent grids)
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -132,15 +133,15 @@ rv_status check_launch(rv_ctx *c) {
 // count -> scan -> expansion for one chunk
 void run_expand(rv_ctx *c, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
     timed(c, RV_STAGE_FILL, [&] { launch_fill_u32(c->counts(), buckets, 0u, c->stream); });
-    timed(c, RV_STAGE_COUNT, [&] { launch_hist(subs, nsub, items, c->counts(), c->d_res, c->stream); });
+    timed(c, RV_STAGE_COUNT, [&] { launch_hist(subs, nsub, items, c->counts(), c->d_res, c->ncu, c->stream); });
     timed(c, RV_STAGE_SCAN, [&] { launch_scan(c->counts(), c->starts(), c->cursor(), c->bsum(), buckets, c->stream); });
-    timed(c, RV_STAGE_EXPAND, [&] { launch_scatter(subs, nsub, items, c->rec(), c->cursor(), c->stream); });
+    timed(c, RV_STAGE_EXPAND, [&] { launch_scatter(subs, nsub, items, c->rec(), c->cursor(), c->ncu, c->stream); });
 }
 
 void run_check_chunk(rv_ctx *c, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
     run_expand(c, subs, nsub, items, buckets);
     timed(c, RV_STAGE_SORT_SCAN, [&] {
-        launch_bucket(subs, nsub, buckets, c->rec(), c->starts(), c->counts(), c->conf(), 0, c->stream);
+        launch_bucket(subs, nsub, buckets, c->rec(), c->starts(), c->counts(), c->conf(), 0, c->ncu, c->stream);
     });
     timed(c, RV_STAGE_FINISH, [&] {
         launch_finish(subs, nsub, buckets, c->conf(), c->d_res, c->stream);
@@ -223,6 +224,9 @@ rv_status rv_ctx_create(rv_ctx **out, int device, void *hip_stream, void *worksp
     c->L = layout_workspace(workspace_bytes);
     if (!c->L.cap_records) { delete c; return RV_ERR_TOO_LARGE; }
     if (hipSetDevice(device) != hipSuccess) { delete c; return RV_ERR_DEVICE; }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        c->ncu = (unsigned)ncu;
     *out = c;
     return RV_OK;
 }
@@ -423,7 +427,7 @@ rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_wit
         const DevSub *subs = k->d_subs + ch.sub_begin;
         const uint32_t nsub = ch.sub_end - ch.sub_begin;
         run_expand(c, subs, nsub, ch.items, ch.buckets);
-        launch_bucket(subs, nsub, ch.buckets, c->rec(), c->starts(), c->counts(), c->conf(), 0, c->stream);
+        launch_bucket(subs, nsub, ch.buckets, c->rec(), c->starts(), c->counts(), c->conf(), 0, c->ncu, c->stream);
         launch_finish(subs, nsub, ch.buckets, c->conf(), c->d_res, c->stream);
         // exclusive scan of per-bucket conflict counts -> list positions (cursor area)
         launch_scan(c->conf(), c->cursor(), nullptr, c->bsum(), ch.buckets, c->stream);
@@ -502,7 +506,7 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
         if (sorted && x > (uint32_t)CAP) return fail(c, RV_ERR_UNSUPPORTED, "a bucket exceeds one on-chip slice");
     }
     if (sorted) {
-        launch_bucket(c->d_bsubs, se - sb, buckets, c->rec(), c->starts(), c->counts(), c->conf(), 1, c->stream);
+        launch_bucket(c->d_bsubs, se - sb, buckets, c->rec(), c->starts(), c->counts(), c->conf(), 1, c->ncu, c->stream);
         if ((st = check_launch(c))) return st;
     }
     std::vector<unsigned long long> recs(total);

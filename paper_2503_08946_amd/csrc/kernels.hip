@@ -1,28 +1,54 @@
 // gfx950 kernels of the per-barrier-interval race check.
 //
-// Pipeline for one chunk of key-range passes (see plan.cpp):
-//   k_hist     count: evaluate every instance (guards, bounds, location),
-//              histogram the records per location bucket        [ALU, no record traffic]
+// Pipeline for one chunk of passes (see plan.cpp):
+//   k_hist     count: evaluate every instance (guards, bounds, location) and
+//              histogram the records per location bucket           [ALU, no record traffic]
 //   k_scan_*   exclusive scan of the bucket counts -> bucket starts
-//   k_scatter  expansion: evaluate the instances again, build the records
-//              (location << 1 | rw, instance id) and write them grouped by
-//              bucket through an LDS-staged counting sort (the most
-//              significant radix digit of the location key)       [writes 8 B / record]
+//   k_scatter  expansion: evaluate the instances again, build the 8-byte
+//              records (location << 1 | rw, instance id) and write them
+//              grouped by bucket through an LDS-staged counting sort (the
+//              most significant radix digit of the location key)   [writes 8 B / record]
 //   k_bucket   per bucket: load the records on chip, LDS radix sort on the
 //              bucket's low key bits, segmented scan (ballot heads, DPP
 //              reductions) giving per location (min id, max id, min write
-//              id, max write id); flag conflicting locations, count them and
-//              write canonical witnesses in location order           [reads 8 B / record]
+//              id, max write id + 1); flag conflicting locations, count them
+//              and write canonical witnesses in location order     [reads 8 B / record]
 //   k_finish / k_first   per-pass conflict totals and first witness.
 //
 // A location conflicts iff it has a write and two different threads touch
-// it in the interval; with instance ids ordered thread-major that is
-// (max write id + 1 != 0) && thread(min id) != thread(max id)  (the RaW / WaW /
-// WaR relations of Section 2.1 restricted to one unordered barrier interval).
+// it in the interval.  Instance ids are ordered thread-major, so that is
+// (max write id + 1 != 0) && thread(min id) != thread(max id): the RaW / WaW /
+// WaR relations of Section 2.1 restricted to one unordered barrier interval.
+//
+// Plan tables are read through the constant address space: they are
+// read-only during a launch, so the compiler keeps them in scalar registers
+// (s_load) even across the atomics of the loops.  Count and scatter run as
+// persistent grids whose workgroups own contiguous runs of work items;
+// adjacent runs go to the same XCD (workgroups are dealt round-robin over the
+// 8 XCDs), so the bucket counters and partially written lines they share stay
+// in one L2.
 
 #include "rv_internal.h"
 
 namespace rv {
+
+#define RV_CONST __attribute__((address_space(4)))
+using CSub = const RV_CONST DevSub;
+using CEnt = const RV_CONST DevEntry;
+using CKer = const RV_CONST DevKernel;
+using CI32 = const RV_CONST int32_t;
+using CU32 = const RV_CONST uint32_t;
+
+template <class T>
+__device__ __forceinline__ const RV_CONST T *cptr(const T *p) {
+    return (const RV_CONST T *)p;
+}
+
+__device__ __forceinline__ Magic ldm(const RV_CONST Magic &x) {
+    Magic g;
+    g.m = x.m; g.s1 = x.s1; g.s2 = x.s2; g.d = x.d;
+    return g;
+}
 
 // ---------------------------------------------------------------- wave utils
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
@@ -44,8 +70,8 @@ __device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
 constexpr int ROW_SHR1 = 0x111, ROW_SHR2 = 0x112, ROW_SHR4 = 0x114, ROW_SHR8 = 0x118;
 constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
 
-// Inclusive wave64 prefix sum: Hillis-Steele inside each row of 16 lanes,
-// then row 0 -> 1, row 2 -> 3 (bcast15) and lane 31 -> rows 2, 3 (bcast31).
+// Inclusive wave64 scans: Hillis-Steele inside each row of 16 lanes, then
+// row 0 -> 1 and row 2 -> 3 (bcast15), lane 31 -> rows 2 and 3 (bcast31).
 __device__ __forceinline__ uint32_t wave_incl_add(uint32_t v) {
     v += dpp<ROW_SHR1, 0xf>(0u, v);
     v += dpp<ROW_SHR2, 0xf>(0u, v);
@@ -56,8 +82,28 @@ __device__ __forceinline__ uint32_t wave_incl_add(uint32_t v) {
     return v;
 }
 
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = min(v, dpp<ROW_SHR1, 0xf>(0xFFFFFFFFu, v));
+    v = min(v, dpp<ROW_SHR2, 0xf>(0xFFFFFFFFu, v));
+    v = min(v, dpp<ROW_SHR4, 0xf>(0xFFFFFFFFu, v));
+    v = min(v, dpp<ROW_SHR8, 0xf>(0xFFFFFFFFu, v));
+    v = min(v, dpp<ROW_BCAST15, 0xa>(0xFFFFFFFFu, v));
+    v = min(v, dpp<ROW_BCAST31, 0xc>(0xFFFFFFFFu, v));
+    return readlane(v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+    v = max(v, dpp<ROW_SHR1, 0xf>(0u, v));
+    v = max(v, dpp<ROW_SHR2, 0xf>(0u, v));
+    v = max(v, dpp<ROW_SHR4, 0xf>(0u, v));
+    v = max(v, dpp<ROW_SHR8, 0xf>(0u, v));
+    v = max(v, dpp<ROW_BCAST15, 0xa>(0u, v));
+    v = max(v, dpp<ROW_BCAST31, 0xc>(0u, v));
+    return readlane(v, 63);
+}
+
 // Exclusive prefix sum over a workgroup of NT threads; returns the prefix and
-// writes the total to *total (all threads).  `red` holds NT/64 + 1 words.
+// writes the total to *total (all threads).  `red` holds NT/64 words.
 template <int NT>
 __device__ __forceinline__ uint32_t block_excl_add(uint32_t v, uint32_t *red, uint32_t *total) {
     const uint32_t wid = threadIdx.x >> 6;
@@ -76,8 +122,27 @@ __device__ __forceinline__ uint32_t block_excl_add(uint32_t v, uint32_t *red, ui
     return before + inc - v;
 }
 
-// Rank of a record inside its bucket counter h[b] (unique per valid lane).
-// All-equal waves (the common case for structured kernels) take one atomic.
+// Workgroup min, max and sum (all threads get the results).  `red` holds
+// 3 * NT/64 words.
+template <int NT>
+__device__ __forceinline__ void block_min_max_sum(uint32_t &mn, uint32_t &mx, uint32_t &sum, uint32_t *red) {
+    const uint32_t wid = threadIdx.x >> 6;
+    const uint32_t a = wave_min(mn), b = wave_max(mx), c = readlane(wave_incl_add(sum), 63);
+    if (lane() == 0) { red[wid] = a; red[NT / 64 + wid] = b; red[2 * (NT / 64) + wid] = c; }
+    __syncthreads();
+    mn = 0xFFFFFFFFu; mx = 0; sum = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) {
+        mn = min(mn, red[w]);
+        mx = max(mx, red[NT / 64 + w]);
+        sum += red[2 * (NT / 64) + w];
+    }
+    __syncthreads();
+}
+
+// Rank of a record inside its bin counter h[b] (unique per valid lane).
+// Waves whose records share one bin (the common case for structured
+// kernels) take one atomic.
 __device__ __forceinline__ uint32_t lds_rank(uint32_t *h, uint32_t b, bool v) {
     const uint64_t act = __ballot(v);
     if (act == 0) return 0;
@@ -93,47 +158,81 @@ __device__ __forceinline__ uint32_t lds_rank(uint32_t *h, uint32_t b, bool v) {
     return v ? atomicAdd(&h[b], 1u) : 0u;
 }
 
+// Rank by wave-level multi-split: `nbits` ballots find the lanes holding the
+// same key; one atomic per distinct key in the wave, ranks in lane order.
+__device__ __forceinline__ uint32_t wlms_rank(uint32_t *h, uint32_t k, bool v, uint32_t nbits) {
+    const uint64_t act = __ballot(v);
+    if (act == 0) return 0;
+    const uint32_t lead = (uint32_t)__builtin_ctzll(act);
+    const uint32_t lk = readlane(k, lead);
+    const uint64_t same = __ballot(v && k == lk);
+    if (same == act) {
+        uint32_t base = 0;
+        if (lane() == lead) base = atomicAdd(&h[lk], (uint32_t)__popcll(act));
+        base = readlane(base, lead);
+        return base + mbcnt(act);
+    }
+    uint64_t peers = act;
+    for (uint32_t bit = 0; bit < nbits; bit++) {
+        const bool x = (k >> bit) & 1u;
+        const uint64_t bb = __ballot(x);
+        peers &= x ? bb : ~bb;
+    }
+    if (!v || peers == 0) peers = 1ull << lane();
+    const uint32_t rank = mbcnt(peers);
+    const uint32_t leader = (uint32_t)__builtin_ctzll(peers);
+    uint32_t base = 0;
+    if (v && rank == 0) base = atomicAdd(&h[k], (uint32_t)__popcll(peers));
+    base = (uint32_t)__shfl((int)base, (int)leader);
+    return base + rank;
+}
+
 // ------------------------------------------------------------ work items
-__device__ __forceinline__ uint32_t sub_by_item(const DevSub *subs, uint32_t n, uint32_t w) {
-    uint32_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (subs[mid].item_begin <= w) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ uint32_t sub_by_bucket(const DevSub *subs, uint32_t n, uint32_t b) {
-    uint32_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (subs[mid].bucket_begin <= b) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-struct Item {
-    const DevSub *S;
-    const DevEntry *E;
-    uint32_t gtile, lchunk;
+// A cursor over the work items of a chunk: pass, entry of the pass's
+// interval, item inside the entry.
+struct Cursor {
+    uint32_t sub, e, li, e_items;
 };
 
-__device__ __forceinline__ Item resolve_item(const DevSub *subs, uint32_t nsub, uint32_t w) {
-    Item it;
-    it.S = subs + sub_by_item(subs, nsub, w);
-    const uint32_t local = w - it.S->item_begin;
-    const uint32_t *pre = it.S->entry_items;
-    uint32_t lo = 0, hi = it.S->n_entries;
+__device__ __forceinline__ void seek(CSub *subs, uint32_t nsub, uint32_t w, Cursor &c) {
+    uint32_t lo = 0, hi = nsub;
     while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (pre[mid] <= local) lo = mid; else hi = mid;
+        const uint32_t mid = (lo + hi) >> 1;
+        if (subs[mid].item_begin <= w) lo = mid; else hi = mid;
     }
-    it.E = it.S->entries + lo;
-    const uint32_t li = local - pre[lo];
-    const uint32_t nl = it.E->n_lchunks;
-    it.gtile = li / nl;
-    it.lchunk = li - it.gtile * nl;
-    return it;
+    c.sub = lo;
+    const uint32_t local = w - subs[lo].item_begin;
+    CU32 *pre = cptr(subs[lo].entry_items);
+    uint32_t elo = 0, ehi = subs[lo].n_entries;
+    while (ehi - elo > 1) {
+        const uint32_t mid = (elo + ehi) >> 1;
+        if (pre[mid] <= local) elo = mid; else ehi = mid;
+    }
+    c.e = elo;
+    c.li = local - pre[elo];
+    c.e_items = pre[elo + 1] - pre[elo];
+}
+
+// Next item; only called while one exists.
+__device__ __forceinline__ void advance(CSub *subs, Cursor &c) {
+    c.li++;
+    while (c.li >= c.e_items) {
+        c.li = 0;
+        c.e++;
+        if (c.e >= subs[c.sub].n_entries) { c.sub++; c.e = 0; }
+        CU32 *pre = cptr(subs[c.sub].entry_items);
+        c.e_items = pre[c.e + 1] - pre[c.e];
+    }
+}
+
+// The contiguous run of items of this workgroup; runs of workgroups that
+// share an XCD are adjacent.
+__device__ __forceinline__ void my_items(uint32_t n, uint32_t &w0, uint32_t &w1) {
+    const uint32_t G = gridDim.x;                  // multiple of 8
+    const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
+    const uint32_t per = (n + G - 1) / G;
+    w0 = min(n, r * per);
+    w1 = min(n, w0 + per);
 }
 
 // Evaluate the RPL instance slots of this lane in one work item and call
@@ -141,13 +240,10 @@ __device__ __forceinline__ Item resolve_item(const DevSub *subs, uint32_t nsub, 
 // `lch` consecutive loop points of `gt` threads per lane; the loop counters
 // are wave-uniform, the thread decode is per lane and per thread.
 template <class F>
-__device__ __forceinline__ void expand_item(const Item &it, F &&f) {
-    const DevSub &S = *it.S;
-    const DevEntry &E = *it.E;
-    const DevKernel &K = *S.kc;
-    const int32_t *__restrict__ G = S.guards;
+__device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t gtile, uint32_t lchunk,
+                                            F &&f) {
     const uint32_t lch = E.lch, gt = E.gt;
-    const uint32_t lstart = it.lchunk * lch;
+    const uint32_t lstart = lchunk * lch;
     const uint32_t lcnt = min(lch, E.box - lstart);
     const uint32_t e1 = E.ext[1], e2 = E.ext[2];
     uint32_t c0s, c1s, c2s;
@@ -163,25 +259,28 @@ __device__ __forceinline__ void expand_item(const Item &it, F &&f) {
     int32_t base[5] = {0, 0, 0, 0, 0};
     uint32_t idbase = 0, locbase = 0;
     bool gval = false;
+    const bool aux0 = E.aux_kind[0] != 0, aux1 = E.aux_kind[1] != 0;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const bool active = gi < gt;
         if (active && li == 0) {
-            const uint32_t g = (it.gtile * gt + gi) * EXP_WG + threadIdx.x;
+            const uint32_t g = (gtile * gt + gi) * EXP_WG + threadIdx.x;
             gval = g < K.nthreads;
             const uint32_t gg = gval ? g : 0u;
-            const uint32_t blk = udiv(gg, K.mg_tpb);
+            const uint32_t blk = udiv(gg, ldm(K.mg_tpb));
             const uint32_t tid = gg - blk * K.tpb;
-            const uint32_t byy = udiv(blk, K.mg_gdx);
-            const uint32_t tyy = udiv(tid, K.mg_bdx);
+            const uint32_t byy = udiv(blk, ldm(K.mg_gdx));
+            const uint32_t tyy = udiv(tid, ldm(K.mg_bdx));
             tx = (int32_t)(tid - tyy * K.bdx);
             ty = (int32_t)tyy;
             bx = (int32_t)(blk - byy * K.gdx);
             by = (int32_t)byy;
 #pragma unroll
-            for (int r = 0; r < 5; r++)
+            for (int r = 0; r < 5; r++) {
+                if (r >= 3 && !(r == 3 ? aux0 : aux1)) continue;
                 base[r] = E.row[r][C_TX] * tx + E.row[r][C_TY] * ty + E.row[r][C_BX] * bx +
                           E.row[r][C_BY] * by + E.row[r][C_C0];
+            }
             idbase = gg * S.M + E.off + lstart;
             locbase = blk * E.loc_mul + E.loc_base;
         }
@@ -189,28 +288,28 @@ __device__ __forceinline__ void expand_item(const Item &it, F &&f) {
         uint32_t loc = 0, id = 0;
         if (active) {
             const int32_t L0 = E.lo[0] + (int32_t)c0, L1 = E.lo[1] + (int32_t)c1, L2 = E.lo[2] + (int32_t)c2;
-            int32_t a[2] = {0, 0};
-#pragma unroll
-            for (int x = 0; x < 2; x++) {
-                if (E.aux_kind[x]) {
-                    const int32_t n = base[3 + x] + E.row[3 + x][C_L0] * L0 + E.row[3 + x][C_L1] * L1 +
-                                      E.row[3 + x][C_L2] * L2;
-                    a[x] = E.aux_kind[x] == RV_AUX_FLOORDIV ? fdiv(n, E.aux_mg[x]) : emod(n, E.aux_mg[x]);
-                }
+            int32_t a0 = 0, a1 = 0;
+            if (aux0) {
+                const int32_t n = base[3] + E.row[3][C_L0] * L0 + E.row[3][C_L1] * L1 + E.row[3][C_L2] * L2;
+                a0 = E.aux_kind[0] == RV_AUX_FLOORDIV ? fdiv(n, ldm(E.aux_mg[0])) : emod(n, ldm(E.aux_mg[0]));
+            }
+            if (aux1) {
+                const int32_t n = base[4] + E.row[4][C_L0] * L0 + E.row[4][C_L1] * L1 + E.row[4][C_L2] * L2;
+                a1 = E.aux_kind[1] == RV_AUX_FLOORDIV ? fdiv(n, ldm(E.aux_mg[1])) : emod(n, ldm(E.aux_mg[1]));
             }
             ok = gval && li < lcnt;
             for (uint32_t q = 0; q < E.guard_count; q++) {
-                const int32_t *gr = G + (size_t)(E.guard_begin + q) * NC;
+                CI32 *gr = G + (size_t)(E.guard_begin + q) * NC;
                 const int32_t gv = gr[C_TX] * tx + gr[C_TY] * ty + gr[C_BX] * bx + gr[C_BY] * by +
-                                   gr[C_L0] * L0 + gr[C_L1] * L1 + gr[C_L2] * L2 + gr[C_A0] * a[0] +
-                                   gr[C_A1] * a[1] + gr[C_C0];
+                                   gr[C_L0] * L0 + gr[C_L1] * L1 + gr[C_L2] * L2 + gr[C_A0] * a0 +
+                                   gr[C_A1] * a1 + gr[C_C0];
                 ok = ok && gv >= 0;
             }
             int32_t ix[3];
 #pragma unroll
             for (int r = 0; r < 3; r++)
                 ix[r] = base[r] + E.row[r][C_L0] * L0 + E.row[r][C_L1] * L1 + E.row[r][C_L2] * L2 +
-                        E.row[r][C_A0] * a[0] + E.row[r][C_A1] * a[1];
+                        E.row[r][C_A0] * a0 + E.row[r][C_A1] * a1;
             inb = (uint32_t)ix[0] < E.dim[0] && (uint32_t)ix[1] < E.dim[1] && (uint32_t)ix[2] < E.dim[2];
             const uint32_t flat = ((uint32_t)ix[0] * E.dim[1] + (uint32_t)ix[1]) * E.dim[2] + (uint32_t)ix[2];
             loc = locbase + flat;
@@ -247,31 +346,67 @@ __global__ void k_init_results(SubResult *r, size_t n) {
 }
 
 // --------------------------------------------------------------- count pass
-__global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *__restrict__ subs, uint32_t nsub,
+__global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t nsub, uint32_t nitems,
                                                   uint32_t *__restrict__ counts, SubResult *__restrict__ res) {
-    __shared__ uint32_t h[NBMAX];
-    __shared__ uint32_t red[EXP_WG / 64 + 1];
-    const Item it = resolve_item(subs, nsub, blockIdx.x);
-    const DevSub &S = *it.S;
-    for (uint32_t i = threadIdx.x; i < S.nb; i += EXP_WG) h[i] = 0;
-    __syncthreads();
-    const uint32_t span = S.khi - S.klo;
-    uint32_t mine = 0;
-    expand_item(it, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {
-        if (ok && !inb) atomicMin(&res[S.res].oob, ((unsigned long long)S.interval << 32) | id);
-        const uint32_t rel = loc - S.klo;
-        const bool v = ok && inb && rel < span;
-        lds_rank(h, rel >> S.s, v);
-        mine += v ? 1u : 0u;
-    });
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < S.nb; i += EXP_WG) {
-        const uint32_t c = h[i];
-        if (c) atomicAdd(&counts[S.bucket_begin + i], c);
+    __shared__ uint32_t h[BINCAP];
+    __shared__ uint32_t red[3 * (EXP_WG / 64)];
+    CSub *subs = cptr(subs_g);
+    uint32_t w0, w1;
+    my_items(nitems, w0, w1);
+    if (w0 >= w1) return;
+    Cursor cur;
+    seek(subs, nsub, w0, cur);
+    for (uint32_t w = w0; w < w1; w++) {
+        CSub &S = subs[cur.sub];
+        CEnt &E = cptr(S.entries)[cur.e];
+        CKer &K = *cptr(S.kc);
+        const uint32_t nl = E.n_lchunks;
+        const uint32_t gtile = cur.li / nl, lchunk = cur.li - gtile * nl;
+        const uint32_t span = S.khi - S.klo;
+        uint32_t bk[RPL];
+        uint32_t mn = 0xFFFFFFFFu, mx = 0, n = 0;
+        expand_item(S, E, K, cptr(S.guards), gtile, lchunk, [&](int s, bool ok, bool inb, uint32_t loc, uint32_t id) {
+            if (ok && !inb) atomicMin(&res[S.res].oob, ((unsigned long long)S.interval << 32) | id);
+            const uint32_t rel = loc - S.klo;
+            const bool v = ok && inb && rel < span;
+            const uint32_t b = rel >> S.s;
+            bk[s] = v ? b : 0xFFFFFFFFu;
+            if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
+        });
+        block_min_max_sum<EXP_WG>(mn, mx, n, red);
+        if (n) {
+            if (threadIdx.x == 0) atomicAdd(&res[S.res].records, (unsigned long long)n);
+            uint32_t *gc = counts + S.bucket_begin;
+            if (mx - mn < (uint32_t)BINCAP) {
+                const uint32_t R = mx - mn + 1;
+                for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
+                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < RPL; s++) lds_rank(h, bk[s] - mn, bk[s] != 0xFFFFFFFFu);
+                __syncthreads();
+                for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) {
+                    const uint32_t c = h[i];
+                    if (c) atomicAdd(&gc[mn + i], c);
+                }
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int s = 0; s < RPL; s++) {
+                    const bool v = bk[s] != 0xFFFFFFFFu;
+                    const uint64_t act = __ballot(v);
+                    if (!act) continue;
+                    const uint32_t lead = (uint32_t)__builtin_ctzll(act);
+                    const uint32_t lb = readlane(bk[s], lead);
+                    if (__ballot(v && bk[s] == lb) == act) {
+                        if (lane() == lead) atomicAdd(&gc[lb], (uint32_t)__popcll(act));
+                    } else if (v) {
+                        atomicAdd(&gc[bk[s]], 1u);
+                    }
+                }
+            }
+        }
+        if (w + 1 < w1) advance(subs, cur);
     }
-    uint32_t tot;
-    block_excl_add<EXP_WG>(mine, red, &tot);
-    if (threadIdx.x == 0 && tot) atomicAdd(&res[S.res].records, (unsigned long long)tot);
 }
 
 // ------------------------------------------------------------------ scans
@@ -279,7 +414,7 @@ constexpr int SCAN_WG = 256, SCAN_PER = 16, SCAN_TILE = SCAN_WG * SCAN_PER;
 
 __global__ void __launch_bounds__(SCAN_WG) k_scan_up(const uint32_t *__restrict__ in, size_t n,
                                                       uint32_t *__restrict__ bsum) {
-    __shared__ uint32_t red[SCAN_WG / 64 + 1];
+    __shared__ uint32_t red[SCAN_WG / 64];
     const size_t base = (size_t)blockIdx.x * SCAN_TILE;
     uint32_t s = 0;
 #pragma unroll
@@ -295,7 +430,7 @@ __global__ void __launch_bounds__(SCAN_WG) k_scan_up(const uint32_t *__restrict_
 // One workgroup: exclusive scan of nb block sums in place; the grand total
 // goes to bsum[nb].
 __global__ void __launch_bounds__(SCAN_WG) k_scan_mid(uint32_t *bsum, uint32_t nb) {
-    __shared__ uint32_t red[SCAN_WG / 64 + 1];
+    __shared__ uint32_t red[SCAN_WG / 64];
     uint32_t carry = 0;
     for (uint32_t b0 = 0; b0 < nb; b0 += SCAN_WG) {
         const uint32_t j = b0 + threadIdx.x;
@@ -311,7 +446,7 @@ __global__ void __launch_bounds__(SCAN_WG) k_scan_mid(uint32_t *bsum, uint32_t n
 __global__ void __launch_bounds__(SCAN_WG) k_scan_down(const uint32_t *__restrict__ in, size_t n,
                                                         const uint32_t *__restrict__ bsum,
                                                         uint32_t *__restrict__ out1, uint32_t *__restrict__ out2) {
-    __shared__ uint32_t red[SCAN_WG / 64 + 1];
+    __shared__ uint32_t red[SCAN_WG / 64];
     // each thread owns SCAN_PER consecutive elements
     const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_PER;
     uint32_t v[SCAN_PER];
@@ -334,63 +469,100 @@ __global__ void __launch_bounds__(SCAN_WG) k_scan_down(const uint32_t *__restric
 }
 
 // -------------------------------------------------------------- expansion
-__global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *__restrict__ subs, uint32_t nsub,
+__global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32_t nsub, uint32_t nitems,
                                                      unsigned long long *__restrict__ rec,
                                                      uint32_t *__restrict__ cursor) {
     __shared__ unsigned long long stage[TILE];
-    __shared__ uint32_t h[NBMAX];
-    __shared__ uint32_t dl[NBMAX];
-    __shared__ uint32_t red[EXP_WG / 64 + 1];
-    const Item it = resolve_item(subs, nsub, blockIdx.x);
-    const DevSub &S = *it.S;
-    const uint32_t nb = S.nb;
-    for (uint32_t i = threadIdx.x; i < nb; i += EXP_WG) h[i] = 0;
-    __syncthreads();
-    const uint32_t span = S.khi - S.klo;
-    const uint32_t rwbit = it.E->rw;
-    unsigned long long r[RPL];
-    uint32_t bk[RPL], rk[RPL];
-    expand_item(it, [&](int s, bool ok, bool inb, uint32_t loc, uint32_t id) {
-        const uint32_t rel = loc - S.klo;
-        const bool v = ok && inb && rel < span;
-        const uint32_t b = rel >> S.s;
-        rk[s] = lds_rank(h, b, v);
-        bk[s] = v ? b : 0xFFFFFFFFu;
-        r[s] = ((unsigned long long)((loc << 1) | rwbit) << 32) | id;
-    });
-    __syncthreads();
-    // exclusive scan of the tile histogram (each thread owns a run of bins)
-    constexpr int PER = NBMAX / EXP_WG;
-    const uint32_t b0 = threadIdx.x * PER;
-    uint32_t hv[PER];
-    uint32_t sum = 0;
+    __shared__ uint32_t h[BINCAP];
+    __shared__ uint32_t dl[BINCAP];
+    __shared__ uint32_t red[3 * (EXP_WG / 64)];
+    constexpr int PER = BINCAP / EXP_WG;
+    CSub *subs = cptr(subs_g);
+    uint32_t w0, w1;
+    my_items(nitems, w0, w1);
+    if (w0 >= w1) return;
+    Cursor cur;
+    seek(subs, nsub, w0, cur);
+    for (uint32_t w = w0; w < w1; w++) {
+        CSub &S = subs[cur.sub];
+        CEnt &E = cptr(S.entries)[cur.e];
+        CKer &K = *cptr(S.kc);
+        const uint32_t nl = E.n_lchunks;
+        const uint32_t gtile = cur.li / nl, lchunk = cur.li - gtile * nl;
+        const uint32_t span = S.khi - S.klo;
+        const uint32_t rwbit = E.rw;
+        unsigned long long r[RPL];
+        uint32_t bk[RPL];
+        uint32_t mn = 0xFFFFFFFFu, mx = 0, n = 0;
+        expand_item(S, E, K, cptr(S.guards), gtile, lchunk, [&](int s, bool ok, bool inb, uint32_t loc, uint32_t id) {
+            const uint32_t rel = loc - S.klo;
+            const bool v = ok && inb && rel < span;
+            const uint32_t b = rel >> S.s;
+            bk[s] = v ? b : 0xFFFFFFFFu;
+            r[s] = ((unsigned long long)((loc << 1) | rwbit) << 32) | id;
+            if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
+        });
+        block_min_max_sum<EXP_WG>(mn, mx, n, red);
+        uint32_t *gcur = cursor + S.bucket_begin;
+        if (n && mx - mn < (uint32_t)BINCAP) {
+            const uint32_t R = mx - mn + 1;
+            for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
+            __syncthreads();
+            uint32_t rk[RPL];
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
-        hv[i] = (b0 + i < nb) ? h[b0 + i] : 0u;
-        sum += hv[i];
-    }
-    uint32_t total;
-    uint32_t run = block_excl_add<EXP_WG>(sum, red, &total);
+            for (int s = 0; s < RPL; s++) rk[s] = lds_rank(h, bk[s] - mn, bk[s] != 0xFFFFFFFFu);
+            __syncthreads();
+            // exclusive scan of the tile histogram; thread t owns bins [t*PER, t*PER + PER)
+            const uint32_t b0 = threadIdx.x * PER;
+            uint32_t hv[PER];
+            uint32_t sum = 0;
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
-        if (b0 + i < nb) h[b0 + i] = run;
-        run += hv[i];
-    }
-    __syncthreads();
+            for (int i = 0; i < PER; i++) {
+                hv[i] = (b0 + i < R) ? h[b0 + i] : 0u;
+                sum += hv[i];
+            }
+            uint32_t total;
+            uint32_t run = block_excl_add<EXP_WG>(sum, red, &total);
 #pragma unroll
-    for (int s = 0; s < RPL; s++)
-        if (bk[s] != 0xFFFFFFFFu) stage[h[bk[s]] + rk[s]] = r[s];
-    // reserve the bucket ranges in the chunk: one atomic per nonempty bucket
+            for (int i = 0; i < PER; i++) {
+                if (hv[i]) {
+                    h[b0 + i] = run;
+                    // reserve this bucket's run in the chunk: one atomic per bucket and tile
+                    dl[b0 + i] = atomicAdd(&gcur[mn + b0 + i], hv[i]) - run;
+                }
+                run += hv[i];
+            }
+            __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
-        const uint32_t b = b0 + i;
-        if (b < nb && hv[i]) dl[b] = atomicAdd(&cursor[S.bucket_begin + b], hv[i]) - h[b];
-    }
-    __syncthreads();
-    for (uint32_t p = threadIdx.x; p < total; p += EXP_WG) {
-        const unsigned long long v = stage[p];
-        const uint32_t b = ((uint32_t)(v >> 33) - S.klo) >> S.s;
-        rec[dl[b] + p] = v;
+            for (int s = 0; s < RPL; s++)
+                if (bk[s] != 0xFFFFFFFFu) stage[h[bk[s] - mn] + rk[s]] = r[s];
+            __syncthreads();
+            for (uint32_t p = threadIdx.x; p < total; p += EXP_WG) {
+                const unsigned long long v = stage[p];
+                const uint32_t b = (((uint32_t)(v >> 33) - S.klo) >> S.s) - mn;
+                rec[dl[b] + p] = v;
+            }
+            __syncthreads();
+        } else if (n) {
+            // a tile spread over more than BINCAP buckets: reserve per record
+#pragma unroll
+            for (int s = 0; s < RPL; s++) {
+                const bool v = bk[s] != 0xFFFFFFFFu;
+                const uint64_t act = __ballot(v);
+                if (!act) continue;
+                const uint32_t lead = (uint32_t)__builtin_ctzll(act);
+                const uint32_t lb = readlane(bk[s], lead);
+                uint32_t pos = 0;
+                if (__ballot(v && bk[s] == lb) == act) {
+                    if (lane() == lead) pos = atomicAdd(&gcur[lb], (uint32_t)__popcll(act));
+                    pos = readlane(pos, lead) + mbcnt(act);
+                } else if (v) {
+                    pos = atomicAdd(&gcur[bk[s]], 1u);
+                }
+                if (v) rec[pos] = r[s];
+            }
+        }
+        if (w + 1 < w1) advance(subs, cur);
     }
 }
 
@@ -436,19 +608,26 @@ __device__ __forceinline__ Seg shfl_up1(const Seg &a) {
 }
 
 __device__ __forceinline__ void seg_combine(Seg &acc, const Seg &b) {   // acc <- acc (+) b
-    if (b.f) {
-        acc = b;
-    } else {
-        acc.mn = min(acc.mn, b.mn);
-        acc.mx = max(acc.mx, b.mx);
-        acc.mnw = min(acc.mnw, b.mnw);
-        acc.mxw1 = max(acc.mxw1, b.mxw1);
-    }
+    acc.mn = b.f ? b.mn : min(acc.mn, b.mn);
+    acc.mx = b.f ? b.mx : max(acc.mx, b.mx);
+    acc.mnw = b.f ? b.mnw : min(acc.mnw, b.mnw);
+    acc.mxw1 = b.f ? b.mxw1 : max(acc.mxw1, b.mxw1);
+    acc.f |= b.f;
 }
 
 constexpr int TBL = 1 << SMAX;
+constexpr int TPER = TBL / BKT_WG;           // table entries per thread
+static_assert(TBL % BKT_WG == 0, "table split");
 
-__global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *__restrict__ subs, uint32_t nsub,
+__device__ __forceinline__ void fold(uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
+                                     uint32_t k, const Seg &s) {
+    atomicMin(&t_mn[k], s.mn);
+    atomicMax(&t_mx[k], s.mx);
+    atomicMin(&t_mnw[k], s.mnw);
+    atomicMax(&t_mxw1[k], s.mxw1);
+}
+
+__global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *subs_g, uint32_t nsub, uint32_t nbuckets,
                                                     unsigned long long *__restrict__ rec,
                                                     const uint32_t *__restrict__ starts,
                                                     const uint32_t *__restrict__ counts,
@@ -458,169 +637,199 @@ __global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *__restrict__ su
     __shared__ uint32_t bins[TBL];
     __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
     __shared__ Seg wtot[BKT_WG / 64];
-    __shared__ uint32_t red[BKT_WG / 64 + 1];
-
-    const uint32_t b = blockIdx.x;
-    const uint32_t cnt = counts[b];
-    if (cnt == 0) {
-        if (threadIdx.x == 0) conf[b] = 0;
-        return;
-    }
-    const DevSub &S = subs[sub_by_bucket(subs, nsub, b)];
-    const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
-    const uint32_t width = min(1u << S.s, S.khi - lo);
-    const uint32_t start = starts[b];
+    __shared__ uint32_t red[BKT_WG / 64];
+    CSub *subs = cptr(subs_g);
     const uint32_t t = threadIdx.x;
     const uint32_t wid = t >> 6;
-    if (t < TBL) {
-        t_mn[t] = 0xFFFFFFFFu; t_mx[t] = 0; t_mnw[t] = 0xFFFFFFFFu; t_mxw1[t] = 0;
-    }
+    const Seg ident{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
 
-    for (uint32_t slice = 0; slice < cnt; slice += CAP) {
-        const uint32_t n = min((uint32_t)CAP, cnt - slice);
-        const unsigned long long *src = rec + start + slice;
-        unsigned long long r[BKT_RPL];
+    for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
+        const uint32_t cnt = counts[b];
+        if (cnt == 0) {
+            if (t == 0) conf[b] = 0;
+            continue;
+        }
+        uint32_t lo_s = 0, hi_s = nsub;
+        while (hi_s - lo_s > 1) {
+            const uint32_t mid = (lo_s + hi_s) >> 1;
+            if (subs[mid].bucket_begin <= b) lo_s = mid; else hi_s = mid;
+        }
+        CSub &S = subs[lo_s];
+        const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
+        const uint32_t width = min(1u << S.s, S.khi - lo);
+        const uint32_t start = starts[b];
 #pragma unroll
-        for (int i = 0; i < BKT_RPL; i++) {
-            const uint32_t j = (uint32_t)i * BKT_WG + t;
-            r[i] = j < n ? src[j] : 0ull;
+        for (int i = 0; i < TPER; i++) {
+            const uint32_t k = t * TPER + i;
+            t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
         }
-        if (t < TBL) bins[t] = 0;
-        __syncthreads();
-        // --- LDS radix sort, one digit of `s` bits (the bucket's local key)
-        uint32_t kk[BKT_RPL], off[BKT_RPL];
+        for (uint32_t slice = 0; slice < cnt; slice += CAP) {
+            const uint32_t n = min((uint32_t)CAP, cnt - slice);
+            const unsigned long long *src = rec + start + slice;
+            // keep 32-bit ids and 16-bit keys (local key | rw << 15) in registers
+            uint32_t id[BKT_RPL], kw[BKT_RPL];
 #pragma unroll
-        for (int i = 0; i < BKT_RPL; i++) {
-            const bool v = (uint32_t)i * BKT_WG + t < n;
-            kk[i] = v ? ((uint32_t)(r[i] >> 33) - lo) : 0u;
-            off[i] = lds_rank(bins, kk[i], v);
-        }
-        __syncthreads();
-        {
-            uint32_t tot;
-            const uint32_t x = t < TBL ? bins[t] : 0u;
-            const uint32_t ex = block_excl_add<BKT_WG>(x, red, &tot);
-            if (t < TBL) bins[t] = ex;
-        }
-        __syncthreads();
+            for (int i = 0; i < BKT_RPL; i++) {
+                const uint32_t j = (uint32_t)i * BKT_WG + t;
+                const unsigned long long x = j < n ? src[j] : 0ull;
+                const uint32_t hi = (uint32_t)(x >> 32);
+                id[i] = (uint32_t)x;
+                kw[i] = j < n ? (((hi >> 1) - lo) | ((hi & 1u) << 15)) : 0u;
+            }
 #pragma unroll
-        for (int i = 0; i < BKT_RPL; i++) {
-            if ((uint32_t)i * BKT_WG + t < n) {
-                const uint32_t pos = bins[kk[i]] + off[i];
-                sid[pos] = (uint32_t)r[i];
-                sk[pos] = (uint16_t)(kk[i] | (((uint32_t)(r[i] >> 32) & 1u) << 15));
+            for (int i = 0; i < TPER; i++) bins[t * TPER + i] = 0;
+            __syncthreads();
+            // --- LDS radix sort: one digit of `s` bits (the bucket's local key)
+            uint32_t off[BKT_RPL];
+#pragma unroll
+            for (int i = 0; i < BKT_RPL; i++) {
+                const bool v = (uint32_t)i * BKT_WG + t < n;
+                off[i] = wlms_rank(bins, kw[i] & 0x7FFFu, v, S.s);
             }
-        }
-        __syncthreads();
-        if (debug_sorted) {
-            for (uint32_t j = t; j < n; j += BKT_WG) {
-                const uint32_t key = sk[j];
-                const uint32_t hi = ((lo + (key & 0x7FFFu)) << 1) | (key >> 15);
-                rec[start + slice + j] = ((unsigned long long)hi << 32) | sid[j];
+            __syncthreads();
+            {
+                uint32_t hv[TPER], sum = 0, tot;
+#pragma unroll
+                for (int i = 0; i < TPER; i++) { hv[i] = bins[t * TPER + i]; sum += hv[i]; }
+                uint32_t run = block_excl_add<BKT_WG>(sum, red, &tot);
+#pragma unroll
+                for (int i = 0; i < TPER; i++) { bins[t * TPER + i] = run; run += hv[i]; }
             }
-        }
-        // --- segmented scan over runs of equal key
-        const uint32_t r0 = t * BKT_RPL;
-        const uint32_t r1 = min(r0 + BKT_RPL, n);
-        Seg a{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
-        uint32_t prevk = r0 > 0 && r0 < n ? (sk[r0 - 1] & 0x7FFFu) : 0xFFFFu;
-        for (uint32_t j = r0; j < r1; j++) {
-            const uint32_t key = sk[j];
-            const uint32_t k = key & 0x7FFFu;
-            if (k != prevk) {   // head (j == 0 always is: prevk starts out of range)
-                a.f = 1; a.mn = 0xFFFFFFFFu; a.mx = 0; a.mnw = 0xFFFFFFFFu; a.mxw1 = 0;
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < BKT_RPL; i++) {
+                if ((uint32_t)i * BKT_WG + t < n) {
+                    const uint32_t pos = bins[kw[i] & 0x7FFFu] + off[i];
+                    sid[pos] = id[i];
+                    sk[pos] = (uint16_t)kw[i];
+                }
             }
-            seg_add(a, sid[j], key >> 15);
-            prevk = k;
-        }
-        // inclusive segmented scan across the wave (DPP), then exclusive
-        Seg inc = a;
-        seg_dpp_step<ROW_SHR1, 0xf>(inc);
-        seg_dpp_step<ROW_SHR2, 0xf>(inc);
-        seg_dpp_step<ROW_SHR4, 0xf>(inc);
-        seg_dpp_step<ROW_SHR8, 0xf>(inc);
-        seg_dpp_step<ROW_BCAST15, 0xa>(inc);
-        seg_dpp_step<ROW_BCAST31, 0xc>(inc);
-        if (lane() == 63) wtot[wid] = inc;
-        Seg carry = shfl_up1(inc);
-        __syncthreads();
-        {
-            Seg wc{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
-            for (uint32_t w = 0; w < wid; w++) seg_combine(wc, wtot[w]);
-            seg_combine(wc, carry);
-            carry = wc;
-        }
-        // finalize segments that end in this run
-        if (r0 < r1) {
-            const uint32_t k0 = sk[r0] & 0x7FFFu;
-            const bool head0 = (r0 == 0) || ((sk[r0 - 1] & 0x7FFFu) != k0);
-            Seg cur = head0 ? Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u} : carry;
-            uint32_t pk = k0;
+            __syncthreads();
+            if (debug_sorted) {
+                for (uint32_t j = t; j < n; j += BKT_WG) {
+                    const uint32_t key = sk[j];
+                    const uint32_t hi = ((lo + (key & 0x7FFFu)) << 1) | (key >> 15);
+                    rec[start + slice + j] = ((unsigned long long)hi << 32) | sid[j];
+                }
+            }
+            // --- segmented scan over runs of equal key (thread-serial runs, DPP across lanes)
+            const uint32_t r0 = t * BKT_RPL;
+            const uint32_t r1 = min(r0 + BKT_RPL, n);
+            Seg a = ident;
+            uint32_t prevk = r0 > 0 && r0 < n ? (sk[r0 - 1] & 0x7FFFu) : 0xFFFFu;
             for (uint32_t j = r0; j < r1; j++) {
                 const uint32_t key = sk[j];
                 const uint32_t k = key & 0x7FFFu;
-                if (j != r0 && k != pk) {
-                    atomicMin(&t_mn[pk], cur.mn);
-                    atomicMax(&t_mx[pk], cur.mx);
-                    atomicMin(&t_mnw[pk], cur.mnw);
-                    atomicMax(&t_mxw1[pk], cur.mxw1);
-                    cur = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                if (k != prevk) {   // segment head
+                    a.f = 1; a.mn = 0xFFFFFFFFu; a.mx = 0; a.mnw = 0xFFFFFFFFu; a.mxw1 = 0;
                 }
-                seg_add(cur, sid[j], key >> 15);
-                pk = k;
+                seg_add(a, sid[j], key >> 15);
+                prevk = k;
             }
-            const bool ends = (r1 == n) || ((sk[r1] & 0x7FFFu) != pk);
-            if (ends) {
-                atomicMin(&t_mn[pk], cur.mn);
-                atomicMax(&t_mx[pk], cur.mx);
-                atomicMin(&t_mnw[pk], cur.mnw);
-                atomicMax(&t_mxw1[pk], cur.mxw1);
+            Seg inc = a;
+            seg_dpp_step<ROW_SHR1, 0xf>(inc);
+            seg_dpp_step<ROW_SHR2, 0xf>(inc);
+            seg_dpp_step<ROW_SHR4, 0xf>(inc);
+            seg_dpp_step<ROW_SHR8, 0xf>(inc);
+            seg_dpp_step<ROW_BCAST15, 0xa>(inc);
+            seg_dpp_step<ROW_BCAST31, 0xc>(inc);
+            if (lane() == 63) wtot[wid] = inc;
+            Seg carry = shfl_up1(inc);
+            __syncthreads();
+            {
+                Seg wc = ident;
+                for (uint32_t w = 0; w < wid; w++) seg_combine(wc, wtot[w]);
+                seg_combine(wc, carry);
+                carry = wc;
             }
+            // finalize the segments that end inside this run
+            if (r0 < r1) {
+                const uint32_t k0 = sk[r0] & 0x7FFFu;
+                const bool head0 = (r0 == 0) || ((sk[r0 - 1] & 0x7FFFu) != k0);
+                Seg cur;
+                cur.f = 0;
+                cur.mn = head0 ? 0xFFFFFFFFu : carry.mn;
+                cur.mx = head0 ? 0u : carry.mx;
+                cur.mnw = head0 ? 0xFFFFFFFFu : carry.mnw;
+                cur.mxw1 = head0 ? 0u : carry.mxw1;
+                uint32_t pk = k0;
+                for (uint32_t j = r0; j < r1; j++) {
+                    const uint32_t key = sk[j];
+                    const uint32_t k = key & 0x7FFFu;
+                    if (j != r0 && k != pk) {
+                        fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
+                        cur.mn = 0xFFFFFFFFu; cur.mx = 0; cur.mnw = 0xFFFFFFFFu; cur.mxw1 = 0;
+                    }
+                    seg_add(cur, sid[j], key >> 15);
+                    pk = k;
+                }
+                if ((r1 == n) || ((sk[r1] & 0x7FFFu) != pk)) fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
+            }
+            __syncthreads();
         }
-        __syncthreads();
-    }
 
-    // --- flag conflicting locations, in key order
-    bool c = false;
-    uint32_t mnw = 0, second = 0, srw = 0;
-    if (t < width) {
-        const uint32_t mn = t_mn[t];
-        const uint32_t mxw1 = t_mxw1[t];
-        if (mn != 0xFFFFFFFFu && mxw1 != 0u) {
-            const uint32_t mx = t_mx[t];
-            mnw = t_mnw[t];
-            const uint32_t th_mn = udiv(mn, S.mgM), th_mx = udiv(mx, S.mgM);
-            if (th_mn != th_mx) {
-                c = true;
-                const uint32_t th_w = udiv(mnw, S.mgM);
-                if (th_mn != th_w) { second = mn; srw = (mn == mnw) ? 1u : 0u; }
-                else { second = mx; srw = (mx + 1 == mxw1) ? 1u : 0u; }
+        // --- flag conflicting locations, in key order (thread t owns keys t*TPER ..)
+        bool c[TPER];
+        uint32_t mnw[TPER], second[TPER], srw[TPER];
+        uint32_t nc = 0;
+#pragma unroll
+        for (int i = 0; i < TPER; i++) {
+            const uint32_t k = t * TPER + i;
+            c[i] = false; mnw[i] = 0; second[i] = 0; srw[i] = 0;
+            if (k < width) {
+                const uint32_t mn = t_mn[k], mxw1 = t_mxw1[k];
+                if (mn != 0xFFFFFFFFu && mxw1 != 0u) {
+                    const uint32_t mx = t_mx[k];
+                    mnw[i] = t_mnw[k];
+                    const uint32_t th_mn = udiv(mn, ldm(S.mgM)), th_mx = udiv(mx, ldm(S.mgM));
+                    if (th_mn != th_mx) {
+                        c[i] = true;
+                        const uint32_t th_w = udiv(mnw[i], ldm(S.mgM));
+                        if (th_mn != th_w) { second[i] = mn; srw[i] = (mn == mnw[i]) ? 1u : 0u; }
+                        else { second[i] = mx; srw[i] = (mx + 1 == mxw1) ? 1u : 0u; }
+                    }
+                }
+            }
+            nc += c[i] ? 1u : 0u;
+        }
+        uint32_t total;
+        uint32_t pos = block_excl_add<BKT_WG>(nc, red, &total);
+        if (!debug_sorted) {   // the region start is 8-byte aligned: store words
+            uint32_t *wout = reinterpret_cast<uint32_t *>(rec + start);
+#pragma unroll
+            for (int i = 0; i < TPER; i++) {
+                if (c[i]) {
+                    uint32_t *w = wout + 4 * (size_t)pos;
+                    w[0] = lo + t * TPER + i; w[1] = mnw[i]; w[2] = second[i]; w[3] = srw[i];
+                    pos++;
+                }
             }
         }
+        if (t == 0) conf[b] = total;
     }
-    uint32_t total;
-    const uint32_t pos = block_excl_add<BKT_WG>(c ? 1u : 0u, red, &total);
-    if (c && !debug_sorted) {   // the region start is 8-byte aligned: store words
-        uint32_t *w = reinterpret_cast<uint32_t *>(rec + start) + 4 * (size_t)pos;
-        w[0] = lo + t; w[1] = mnw; w[2] = second; w[3] = srw;
-    }
-    if (t == 0) conf[b] = total;
 }
 
 // ------------------------------------------------------------- finishing
-__global__ void k_finish(const DevSub *__restrict__ subs, uint32_t nsub, size_t nbuckets,
-                         const uint32_t *__restrict__ conf, SubResult *__restrict__ res) {
+__global__ void k_finish(const DevSub *subs_g, uint32_t nsub, size_t nbuckets, const uint32_t *__restrict__ conf,
+                         SubResult *__restrict__ res) {
+    CSub *subs = cptr(subs_g);
     const size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbuckets) return;
     const uint32_t c = conf[b];
     if (!c) return;
-    const DevSub &S = subs[sub_by_bucket(subs, nsub, (uint32_t)b)];
-    atomicAdd(&res[S.res].conflicts, (unsigned long long)c);
-    atomicMin(&res[S.res].first_bucket, (uint32_t)b);
+    uint32_t lo = 0, hi = nsub;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (subs[mid].bucket_begin <= (uint32_t)b) lo = mid; else hi = mid;
+    }
+    const uint32_t slot = subs[lo].res;
+    atomicAdd(&res[slot].conflicts, (unsigned long long)c);
+    atomicMin(&res[slot].first_bucket, (uint32_t)b);
 }
 
-__global__ void k_first(const DevSub *__restrict__ subs, uint32_t nsub, const unsigned long long *__restrict__ rec,
+__global__ void k_first(const DevSub *subs_g, uint32_t nsub, const unsigned long long *__restrict__ rec,
                         const uint32_t *__restrict__ starts, SubResult *__restrict__ res) {
+    CSub *subs = cptr(subs_g);
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nsub) return;
     SubResult &R = res[subs[j].res];
@@ -630,16 +839,22 @@ __global__ void k_first(const DevSub *__restrict__ subs, uint32_t nsub, const un
     R.w[0] = w[0]; R.w[1] = w[1]; R.w[2] = w[2]; R.w[3] = w[3];
 }
 
-__global__ void k_gather(const DevSub *__restrict__ subs, uint32_t nsub, const unsigned long long *__restrict__ rec,
+__global__ void k_gather(const DevSub *subs_g, uint32_t nsub, const unsigned long long *__restrict__ rec,
                          const uint32_t *__restrict__ starts, const uint32_t *__restrict__ conf,
                          const uint32_t *__restrict__ wpos, unsigned long long base, unsigned long long lo,
                          unsigned long long hi, DevWitness *__restrict__ out) {
+    CSub *subs = cptr(subs_g);
     const uint32_t b = blockIdx.x;
     const uint32_t c = conf[b];
     if (!c) return;
     const unsigned long long first = base + wpos[b];
     if (first >= hi || first + c <= lo) return;
-    const uint32_t sub = subs[sub_by_bucket(subs, nsub, b)].res;
+    uint32_t slo = 0, shi = nsub;
+    while (shi - slo > 1) {
+        const uint32_t mid = (slo + shi) >> 1;
+        if (subs[mid].bucket_begin <= b) slo = mid; else shi = mid;
+    }
+    const uint32_t sub = subs[slo].res;
     const uint32_t *w = reinterpret_cast<const uint32_t *>(rec + starts[b]);
     for (uint32_t k = threadIdx.x; k < c; k += blockDim.x) {
         const unsigned long long g = first + k;
@@ -658,6 +873,22 @@ static inline unsigned grid_for(size_t n, unsigned per) {
     return (unsigned)(g < 1 ? 1 : (g > 65535u * 16 ? 65535u * 16 : g));
 }
 
+// Resident workgroups per CU of a kernel (queried once).
+template <class K>
+static unsigned occupancy(K kern, int block, unsigned fallback) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, 0) != hipSuccess || n < 1) return fallback;
+    return (unsigned)n;
+}
+
+// persistent grid: a multiple of 8 workgroups, no more than one per item
+static inline unsigned persistent_grid(uint64_t items, unsigned ncu, unsigned per_cu) {
+    uint64_t g = (uint64_t)ncu * per_cu;
+    if (g > items) g = items;
+    g = (g + 7) & ~7ull;
+    return (unsigned)(g < 8 ? 8 : g);
+}
+
 void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st) {
     if (!n) return;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256 * 4)), dim3(256), 0, st, p, n, v);
@@ -669,9 +900,11 @@ void launch_init_results(SubResult *r, size_t n, hipStream_t st) {
 }
 
 void launch_hist(const DevSub *subs, uint32_t nsub, uint64_t items, uint32_t *counts, SubResult *res,
-                 hipStream_t st) {
+                 unsigned ncu, hipStream_t st) {
     if (!items) return;
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)items), dim3(EXP_WG), 0, st, subs, nsub, counts, res);
+    static const unsigned occ = occupancy(k_hist, EXP_WG, 4);
+    hipLaunchKernelGGL(k_hist, dim3(persistent_grid(items, ncu, occ)), dim3(EXP_WG), 0, st, subs, nsub,
+                       (uint32_t)items, counts, res);
 }
 
 size_t scan_bsum_words(size_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
@@ -685,17 +918,22 @@ void launch_scan(const uint32_t *in, uint32_t *starts, uint32_t *cursor, uint32_
 }
 
 void launch_scatter(const DevSub *subs, uint32_t nsub, uint64_t items, unsigned long long *rec, uint32_t *cursor,
-                    hipStream_t st) {
+                    unsigned ncu, hipStream_t st) {
     if (!items) return;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)items), dim3(EXP_WG), 0, st, subs, nsub, rec, cursor);
+    static const unsigned occ = occupancy(k_scatter, EXP_WG, 2);
+    hipLaunchKernelGGL(k_scatter, dim3(persistent_grid(items, ncu, occ)), dim3(EXP_WG), 0, st, subs, nsub,
+                       (uint32_t)items, rec, cursor);
 }
 
 void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
                    const uint32_t *starts, const uint32_t *counts, uint32_t *conf, int debug_sorted,
-                   hipStream_t st) {
+                   unsigned ncu, hipStream_t st) {
     if (!nbuckets) return;
-    hipLaunchKernelGGL(k_bucket, dim3((unsigned)nbuckets), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts,
-                       conf, debug_sorted);
+    static const unsigned occ = occupancy(k_bucket, BKT_WG, 2);
+    uint64_t g = (uint64_t)ncu * occ;
+    if (g > nbuckets) g = nbuckets;
+    hipLaunchKernelGGL(k_bucket, dim3((unsigned)g), dim3(BKT_WG), 0, st, subs, nsub, (uint32_t)nbuckets, rec,
+                       starts, counts, conf, debug_sorted);
 }
 
 void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf, SubResult *res,

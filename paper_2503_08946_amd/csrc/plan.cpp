@@ -314,7 +314,7 @@ WorkspaceLayout layout_workspace(size_t bytes) {
     // records : buckets = 8 B : 16 B per 256 records
     size_t R = (size_t)(((long double)(bytes - reserve)) / (8.0L + 16.0L / 256.0L));
     R = std::min<size_t>(R, (size_t)0xFFF00000u);
-    size_t BC = std::max<size_t>(1 << 16, R / 256);
+    size_t BC = std::max<size_t>((size_t)NBMAX, R / 256);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = al(R * 8);
     L.off_counts = off; off = al(off + BC * 4);

@@ -16,14 +16,16 @@ namespace rv {
 constexpr int EXP_WG = 256;              // expansion workgroup (4 waves)
 constexpr int RPL = 16;                  // records per lane per work item
 constexpr int TILE = EXP_WG * RPL;       // records per expansion work item
-constexpr int NBMAX = 4096;              // location buckets per key-range pass
+constexpr int BINCAP = 2048;             // buckets one expansion tile may span on the LDS path
+constexpr int NBMAX = 1 << 20;           // location buckets per key-range pass
 constexpr int SMAX = 9;                  // a bucket spans at most 2^SMAX locations
-constexpr int BKT_WG = 512;              // sort + scan workgroup (8 waves)
+constexpr int BKT_WG = 256;              // sort + scan workgroup (4 waves)
 constexpr int BKT_RPL = 16;              // records per lane in one on-chip slice
 constexpr int CAP = BKT_WG * BKT_RPL;    // records per on-chip slice
-constexpr int DEFAULT_TARGET = 4096;     // planner: mean records per bucket
+constexpr int DEFAULT_TARGET = 2048;     // planner: mean records per bucket
 
-static_assert((1 << SMAX) <= BKT_WG, "one bucket location per sort+scan thread");
+static_assert((1 << SMAX) % BKT_WG == 0, "bucket locations split evenly over sort+scan threads");
+static_assert(BINCAP % EXP_WG == 0, "tile bins split evenly over expansion threads");
 
 // ------------------------------------------- division by invariant integers
 // floor(n / d) for 32-bit n and a divisor d >= 1 fixed at plan time:
@@ -221,14 +223,14 @@ struct Timer;
 void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 void launch_init_results(SubResult *r, size_t n, hipStream_t st);
 void launch_hist(const DevSub *subs, uint32_t nsub, uint64_t items, uint32_t *counts, SubResult *res,
-                 hipStream_t st);
+                 unsigned ncu, hipStream_t st);
 void launch_scan(const uint32_t *in, uint32_t *starts, uint32_t *cursor, uint32_t *bsum, size_t n,
                  hipStream_t st);
 void launch_scatter(const DevSub *subs, uint32_t nsub, uint64_t items, unsigned long long *rec,
-                    uint32_t *cursor, hipStream_t st);
+                    uint32_t *cursor, unsigned ncu, hipStream_t st);
 void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
                    const uint32_t *starts, const uint32_t *counts, uint32_t *conf, int debug_sorted,
-                   hipStream_t st);
+                   unsigned ncu, hipStream_t st);
 void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf,
                    SubResult *res, hipStream_t st);
 void launch_first(const DevSub *subs, uint32_t nsub, const unsigned long long *rec,

@@ -187,14 +187,15 @@ def test_hot_location_exceeds_one_slice(ctx):
 
 
 def test_key_range_passes(ctx):
-    # a 3M-element global array touched sparsely: the interval's location space
-    # needs more than one key-range pass
+    # a 2^30-element global array touched sparsely: the interval's location
+    # space needs more than one key-range pass
     b = Builder((64, 1), (32, 1), "wide-global")
-    g = b.array(GLOBAL, (3 << 20,))
-    p = b.phase([rw(g, True, aff(tx=1, bx=98304)),
-                 rw(g, False, aff(7, tx=1, bx=98304)),
-                 rw(g, True, aff(3 << 19, tx=2)),
-                 rw(g, False, aff(3 << 19, tx=1))], False)
+    g = b.array(GLOBAL, (1 << 30,))
+    stride = (1 << 30) // 32
+    p = b.phase([rw(g, True, aff(tx=1, bx=stride)),
+                 rw(g, False, aff(7, tx=1, bx=stride)),
+                 rw(g, True, aff(3 << 28, tx=2)),
+                 rw(g, False, aff(3 << 28, tx=1))], False)
     b.segment([p])
     desc = b.build()
     k = ctx.load(desc)
