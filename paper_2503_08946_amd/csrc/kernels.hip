@@ -158,35 +158,6 @@ __device__ __forceinline__ uint32_t lds_rank(uint32_t *h, uint32_t b, bool v) {
     return v ? atomicAdd(&h[b], 1u) : 0u;
 }
 
-// Rank by wave-level multi-split: `nbits` ballots find the lanes holding the
-// same key; one atomic per distinct key in the wave, ranks in lane order.
-__device__ __forceinline__ uint32_t wlms_rank(uint32_t *h, uint32_t k, bool v, uint32_t nbits) {
-    const uint64_t act = __ballot(v);
-    if (act == 0) return 0;
-    const uint32_t lead = (uint32_t)__builtin_ctzll(act);
-    const uint32_t lk = readlane(k, lead);
-    const uint64_t same = __ballot(v && k == lk);
-    if (same == act) {
-        uint32_t base = 0;
-        if (lane() == lead) base = atomicAdd(&h[lk], (uint32_t)__popcll(act));
-        base = readlane(base, lead);
-        return base + mbcnt(act);
-    }
-    uint64_t peers = act;
-    for (uint32_t bit = 0; bit < nbits; bit++) {
-        const bool x = (k >> bit) & 1u;
-        const uint64_t bb = __ballot(x);
-        peers &= x ? bb : ~bb;
-    }
-    if (!v || peers == 0) peers = 1ull << lane();
-    const uint32_t rank = mbcnt(peers);
-    const uint32_t leader = (uint32_t)__builtin_ctzll(peers);
-    uint32_t base = 0;
-    if (v && rank == 0) base = atomicAdd(&h[k], (uint32_t)__popcll(peers));
-    base = (uint32_t)__shfl((int)base, (int)leader);
-    return base + rank;
-}
-
 // ------------------------------------------------------------ work items
 // A cursor over the work items of a chunk: pass, entry of the pass's
 // interval, item inside the entry.
@@ -330,6 +301,89 @@ __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, 
     }
 }
 
+// Fast path of expand_item for entries without aux terms or guards: the
+// per-thread index bases use 24-bit multiplies, the loop terms are
+// wave-uniform (scalar unit), and the location is one add per record from the
+// flattened row (exact modulo 2^32 for in-bounds records).
+template <class F>
+__device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t gtile, uint32_t lchunk, F &&f) {
+    const uint32_t lch = E.lch, gt = E.gt;
+    const uint32_t lstart = lchunk * lch;
+    const uint32_t lcnt = min(lch, E.box - lstart);
+    const uint32_t e1 = E.ext[1], e2 = E.ext[2];
+    const int32_t lo0 = E.lo[0], lo1 = E.lo[1], lo2 = E.lo[2];
+    int32_t ct[3][5], cl[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        ct[r][0] = E.row[r][C_TX]; ct[r][1] = E.row[r][C_TY]; ct[r][2] = E.row[r][C_BX];
+        ct[r][3] = E.row[r][C_BY]; ct[r][4] = E.row[r][C_C0];
+        cl[r][0] = E.row[r][C_L0]; cl[r][1] = E.row[r][C_L1]; cl[r][2] = E.row[r][C_L2];
+    }
+    const uint32_t d0 = E.dim[0], d1 = E.dim[1], d2 = E.dim[2];
+    const uint32_t ftx = E.fr[C_TX], fty = E.fr[C_TY], fbx = E.fr[C_BX], fby = E.fr[C_BY], fc0 = E.fr[C_C0];
+    const uint32_t fl0 = E.fr[C_L0], fl1 = E.fr[C_L1], fl2 = E.fr[C_L2];
+    const uint32_t loc_mul = E.loc_mul, eoff = E.off;
+    const uint32_t tpb = K.tpb, bdx = K.bdx, gdx = K.gdx, nthreads = K.nthreads, M = S.M;
+    const Magic mg_tpb = ldm(K.mg_tpb), mg_gdx = ldm(K.mg_gdx), mg_bdx = ldm(K.mg_bdx);
+    uint32_t c0s, c1s, c2s;
+    {
+        uint32_t r = lstart;
+        c2s = r % e2; r /= e2;
+        c1s = r % e1; r /= e1;
+        c0s = r;
+    }
+    uint32_t c0 = c0s, c1 = c1s, c2 = c2s;
+    uint32_t gi = 0, li = 0;
+    int32_t base0 = 0, base1 = 0, base2 = 0;
+    uint32_t lbase = 0, idbase = 0;
+    bool gval = false;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const bool active = gi < gt;
+        if (active && li == 0) {
+            const uint32_t g = (gtile * gt + gi) * EXP_WG + threadIdx.x;
+            gval = g < nthreads;
+            const uint32_t gg = gval ? g : 0u;
+            const uint32_t blk = udiv(gg, mg_tpb);
+            const uint32_t tid = gg - blk * tpb;
+            const uint32_t byy = udiv(blk, mg_gdx);
+            const uint32_t tyy = udiv(tid, mg_bdx);
+            const int32_t tx = (int32_t)(tid - tyy * bdx), ty = (int32_t)tyy;
+            const int32_t bx = (int32_t)(blk - byy * gdx), by = (int32_t)byy;
+            base0 = __mul24(ct[0][0], tx) + __mul24(ct[0][1], ty) + __mul24(ct[0][2], bx) + __mul24(ct[0][3], by) + ct[0][4];
+            base1 = __mul24(ct[1][0], tx) + __mul24(ct[1][1], ty) + __mul24(ct[1][2], bx) + __mul24(ct[1][3], by) + ct[1][4];
+            base2 = __mul24(ct[2][0], tx) + __mul24(ct[2][1], ty) + __mul24(ct[2][2], bx) + __mul24(ct[2][3], by) + ct[2][4];
+            lbase = blk * loc_mul + ftx * (uint32_t)tx + fty * (uint32_t)ty + fbx * (uint32_t)bx +
+                    fby * (uint32_t)by + fc0;
+            idbase = gg * M + eoff + lstart;
+        }
+        bool ok = false, inb = false;
+        uint32_t loc = 0, id = 0;
+        if (active) {
+            const int32_t L0 = lo0 + (int32_t)c0, L1 = lo1 + (int32_t)c1, L2 = lo2 + (int32_t)c2;
+            const int32_t i0 = base0 + (cl[0][0] * L0 + cl[0][1] * L1 + cl[0][2] * L2);
+            const int32_t i1 = base1 + (cl[1][0] * L0 + cl[1][1] * L1 + cl[1][2] * L2);
+            const int32_t i2 = base2 + (cl[2][0] * L0 + cl[2][1] * L1 + cl[2][2] * L2);
+            inb = (uint32_t)i0 < d0 && (uint32_t)i1 < d1 && (uint32_t)i2 < d2;
+            loc = lbase + (fl0 * (uint32_t)L0 + fl1 * (uint32_t)L1 + fl2 * (uint32_t)L2);
+            id = idbase + li;
+            ok = gval && li < lcnt;
+        }
+        f(s, ok, inb, loc, id);
+        if (active) {
+            li++;
+            if (li == lch) {
+                li = 0;
+                gi++;
+                c0 = c0s; c1 = c1s; c2 = c2s;
+            } else {
+                c2++;
+                if (c2 == e2) { c2 = 0; c1++; if (c1 == e1) { c1 = 0; c0++; } }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------- fill kernels
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -365,14 +419,17 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
         const uint32_t span = S.khi - S.klo;
         uint32_t bk[RPL];
         uint32_t mn = 0xFFFFFFFFu, mx = 0, n = 0;
-        expand_item(S, E, K, cptr(S.guards), gtile, lchunk, [&](int s, bool ok, bool inb, uint32_t loc, uint32_t id) {
+        const uint32_t klo = S.klo, sh = S.s;
+        auto on_rec = [&](int s, bool ok, bool inb, uint32_t loc, uint32_t id) {
             if (ok && !inb) atomicMin(&res[S.res].oob, ((unsigned long long)S.interval << 32) | id);
-            const uint32_t rel = loc - S.klo;
+            const uint32_t rel = loc - klo;
             const bool v = ok && inb && rel < span;
-            const uint32_t b = rel >> S.s;
+            const uint32_t b = rel >> sh;
             bk[s] = v ? b : 0xFFFFFFFFu;
             if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
-        });
+        };
+        if (E.fast) expand_fast(S, E, K, gtile, lchunk, on_rec);
+        else expand_item(S, E, K, cptr(S.guards), gtile, lchunk, on_rec);
         block_min_max_sum<EXP_WG>(mn, mx, n, red);
         if (n) {
             if (threadIdx.x == 0) atomicAdd(&res[S.res].records, (unsigned long long)n);
@@ -472,11 +529,9 @@ __global__ void __launch_bounds__(SCAN_WG) k_scan_down(const uint32_t *__restric
 __global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32_t nsub, uint32_t nitems,
                                                      unsigned long long *__restrict__ rec,
                                                      uint32_t *__restrict__ cursor) {
-    __shared__ unsigned long long stage[TILE];
     __shared__ uint32_t h[BINCAP];
-    __shared__ uint32_t dl[BINCAP];
+    __shared__ uint32_t gb[BINCAP];
     __shared__ uint32_t red[3 * (EXP_WG / 64)];
-    constexpr int PER = BINCAP / EXP_WG;
     CSub *subs = cptr(subs_g);
     uint32_t w0, w1;
     my_items(nitems, w0, w1);
@@ -494,17 +549,24 @@ __global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32
         unsigned long long r[RPL];
         uint32_t bk[RPL];
         uint32_t mn = 0xFFFFFFFFu, mx = 0, n = 0;
-        expand_item(S, E, K, cptr(S.guards), gtile, lchunk, [&](int s, bool ok, bool inb, uint32_t loc, uint32_t id) {
-            const uint32_t rel = loc - S.klo;
+        const uint32_t klo = S.klo, sh = S.s;
+        auto on_rec = [&](int s, bool ok, bool inb, uint32_t loc, uint32_t id) {
+            const uint32_t rel = loc - klo;
             const bool v = ok && inb && rel < span;
-            const uint32_t b = rel >> S.s;
+            const uint32_t b = rel >> sh;
             bk[s] = v ? b : 0xFFFFFFFFu;
             r[s] = ((unsigned long long)((loc << 1) | rwbit) << 32) | id;
             if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
-        });
+        };
+        if (E.fast) expand_fast(S, E, K, gtile, lchunk, on_rec);
+        else expand_item(S, E, K, cptr(S.guards), gtile, lchunk, on_rec);
         block_min_max_sum<EXP_WG>(mn, mx, n, red);
         uint32_t *gcur = cursor + S.bucket_begin;
         if (n && mx - mn < (uint32_t)BINCAP) {
+            // Rank every record inside its bucket for this tile, reserve one run
+            // per bucket in the chunk, write each record to run base + rank.
+            // Waves whose records share a bucket get consecutive ranks, so the
+            // stores of a wave slot are one contiguous 512-byte run.
             const uint32_t R = mx - mn + 1;
             for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
             __syncthreads();
@@ -512,36 +574,14 @@ __global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32
 #pragma unroll
             for (int s = 0; s < RPL; s++) rk[s] = lds_rank(h, bk[s] - mn, bk[s] != 0xFFFFFFFFu);
             __syncthreads();
-            // exclusive scan of the tile histogram; thread t owns bins [t*PER, t*PER + PER)
-            const uint32_t b0 = threadIdx.x * PER;
-            uint32_t hv[PER];
-            uint32_t sum = 0;
-#pragma unroll
-            for (int i = 0; i < PER; i++) {
-                hv[i] = (b0 + i < R) ? h[b0 + i] : 0u;
-                sum += hv[i];
-            }
-            uint32_t total;
-            uint32_t run = block_excl_add<EXP_WG>(sum, red, &total);
-#pragma unroll
-            for (int i = 0; i < PER; i++) {
-                if (hv[i]) {
-                    h[b0 + i] = run;
-                    // reserve this bucket's run in the chunk: one atomic per bucket and tile
-                    dl[b0 + i] = atomicAdd(&gcur[mn + b0 + i], hv[i]) - run;
-                }
-                run += hv[i];
+            for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) {
+                const uint32_t c = h[i];
+                if (c) gb[i] = atomicAdd(&gcur[mn + i], c);
             }
             __syncthreads();
 #pragma unroll
             for (int s = 0; s < RPL; s++)
-                if (bk[s] != 0xFFFFFFFFu) stage[h[bk[s] - mn] + rk[s]] = r[s];
-            __syncthreads();
-            for (uint32_t p = threadIdx.x; p < total; p += EXP_WG) {
-                const unsigned long long v = stage[p];
-                const uint32_t b = (((uint32_t)(v >> 33) - S.klo) >> S.s) - mn;
-                rec[dl[b] + p] = v;
-            }
+                if (bk[s] != 0xFFFFFFFFu) rec[gb[bk[s] - mn] + rk[s]] = r[s];
             __syncthreads();
         } else if (n) {
             // a tile spread over more than BINCAP buckets: reserve per record
@@ -627,13 +667,35 @@ __device__ __forceinline__ void fold(uint32_t *t_mn, uint32_t *t_mx, uint32_t *t
     atomicMax(&t_mxw1[k], s.mxw1);
 }
 
+// Conflict test and canonical witness of one location's summary.
+__device__ __forceinline__ bool judge(const Seg &s, Magic mgM, uint32_t &second, uint32_t &srw) {
+    if (s.mxw1 == 0u || s.mn == s.mx) return false;          // no write, or one record
+    const uint32_t th_mn = udiv(s.mn, mgM), th_mx = udiv(s.mx, mgM);
+    if (th_mn == th_mx) return false;                         // one thread
+    const uint32_t th_w = udiv(s.mnw, mgM);
+    if (th_mn != th_w) { second = s.mn; srw = (s.mn == s.mnw) ? 1u : 0u; }
+    else { second = s.mx; srw = (s.mx + 1 == s.mxw1) ? 1u : 0u; }
+    return true;
+}
+
+__device__ __forceinline__ void put_witness(uint32_t *wout, uint32_t pos, uint32_t loc, const Seg &s,
+                                            uint32_t second, uint32_t srw) {
+    uint32_t *w = wout + 4 * (size_t)pos;    // the region start is 8-byte aligned: store words
+    w[0] = loc; w[1] = s.mnw; w[2] = second; w[3] = srw;
+}
+
+// Sorted slice in LDS: element p (sorted position) lives at padded slot
+// (p / rpl) * stride + p % rpl, so that lane t's run [t*rpl, t*rpl + rpl)
+// starts at t*stride with an odd stride: the lanes of a wave then read
+// different banks.  Each slot holds (local key | rw << 15) << 32 | id.
+constexpr int SRT_SLOTS = CAP + BKT_WG;
+
 __global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *subs_g, uint32_t nsub, uint32_t nbuckets,
                                                     unsigned long long *__restrict__ rec,
                                                     const uint32_t *__restrict__ starts,
                                                     const uint32_t *__restrict__ counts,
                                                     uint32_t *__restrict__ conf, int debug_sorted) {
-    __shared__ uint32_t sid[CAP];
-    __shared__ uint16_t sk[CAP];
+    __shared__ unsigned long long srt[SRT_SLOTS];
     __shared__ uint32_t bins[TBL];
     __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
     __shared__ Seg wtot[BKT_WG / 64];
@@ -641,7 +703,6 @@ __global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *subs_g, uint32_
     CSub *subs = cptr(subs_g);
     const uint32_t t = threadIdx.x;
     const uint32_t wid = t >> 6;
-    const Seg ident{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
 
     for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
         const uint32_t cnt = counts[b];
@@ -655,76 +716,105 @@ __global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *subs_g, uint32_
             if (subs[mid].bucket_begin <= b) lo_s = mid; else hi_s = mid;
         }
         CSub &S = subs[lo_s];
+        const Magic mgM = ldm(S.mgM);
+        const uint32_t nbins = 1u << S.s;
         const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
-        const uint32_t width = min(1u << S.s, S.khi - lo);
+        const uint32_t width = min(nbins, S.khi - lo);
         const uint32_t start = starts[b];
+        const bool single = cnt <= (uint32_t)CAP;
+        if (!single) {
 #pragma unroll
-        for (int i = 0; i < TPER; i++) {
-            const uint32_t k = t * TPER + i;
-            t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+            for (int i = 0; i < TPER; i++) {
+                const uint32_t k = t * TPER + i;
+                t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+            }
         }
+        uint32_t nconf = 0;      // conflicts this thread finalized (single-slice path)
         for (uint32_t slice = 0; slice < cnt; slice += CAP) {
             const uint32_t n = min((uint32_t)CAP, cnt - slice);
-            const unsigned long long *src = rec + start + slice;
-            // keep 32-bit ids and 16-bit keys (local key | rw << 15) in registers
-            uint32_t id[BKT_RPL], kw[BKT_RPL];
+            const uint32_t rpl = (n + BKT_WG - 1) / BKT_WG;           // records per lane, 1..BKT_RPL
+            const uint32_t stride = rpl | 1u;
+            const uint32_t rdiv = ((1u << 20) + rpl - 1) / rpl;          // p / rpl == (p * rdiv) >> 20 for p < 2^12
+            const uint32_t r0 = t * rpl;
+            const uint32_t m = r0 < n ? min(rpl, n - r0) : 0u;          // this lane's records
+            const unsigned long long *src = rec + start + slice + r0;
+            // --- load a contiguous run per lane: ids and keys (local key | rw << 15)
+            uint32_t kw[BKT_RPL], id[BKT_RPL];
 #pragma unroll
             for (int i = 0; i < BKT_RPL; i++) {
-                const uint32_t j = (uint32_t)i * BKT_WG + t;
-                const unsigned long long x = j < n ? src[j] : 0ull;
+                const unsigned long long x = (uint32_t)i < m ? src[i] : 0ull;
                 const uint32_t hi = (uint32_t)(x >> 32);
                 id[i] = (uint32_t)x;
-                kw[i] = j < n ? (((hi >> 1) - lo) | ((hi & 1u) << 15)) : 0u;
+                kw[i] = ((hi >> 1) - lo) | ((hi & 1u) << 15);
             }
-#pragma unroll
-            for (int i = 0; i < TPER; i++) bins[t * TPER + i] = 0;
+            for (uint32_t k = t; k < nbins; k += BKT_WG) bins[k] = 0;
             __syncthreads();
-            // --- LDS radix sort: one digit of `s` bits (the bucket's local key)
+            // --- LDS radix sort, one counting-sort digit of `s` bits.  Each
+            // record takes its rank with one LDS atomic; lanes hold
+            // contiguous runs, so the lanes of one atomic rarely share a key.
             uint32_t off[BKT_RPL];
 #pragma unroll
-            for (int i = 0; i < BKT_RPL; i++) {
-                const bool v = (uint32_t)i * BKT_WG + t < n;
-                off[i] = wlms_rank(bins, kw[i] & 0x7FFFu, v, S.s);
-            }
+            for (int i = 0; i < BKT_RPL; i++)
+                off[i] = (uint32_t)i < m ? atomicAdd(&bins[kw[i] & 0x7FFFu], 1u) : 0u;
             __syncthreads();
             {
                 uint32_t hv[TPER], sum = 0, tot;
 #pragma unroll
-                for (int i = 0; i < TPER; i++) { hv[i] = bins[t * TPER + i]; sum += hv[i]; }
+                for (int i = 0; i < TPER; i++) {
+                    const uint32_t k = t * TPER + i;
+                    hv[i] = k < nbins ? bins[k] : 0u;
+                    sum += hv[i];
+                }
                 uint32_t run = block_excl_add<BKT_WG>(sum, red, &tot);
 #pragma unroll
-                for (int i = 0; i < TPER; i++) { bins[t * TPER + i] = run; run += hv[i]; }
+                for (int i = 0; i < TPER; i++) {
+                    const uint32_t k = t * TPER + i;
+                    if (k < nbins) bins[k] = run;
+                    run += hv[i];
+                }
             }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < BKT_RPL; i++) {
-                if ((uint32_t)i * BKT_WG + t < n) {
-                    const uint32_t pos = bins[kw[i] & 0x7FFFu] + off[i];
-                    sid[pos] = id[i];
-                    sk[pos] = (uint16_t)kw[i];
+                if ((uint32_t)i < m) {
+                    const uint32_t p = bins[kw[i] & 0x7FFFu] + off[i];
+                    const uint32_t q = (p * rdiv) >> 20;
+                    srt[q * stride + (p - q * rpl)] = ((unsigned long long)kw[i] << 32) | id[i];
                 }
             }
             __syncthreads();
             if (debug_sorted) {
                 for (uint32_t j = t; j < n; j += BKT_WG) {
-                    const uint32_t key = sk[j];
+                    const uint32_t q = (j * rdiv) >> 20;
+                    const unsigned long long x = srt[q * stride + (j - q * rpl)];
+                    const uint32_t key = (uint32_t)(x >> 32);
                     const uint32_t hi = ((lo + (key & 0x7FFFu)) << 1) | (key >> 15);
-                    rec[start + slice + j] = ((unsigned long long)hi << 32) | sid[j];
+                    rec[start + slice + j] = ((unsigned long long)hi << 32) | (uint32_t)x;
                 }
             }
-            // --- segmented scan over runs of equal key (thread-serial runs, DPP across lanes)
-            const uint32_t r0 = t * BKT_RPL;
-            const uint32_t r1 = min(r0 + BKT_RPL, n);
-            Seg a = ident;
-            uint32_t prevk = r0 > 0 && r0 < n ? (sk[r0 - 1] & 0x7FFFu) : 0xFFFFu;
-            for (uint32_t j = r0; j < r1; j++) {
-                const uint32_t key = sk[j];
-                const uint32_t k = key & 0x7FFFu;
-                if (k != prevk) {   // segment head
-                    a.f = 1; a.mn = 0xFFFFFFFFu; a.mx = 0; a.mnw = 0xFFFFFFFFu; a.mxw1 = 0;
+            // --- segmented scan over this lane's sorted run (same positions r0 .. r0 + m)
+            uint32_t kv[BKT_RPL], iv[BKT_RPL];
+            const unsigned long long *mine = srt + t * stride;
+#pragma unroll
+            for (int i = 0; i < BKT_RPL; i++) {
+                const unsigned long long x = (uint32_t)i < m ? mine[i] : 0ull;
+                kv[i] = (uint32_t)(x >> 32);
+                iv[i] = (uint32_t)x;
+            }
+            const uint32_t prevk = (t > 0 && m) ? ((uint32_t)(srt[(t - 1) * stride + rpl - 1] >> 32) & 0x7FFFu) : 0xFFFFu;
+            const uint32_t nextk = (m && r0 + m < n) ? ((uint32_t)(srt[(t + 1) * stride] >> 32) & 0x7FFFu) : 0xFFFFu;
+            Seg a{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+            {
+                uint32_t pk = prevk;
+#pragma unroll
+                for (int j = 0; j < BKT_RPL; j++) {
+                    if ((uint32_t)j < m) {
+                        const uint32_t k = kv[j] & 0x7FFFu;
+                        if (k != pk) { a.f = 1; a.mn = 0xFFFFFFFFu; a.mx = 0; a.mnw = 0xFFFFFFFFu; a.mxw1 = 0; }
+                        seg_add(a, iv[j], kv[j] >> 15);
+                        pk = k;
+                    }
                 }
-                seg_add(a, sid[j], key >> 15);
-                prevk = k;
             }
             Seg inc = a;
             seg_dpp_step<ROW_SHR1, 0xf>(inc);
@@ -737,73 +827,89 @@ __global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *subs_g, uint32_
             Seg carry = shfl_up1(inc);
             __syncthreads();
             {
-                Seg wc = ident;
+                Seg wc{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
                 for (uint32_t w = 0; w < wid; w++) seg_combine(wc, wtot[w]);
                 seg_combine(wc, carry);
                 carry = wc;
             }
-            // finalize the segments that end inside this run
-            if (r0 < r1) {
-                const uint32_t k0 = sk[r0] & 0x7FFFu;
-                const bool head0 = (r0 == 0) || ((sk[r0 - 1] & 0x7FFFu) != k0);
+            // Walk the run and finalize the segments that end inside it.
+            // pass 0: count (single slice) or fold (several slices); pass 1: write witnesses.
+            auto walk = [&](int pass, uint32_t pos) {
                 Seg cur;
+                const bool head0 = m && ((kv[0] & 0x7FFFu) != prevk);
                 cur.f = 0;
                 cur.mn = head0 ? 0xFFFFFFFFu : carry.mn;
                 cur.mx = head0 ? 0u : carry.mx;
                 cur.mnw = head0 ? 0xFFFFFFFFu : carry.mnw;
                 cur.mxw1 = head0 ? 0u : carry.mxw1;
-                uint32_t pk = k0;
-                for (uint32_t j = r0; j < r1; j++) {
-                    const uint32_t key = sk[j];
-                    const uint32_t k = key & 0x7FFFu;
-                    if (j != r0 && k != pk) {
-                        fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
-                        cur.mn = 0xFFFFFFFFu; cur.mx = 0; cur.mnw = 0xFFFFFFFFu; cur.mxw1 = 0;
+                uint32_t pk = m ? (kv[0] & 0x7FFFu) : 0u;
+                uint32_t *wout = reinterpret_cast<uint32_t *>(rec + start);
+#pragma unroll
+                for (int j = 0; j < BKT_RPL; j++) {
+                    if ((uint32_t)j < m) {
+                        const uint32_t k = kv[j] & 0x7FFFu;
+                        if (j != 0 && k != pk) {
+                            if (!single) {
+                                fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
+                            } else {
+                                uint32_t sec = 0, srw = 0;
+                                if (judge(cur, mgM, sec, srw)) {
+                                    if (pass) put_witness(wout, pos++, lo + pk, cur, sec, srw);
+                                    else nconf++;
+                                }
+                            }
+                            cur.mn = 0xFFFFFFFFu; cur.mx = 0; cur.mnw = 0xFFFFFFFFu; cur.mxw1 = 0;
+                        }
+                        seg_add(cur, iv[j], kv[j] >> 15);
+                        pk = k;
                     }
-                    seg_add(cur, sid[j], key >> 15);
-                    pk = k;
                 }
-                if ((r1 == n) || ((sk[r1] & 0x7FFFu) != pk)) fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
+                if (m && nextk != pk) {   // the last segment ends here too
+                    if (!single) {
+                        fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
+                    } else {
+                        uint32_t sec = 0, srw = 0;
+                        if (judge(cur, mgM, sec, srw)) {
+                            if (pass) put_witness(wout, pos++, lo + pk, cur, sec, srw);
+                            else nconf++;
+                        }
+                    }
+                }
+            };
+            walk(0, 0);
+            if (single) {
+                uint32_t total;
+                const uint32_t pos = block_excl_add<BKT_WG>(nconf, red, &total);
+                if (total && !debug_sorted) walk(1, pos);
+                if (t == 0) conf[b] = total;
             }
             __syncthreads();
         }
+        if (single) continue;
 
-        // --- flag conflicting locations, in key order (thread t owns keys t*TPER ..)
+        // --- several slices: flag the folded locations, in key order
         bool c[TPER];
-        uint32_t mnw[TPER], second[TPER], srw[TPER];
+        Seg e[TPER];
+        uint32_t second[TPER], srw[TPER];
         uint32_t nc = 0;
 #pragma unroll
         for (int i = 0; i < TPER; i++) {
             const uint32_t k = t * TPER + i;
-            c[i] = false; mnw[i] = 0; second[i] = 0; srw[i] = 0;
+            c[i] = false; second[i] = 0; srw[i] = 0;
+            e[i] = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
             if (k < width) {
-                const uint32_t mn = t_mn[k], mxw1 = t_mxw1[k];
-                if (mn != 0xFFFFFFFFu && mxw1 != 0u) {
-                    const uint32_t mx = t_mx[k];
-                    mnw[i] = t_mnw[k];
-                    const uint32_t th_mn = udiv(mn, ldm(S.mgM)), th_mx = udiv(mx, ldm(S.mgM));
-                    if (th_mn != th_mx) {
-                        c[i] = true;
-                        const uint32_t th_w = udiv(mnw[i], ldm(S.mgM));
-                        if (th_mn != th_w) { second[i] = mn; srw[i] = (mn == mnw[i]) ? 1u : 0u; }
-                        else { second[i] = mx; srw[i] = (mx + 1 == mxw1) ? 1u : 0u; }
-                    }
-                }
+                e[i].mn = t_mn[k]; e[i].mx = t_mx[k]; e[i].mnw = t_mnw[k]; e[i].mxw1 = t_mxw1[k];
+                if (e[i].mn != 0xFFFFFFFFu) c[i] = judge(e[i], mgM, second[i], srw[i]);
             }
             nc += c[i] ? 1u : 0u;
         }
         uint32_t total;
         uint32_t pos = block_excl_add<BKT_WG>(nc, red, &total);
-        if (!debug_sorted) {   // the region start is 8-byte aligned: store words
+        if (!debug_sorted) {
             uint32_t *wout = reinterpret_cast<uint32_t *>(rec + start);
 #pragma unroll
-            for (int i = 0; i < TPER; i++) {
-                if (c[i]) {
-                    uint32_t *w = wout + 4 * (size_t)pos;
-                    w[0] = lo + t * TPER + i; w[1] = mnw[i]; w[2] = second[i]; w[3] = srw[i];
-                    pos++;
-                }
-            }
+            for (int i = 0; i < TPER; i++)
+                if (c[i]) put_witness(wout, pos++, lo + t * TPER + i, e[i], second[i], srw[i]);
         }
         if (t == 0) conf[b] = total;
     }

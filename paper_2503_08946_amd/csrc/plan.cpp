@@ -247,6 +247,21 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                     if (!ok || row_bound(row, vmax) > LIM) { msg = fmt("access %lld: guard may leave int32", a); return RV_ERR_RANGE; }
                     k.guard_rows.insert(k.guard_rows.end(), row, row + NC);
                 }
+                // fast path: no aux terms, no guards, per-thread coefficients within 24 bits
+                E.ndim = (uint32_t)ar.ndim;
+                bool fast = E.aux_kind[0] == RV_AUX_NONE && E.aux_kind[1] == RV_AUX_NONE && E.guard_count == 0;
+                for (int j = 0; j < ar.ndim && fast; j++)
+                    for (int v : {C_TX, C_TY, C_BX, C_BY})
+                        if (E.row[j][v] <= -(1 << 23) || E.row[j][v] >= (1 << 23)) fast = false;
+                E.fast = fast ? 1u : 0u;
+                // the flattened location row, modulo 2^32: sum over dims of stride * row
+                uint32_t stride = 1;
+                for (int v = 0; v < NC; v++) E.fr[v] = 0;
+                for (int j = ar.ndim - 1; j >= 0; j--) {
+                    for (int v = 0; v < NC; v++) E.fr[v] += stride * (uint32_t)E.row[j][v];
+                    stride *= (uint32_t)ar.dim[j];
+                }
+                E.fr[C_C0] += E.loc_base;
                 // work items: lch loop points x gt threads per lane
                 if (E.box > 0) {
                     E.lch = std::min<uint32_t>(E.box, RPL);

@@ -80,6 +80,12 @@ struct DevEntry {
     uint32_t lch;              // loop points per lane per work item
     uint32_t gt;               // threads per lane per work item
     uint32_t n_lchunks;        // work items along the loop box
+    // Fast path (no aux terms, no guards, |tx..by coefficients| < 2^23): the
+    // location as one affine row modulo 2^32, loc = fr . (tx,ty,bx,by,l0,l1,l2) +
+    // fr[C_C0] + block * loc_mul; exact for every in-bounds record.
+    uint32_t fast;
+    uint32_t ndim;
+    uint32_t fr[NC];
 };
 
 struct DevKernel {

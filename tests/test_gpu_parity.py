@@ -109,7 +109,8 @@ def test_expansion_record_multiset(ctx, desc):
 
 
 @pytest.mark.parametrize("desc", [K.tiny_fixed(), K.tree_reduction(4, block=512, grid=3),
-                                  K.tiled_matmul(grid=2, k_iters=2), K.half_index_global(block=256, grid=8)],
+                                  K.tiled_matmul(grid=2, k_iters=2), K.half_index_global(block=256, grid=8),
+                                  K.polynomial_product(64)],
                          ids=lambda d: d.name)
 def test_sort_output_is_sorted_permutation(ctx, desc):
     k = ctx.load(desc)
