@@ -13,6 +13,13 @@ Workloads (synthetic, seeded descriptions from ``workloads``):
   matmul64   the same pattern at gridDim (64,64): 18,257,805,312 records
   tree       shared-memory tree reduction, blockDim 1024, gridDim 128, 11
              variants checked as one batch (4,321,152 records)
+  batch      4096 random affine 2-D kernels (seed 4, records log-uniform in
+             [1e2, 1e6], 432,085,651 records) checked by one rv_check_batch
+             per step; also times one rv_check per kernel for comparison
+  serve      a server over a 64 GiB budget fed 10,000 random affine jobs
+             (seed 5, records log-uniform in [1e3, 1e7]) at Poisson arrival
+             times, rate 0.7 x the measured closed-loop capacity, after 500
+             warm-up jobs; reports per-job latency p50/p99
 """
 
 from __future__ import annotations
@@ -54,6 +61,22 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def cpu_baseline_kernels(descs, max_seconds):
+    """The oracle on whole kernels of the list, in order, until about
+    max_seconds of CPU time."""
+    import oracle
+    oracle.build(force=False)
+    recs = 0
+    t0 = time.perf_counter()
+    n = 0
+    while n < len(descs) and time.perf_counter() - t0 < max_seconds:
+        recs += oracle.check(descs[n], max_witnesses=1).n_records
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": recs / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
+            "sample": f"kernels 0..{n - 1} of {len(descs)} ({recs} records, {dt:.1f} s, single thread)"}
+
+
 def cpu_baseline(desc, max_seconds):
     """The oracle (single-threaded C) on the first intervals of the workload,
     adding intervals until about max_seconds of CPU time."""
@@ -88,6 +111,151 @@ def traffic_for(kernel_name, records_per_launch):
         return None
 
 
+def roofline_from(stages, n_records_timed):
+    """Dominant kernel (by GPU time, among those with a byte count) and its
+    algorithmic bandwidth: bytes per record x records per launch / average
+    launch time (HIP events on the stream the kernel runs on)."""
+    dom = max(ALG_BYTES, key=lambda k: stages[k][0])
+    launches = max(1, stages[dom][1])
+    avg_ms = stages[dom][0] / launches
+    recs_per_launch = n_records_timed / launches
+    achieved = ALG_BYTES[dom] * recs_per_launch / (avg_ms * 1e-3) / 1e9
+    kname = {"expand": "k_scatter", "sort_scan": "k_bucket"}[dom]
+    traffic = traffic_for(kname, int(recs_per_launch))
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
+            "alg_bytes_per_record": ALG_BYTES[dom]}
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
+
+
+def bench_batch(args, rv, torch):
+    from workloads import random_affine as RA
+    t0 = time.perf_counter()
+    descs = RA.batch_kernels(seed=4, count=4096)
+    log(f"[bench] generated 4096 kernels in {time.perf_counter() - t0:.1f} s")
+    ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
+    ks = [ctx.load(d) for d in descs]
+    log(f"[bench] loaded 4096 kernels")
+    for i in range(args.warmup):
+        res = ctx.check_batch(ks)
+        log(f"[bench] warmup {i}: records={sum(r.n_records for r in res)}")
+    # per-kernel plain launches, one pass over the batch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [ctx.check(k) for k in ks]
+    t_single = time.perf_counter() - t0
+    n_records = sum(r.n_records for r in single)
+    log(f"[bench] one rv_check per kernel: {t_single * 1e3:.1f} ms for the batch")
+    ctx.timing(reset=True)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        res = ctx.check_batch(ks)
+        lat.append(time.perf_counter() - s0)
+        log(f"[bench] step {i}: {lat[-1] * 1e3:.2f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_timing(False)
+    stages = ctx.timing(reset=True)
+    assert [(r.n_records, r.n_conflicts) for r in res] == [(r.n_records, r.n_conflicts) for r in single]
+    per_step = {k: v[0] / args.steps for k, v in stages.items()}
+    log("[bench] GPU ms per step by stage: " + ", ".join(f"{k}={v:.3f}" for k, v in per_step.items()))
+    value = n_records * args.steps / elapsed
+    out = {
+        "metric": "access records race-checked/sec + % HBM peak; p50/p99 verify latency",
+        "value": value, "unit": "records/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "4096 random affine 2-D kernels, seed 4, records log-uniform in [1e2, 1e6], "
+                               "one batched check per step",
+                   "records": n_records, "kernels": len(ks),
+                   "kernels_with_conflicts": sum(1 for r in res if r.n_conflicts)},
+        "latency_ms": {"p50": round(percentile(lat, 0.5) * 1e3, 3), "p99": round(percentile(lat, 0.99) * 1e3, 3)},
+        "per_kernel_launches": {"ms_per_batch": round(t_single * 1e3, 2), "value": n_records / t_single,
+                                "batched_speedup": round(t_single / (elapsed / args.steps), 2)},
+        "stage_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "roofline": roofline_from(stages, n_records * args.steps),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_kernels(descs, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, rv, torch):
+    import numpy as np
+    from workloads import random_affine as RA
+    n_warm, n_jobs = 500, args.serve_jobs
+    t0 = time.perf_counter()
+    descs = list(RA.serving_stream(seed=5, count=n_warm + n_jobs))
+    log(f"[bench] generated {len(descs)} jobs in {time.perf_counter() - t0:.1f} s")
+    ctx = rv.Context(0, workspace_bytes=1 << 30)
+    ks = [ctx.load(d) for d in descs]
+    log(f"[bench] loaded {len(ks)} jobs")
+    srv = rv.Server(ctx, budget_bytes=int(args.budget_gb * (1 << 30)))
+    # closed-loop capacity: the warm-up jobs submitted at once
+    t0 = time.perf_counter()
+    for k in ks[:n_warm]:
+        srv.submit(k)
+    srv.drain(600000)
+    cap_jobs = n_warm / (time.perf_counter() - t0)
+    warm = srv.poll(cap=n_warm)
+    assert len(warm) == n_warm and all(r.status == 0 for r in warm)
+    rate = args.serve_load * cap_jobs
+    log(f"[bench] closed-loop capacity {cap_jobs:.0f} jobs/s; Poisson rate {rate:.0f} jobs/s")
+    arrivals = RA.poisson_arrivals(seed=5, count=n_jobs, rate_per_s=rate)
+    done = []
+    lag = []
+    t0 = time.perf_counter()
+    for i, k in enumerate(ks[n_warm:]):
+        target = t0 + arrivals[i]
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            if target - now > 2e-4:
+                time.sleep((target - now) * 0.5)
+        lag.append(time.perf_counter() - target)
+        srv.submit(k)
+        if i % 256 == 255:
+            done += srv.poll()
+            log(f"[bench] submitted {i + 1} jobs, {len(done)} done")
+    srv.drain(600000)
+    t_end = time.perf_counter()
+    done += srv.poll(cap=n_jobs)
+    assert len(done) == n_jobs and all(r.status == 0 for r in done)
+    srv.close()
+    lat = np.array([r.latency_ns for r in done], dtype=np.float64) / 1e6
+    queue = np.array([r.t_start_ns - r.t_submit_ns for r in done], dtype=np.float64) / 1e6
+    n_records = sum(r.result.n_records for r in done)
+    elapsed = t_end - t0
+    out = {
+        "metric": "access records race-checked/sec + % HBM peak; p50/p99 verify latency",
+        "value": n_records / elapsed, "unit": "records/s", "n_gpus": 1, "steps": n_jobs, "warmup": n_warm,
+        "ms_per_step": elapsed / n_jobs * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "served check: random affine 2-D jobs, seed 5, records log-uniform in "
+                               f"[1e3, 1e7], Poisson arrivals at {args.serve_load} x closed-loop capacity, "
+                               f"{args.budget_gb:g} GiB budget",
+                   "records": n_records, "jobs": n_jobs},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "queue_p50": round(float(np.percentile(queue, 50)), 3)},
+        "arrival_rate_jobs_per_s": round(rate, 1),
+        "closed_loop_capacity_jobs_per_s": round(cap_jobs, 1),
+        "submit_lag_ms_p99": round(float(np.percentile(lag, 99)) * 1e3, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +265,9 @@ def main():
     ap.add_argument("--workspace-gb", type=float, default=16.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="server budget (serve workload)")
+    ap.add_argument("--serve-jobs", type=int, default=10000)
+    ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / closed-loop capacity")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only copy GIB gibibytes device-to-device (a plain copy kernel of known size, "
                          "to scale the HBM byte counters) and exit")
@@ -121,6 +292,10 @@ def main():
     import torch
     import paper_2503_08946_amd as rv
 
+    if args.workload == "batch":
+        return bench_batch(args, rv, torch)
+    if args.workload == "serve":
+        return bench_serve(args, rv, torch)
     descs, wl_text = make_workload(args.workload)
     log(f"[bench] workload {args.workload}: {wl_text}")
     ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
@@ -151,23 +326,11 @@ def main():
     stages = ctx.timing(reset=True)
     assert sum(r.n_records for r in res) == n_records
     value = n_records * args.steps / elapsed
-    lat.sort()
-    p50 = lat[len(lat) // 2]
-    p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
+    p50 = percentile(lat, 0.5)
+    p99 = percentile(lat, 0.99)
     per_step = {k: v[0] / args.steps for k, v in stages.items()}
     log("[bench] GPU ms per step by stage: " + ", ".join(f"{k}={v:.3f}" for k, v in per_step.items()))
-    # dominant kernel among those with a defined byte count
-    dom = max(ALG_BYTES, key=lambda k: stages[k][0])
-    launches = max(1, stages[dom][1])
-    avg_ms = stages[dom][0] / launches
-    recs_per_launch = n_records * args.steps / launches
-    achieved = ALG_BYTES[dom] * recs_per_launch / (avg_ms * 1e-3) / 1e9
-    kname = {"expand": "k_scatter", "sort_scan": "k_bucket"}[dom]
-    traffic = traffic_for(kname, int(recs_per_launch))
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
-                "alg_bytes_per_record": ALG_BYTES[dom]}
+    roofline = roofline_from(stages, n_records * args.steps)
     out = {
         "metric": "access records race-checked/sec + % HBM peak; p50/p99 verify latency",
         "value": value,

@@ -182,8 +182,20 @@ typedef struct {
     int32_t is_write;
 } rv_record;
 
+/* One finished job of a server.  Times are the host's steady clock in ns:
+ * submission, the launch of the batch that carried the job, and the moment
+ * the server saw that batch's results on the host. */
+typedef struct {
+    uint64_t job_id;
+    int32_t status;        /* as rv_check would return for the kernel */
+    int32_t reserved;
+    rv_result result;      /* valid when status == RV_OK */
+    uint64_t t_submit_ns, t_start_ns, t_done_ns;
+} rv_job_result;
+
 typedef struct rv_ctx rv_ctx;
 typedef struct rv_kernel rv_kernel;
+typedef struct rv_server rv_server;
 
 /* ------------------------------------------------------------- functions */
 
@@ -237,6 +249,34 @@ rv_status rv_debug_records(rv_ctx *ctx, rv_kernel *k, uint32_t interval, int sor
  * reset != 0, clears the accumulators. */
 rv_status rv_set_timing(rv_ctx *ctx, int enable);
 rv_status rv_get_timing(rv_ctx *ctx, rv_timing *out, int reset);
+
+/* ------------------------------------------------------------- serving
+ * A server checks a stream of submitted kernels with continuous batching:
+ * the caller's device memory of `budget_bytes` (>= 128 MiB) is split into
+ * two lanes, each with a HIP stream of its own (default priority); a worker
+ * thread gives every idle lane the waiting jobs in arrival order while their
+ * records fit the lane's half of the budget, and launches them as one
+ * batched check (as rv_check_batch).  Jobs that arrive while both lanes are
+ * busy join the next batch, so one lane's batch runs while the next one is
+ * admitted and launched.  Each job's result is bit-identical to rv_check of
+ * its kernel alone.
+ *
+ * While a server exists its context accepts no rv_check / rv_check_batch /
+ * rv_get_witnesses / rv_debug_records (RV_ERR_STATE), timing is not
+ * collected for server work, and submitted kernels must stay loaded until
+ * their results have been polled.  submit, poll and drain may be called from
+ * any host thread. */
+rv_status rv_server_create(rv_ctx *ctx, void *workspace, size_t budget_bytes, rv_server **out);
+/* Finishes the jobs already submitted, stops the worker and frees the
+ * server's streams and tables (not the workspace). */
+rv_status rv_server_destroy(rv_server *s);
+/* Queue k; non-blocking.  RV_ERR_BUDGET if one of k's passes cannot fit a
+ * lane's half of the budget (such a job would never be admitted). */
+rv_status rv_server_submit(rv_server *s, rv_kernel *k, uint64_t *job_id);
+/* Move up to cap finished jobs (completion order) into out; *n_out = count. */
+rv_status rv_server_poll(rv_server *s, rv_job_result *out, size_t cap, size_t *n_out);
+/* Wait until every submitted job has finished (RV_ERR_STATE on timeout). */
+rv_status rv_server_drain(rv_server *s, uint64_t timeout_ms);
 
 /* Host-side self test of the library's integer helpers (division by
  * invariant integers, key layout); returns RV_OK or RV_ERR_STATE with a

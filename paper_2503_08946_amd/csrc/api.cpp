@@ -1,44 +1,77 @@
 // C ABI of librv (declared in include/rv.h).  Host orchestration only: every
 // step of the check runs in the gfx950 kernels of kernels.hip.
+//
+// Work runs on a "lane": a HIP stream, a workspace (records of one chunk and
+// the per-bucket arrays) and its own result slots and pinned staging.  A
+// context has one lane on the caller's stream and workspace; a server has
+// two lanes on streams of its own, so that one batch runs on the device while
+// the next is being admitted and launched.
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
 #include <random>
+#include <thread>
 
 #include "rv_internal.h"
 
 using namespace rv;
 
+namespace {
+
+struct Lane {
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    WorkspaceLayout L;
+    SubResult *d_res = nullptr;
+    size_t res_cap = 0;
+    DevSub *d_subs = nullptr;
+    size_t subs_cap = 0;
+    void *h_up = nullptr;       // pinned: pass tables going up
+    size_t up_cap = 0;
+    void *h_down = nullptr;     // pinned: results coming down
+    size_t down_cap = 0;
+    hipEvent_t done = nullptr;
+    // the batch in flight
+    std::vector<rv_kernel *> jobs;
+    std::vector<size_t> res0;
+    size_t ns = 0;
+    bool busy = false;
+
+    unsigned long long *rec() const { return reinterpret_cast<unsigned long long *>(ws); }
+    uint32_t *counts() const { return reinterpret_cast<uint32_t *>(ws + L.off_counts); }
+    uint32_t *starts() const { return reinterpret_cast<uint32_t *>(ws + L.off_starts); }
+    uint32_t *cursor() const { return reinterpret_cast<uint32_t *>(ws + L.off_cursor); }
+    uint32_t *conf() const { return reinterpret_cast<uint32_t *>(ws + L.off_conf); }
+    uint32_t *bsum() const { return reinterpret_cast<uint32_t *>(ws + L.off_bsum); }
+};
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
 struct rv_ctx {
     int device = 0;
     unsigned ncu = 256;             // compute units of the device (persistent grids)
-    hipStream_t stream = nullptr;
-    char *ws = nullptr;
     size_t ws_bytes = 0;
-    WorkspaceLayout L;
+    Lane main;
     std::string err;
-    // context-owned device buffers (grown on demand)
-    SubResult *d_res = nullptr;
-    size_t res_cap = 0;
-    DevSub *d_bsubs = nullptr;
-    size_t bsubs_cap = 0;
-    void *h_pin = nullptr;
-    size_t pin_cap = 0;
+    bool serving = false;           // a server owns the device work of this context
     // timing
     bool timing = false;
     struct Ev { int stage; hipEvent_t a, b; };
     std::vector<Ev> pending;
     std::vector<hipEvent_t> pool;
     rv_timing acc{};
-
-    unsigned long long *rec() { return reinterpret_cast<unsigned long long *>(ws); }
-    uint32_t *counts() { return reinterpret_cast<uint32_t *>(ws + L.off_counts); }
-    uint32_t *starts() { return reinterpret_cast<uint32_t *>(ws + L.off_starts); }
-    uint32_t *cursor() { return reinterpret_cast<uint32_t *>(ws + L.off_cursor); }
-    uint32_t *conf() { return reinterpret_cast<uint32_t *>(ws + L.off_conf); }
-    uint32_t *bsum() { return reinterpret_cast<uint32_t *>(ws + L.off_bsum); }
 };
 
 namespace {
@@ -67,13 +100,13 @@ hipEvent_t get_event(rv_ctx *c) {
 }
 
 template <class F>
-void timed(rv_ctx *c, int stage, F &&f) {
-    if (!c->timing) { f(); return; }
+void timed(rv_ctx *c, hipStream_t st, int stage, F &&f) {
+    if (!c->timing || c->serving) { f(); return; }
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) { f(); return; }
-    (void)hipEventRecord(a, c->stream);
+    (void)hipEventRecord(a, st);
     f();
-    (void)hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, st);
     c->pending.push_back({stage, a, b});
 }
 
@@ -91,37 +124,37 @@ rv_status drain_timing(rv_ctx *c) {
     return RV_OK;
 }
 
-rv_status ensure_res(rv_ctx *c, size_t n) {
-    if (n <= c->res_cap) return RV_OK;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (c->d_res) HIP_TRY(c, hipFree(c->d_res));
-    c->d_res = nullptr;
-    size_t cap = std::max<size_t>(n, 2 * c->res_cap);
-    HIP_TRY(c, hipMalloc(&c->d_res, cap * sizeof(SubResult)));
-    c->res_cap = cap;
+template <class T>
+rv_status grow_device(rv_ctx *c, Lane &ln, T *&p, size_t &cap, size_t n) {
+    if (n <= cap) return RV_OK;
+    HIP_TRY(c, hipStreamSynchronize(ln.stream));
+    if (p) HIP_TRY(c, hipFree(p));
+    p = nullptr;
+    const size_t nc = std::max<size_t>(n, 2 * cap);
+    HIP_TRY(c, hipMalloc(reinterpret_cast<void **>(&p), nc * sizeof(T)));
+    cap = nc;
     return RV_OK;
 }
 
-rv_status ensure_bsubs(rv_ctx *c, size_t n) {
-    if (n <= c->bsubs_cap) return RV_OK;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (c->d_bsubs) HIP_TRY(c, hipFree(c->d_bsubs));
-    c->d_bsubs = nullptr;
-    size_t cap = std::max<size_t>(n, 2 * c->bsubs_cap);
-    HIP_TRY(c, hipMalloc(&c->d_bsubs, cap * sizeof(DevSub)));
-    c->bsubs_cap = cap;
+rv_status grow_pinned(rv_ctx *c, Lane &ln, void *&p, size_t &cap, size_t bytes) {
+    if (bytes <= cap) return RV_OK;
+    HIP_TRY(c, hipStreamSynchronize(ln.stream));
+    if (p) HIP_TRY(c, hipHostFree(p));
+    p = nullptr;
+    const size_t nc = std::max<size_t>(bytes, 2 * cap);
+    HIP_TRY(c, hipHostMalloc(&p, nc, hipHostMallocDefault));
+    cap = nc;
     return RV_OK;
 }
 
-rv_status ensure_pin(rv_ctx *c, size_t bytes) {
-    if (bytes <= c->pin_cap) return RV_OK;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (c->h_pin) HIP_TRY(c, hipHostFree(c->h_pin));
-    c->h_pin = nullptr;
-    size_t cap = std::max<size_t>(bytes, 2 * c->pin_cap);
-    HIP_TRY(c, hipHostMalloc(&c->h_pin, cap, hipHostMallocDefault));
-    c->pin_cap = cap;
-    return RV_OK;
+void lane_release(Lane &ln) {
+    if (ln.d_res) (void)hipFree(ln.d_res);
+    if (ln.d_subs) (void)hipFree(ln.d_subs);
+    if (ln.h_up) (void)hipHostFree(ln.h_up);
+    if (ln.h_down) (void)hipHostFree(ln.h_down);
+    if (ln.done) (void)hipEventDestroy(ln.done);
+    ln.d_res = nullptr; ln.d_subs = nullptr; ln.h_up = nullptr; ln.h_down = nullptr; ln.done = nullptr;
+    ln.res_cap = ln.subs_cap = ln.up_cap = ln.down_cap = 0;
 }
 
 rv_status check_launch(rv_ctx *c) {
@@ -131,21 +164,25 @@ rv_status check_launch(rv_ctx *c) {
 }
 
 // count -> scan -> expansion for one chunk
-void run_expand(rv_ctx *c, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
-    timed(c, RV_STAGE_FILL, [&] { launch_fill_u32(c->counts(), buckets, 0u, c->stream); });
-    timed(c, RV_STAGE_COUNT, [&] { launch_hist(subs, nsub, items, c->counts(), c->d_res, c->ncu, c->stream); });
-    timed(c, RV_STAGE_SCAN, [&] { launch_scan(c->counts(), c->starts(), c->cursor(), c->bsum(), buckets, c->stream); });
-    timed(c, RV_STAGE_EXPAND, [&] { launch_scatter(subs, nsub, items, c->rec(), c->cursor(), c->ncu, c->stream); });
+void run_expand(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
+    hipStream_t st = ln.stream;
+    timed(c, st, RV_STAGE_FILL, [&] { launch_fill_u32(ln.counts(), buckets, 0u, st); });
+    timed(c, st, RV_STAGE_COUNT, [&] { launch_hist(subs, nsub, items, ln.counts(), ln.d_res, c->ncu, st); });
+    timed(c, st, RV_STAGE_SCAN,
+          [&] { launch_scan(ln.counts(), ln.starts(), ln.cursor(), ln.bsum(), buckets, st); });
+    timed(c, st, RV_STAGE_EXPAND,
+          [&] { launch_scatter(subs, nsub, items, ln.rec(), ln.cursor(), c->ncu, st); });
 }
 
-void run_check_chunk(rv_ctx *c, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
-    run_expand(c, subs, nsub, items, buckets);
-    timed(c, RV_STAGE_SORT_SCAN, [&] {
-        launch_bucket(subs, nsub, buckets, c->rec(), c->starts(), c->counts(), c->conf(), 0, c->ncu, c->stream);
+void run_check_chunk(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
+    hipStream_t st = ln.stream;
+    run_expand(c, ln, subs, nsub, items, buckets);
+    timed(c, st, RV_STAGE_SORT_SCAN, [&] {
+        launch_bucket(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 0, c->ncu, st);
     });
-    timed(c, RV_STAGE_FINISH, [&] {
-        launch_finish(subs, nsub, buckets, c->conf(), c->d_res, c->stream);
-        launch_first(subs, nsub, c->rec(), c->starts(), c->d_res, c->stream);
+    timed(c, st, RV_STAGE_FINISH, [&] {
+        launch_finish(subs, nsub, buckets, ln.conf(), ln.d_res, st);
+        launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_res, st);
     });
 }
 
@@ -159,7 +196,7 @@ void decode_witness(const rv_kernel &k, uint32_t interval, const uint32_t w[4], 
 }
 
 // Per-kernel result from its passes' slots hr[0 .. k.subs.size()).
-rv_status assemble(rv_ctx *c, const rv_kernel &k, const SubResult *hr, rv_result *out) {
+rv_status assemble(const rv_kernel &k, const SubResult *hr, rv_result *out, std::string &msg) {
     rv_result r;
     memset(&r, 0, sizeof r);
     unsigned long long oob = ~0ull;
@@ -177,7 +214,8 @@ rv_status assemble(rv_ctx *c, const rv_kernel &k, const SubResult *hr, rv_result
         snprintf(buf, sizeof buf,
                  "index out of bounds: interval %u, block %u, thread %u, dynamic phase %u, access %u, loop (%d,%d,%d)",
                  iv, s.block, s.tid, s.dyn_phase, s.access, s.loop[0], s.loop[1], s.loop[2]);
-        return fail(c, RV_ERR_OOB, buf);
+        msg = buf;
+        return RV_ERR_OOB;
     }
     for (size_t i = 0; i < k.subs.size(); i++) {
         if (hr[i].conflicts) {
@@ -188,6 +226,212 @@ rv_status assemble(rv_ctx *c, const rv_kernel &k, const SubResult *hr, rv_result
     }
     *out = r;
     return RV_OK;
+}
+
+// Records a job of k may need on a lane (its largest pass and bucket count).
+bool fits(const rv_kernel &k, const WorkspaceLayout &L) {
+    for (const auto &sp : k.subs)
+        if (k.intervals[sp.interval].P > L.cap_records || sp.nb > L.cap_buckets) return false;
+    return true;
+}
+
+// Launch the check of ks[0..n) on a lane, asynchronously; results come down
+// into pinned memory and `ln.done` is recorded after them.
+rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
+    ln.jobs.assign(ks, ks + n);
+    ln.res0.assign(n + 1, 0);
+    for (size_t j = 0; j < n; j++) ln.res0[j + 1] = ln.res0[j] + ks[j]->subs.size();
+    const size_t ns = ln.res0[n];
+    ln.ns = ns;
+    rv_status st = grow_device(c, ln, ln.d_res, ln.res_cap, std::max<size_t>(ns, 1));
+    if (st) return st;
+    st = grow_pinned(c, ln, ln.h_down, ln.down_cap, std::max<size_t>(ns, 1) * sizeof(SubResult));
+    if (st) return st;
+    hipStream_t s = ln.stream;
+    // A single kernel planned for this workspace uses its resident pass table.
+    const bool resident = n == 1 && ks[0]->plan_cap_records == ln.L.cap_records &&
+                          ks[0]->plan_cap_buckets == ln.L.cap_buckets;
+    timed(c, s, RV_STAGE_FILL, [&] { launch_init_results(ln.d_res, ns, s); });
+    if (resident) {
+        const rv_kernel *k = ks[0];
+        for (auto &ch : k->chunks)
+            run_check_chunk(c, ln, k->d_subs + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets);
+    } else {
+        // passes in (kernel, pass) order, greedy chunks by capacity
+        struct Chunk { size_t sub_begin, sub_end; uint64_t items, buckets; };
+        std::vector<Chunk> chunks;
+        std::vector<DevSub> table;
+        table.reserve(ns);
+        Chunk cur{0, 0, 0, 0};
+        uint64_t rec_bound = 0;
+        for (size_t j = 0; j < n; j++) {
+            const rv_kernel &k = *ks[j];
+            for (uint32_t i = 0; i < k.subs.size(); i++) {
+                const IntervalPlan &I = k.intervals[k.subs[i].interval];
+                const uint32_t nb = k.subs[i].nb;
+                if (cur.sub_end > cur.sub_begin &&
+                    (rec_bound + I.P > ln.L.cap_records || cur.buckets + nb > ln.L.cap_buckets ||
+                     cur.items + I.items >= (1ull << 31))) {
+                    chunks.push_back(cur);
+                    cur = Chunk{table.size(), table.size(), 0, 0};
+                    rec_bound = 0;
+                }
+                make_devsubs(k, i, i + 1, (uint32_t)(ln.res0[j] + i), table, cur.items, cur.buckets);
+                cur.sub_end = table.size();
+                rec_bound += I.P;
+            }
+        }
+        if (cur.sub_end > cur.sub_begin) chunks.push_back(cur);
+        st = grow_device(c, ln, ln.d_subs, ln.subs_cap, std::max<size_t>(table.size(), 1));
+        if (st) return st;
+        st = grow_pinned(c, ln, ln.h_up, ln.up_cap, std::max<size_t>(table.size(), 1) * sizeof(DevSub));
+        if (st) return st;
+        if (!table.empty()) {
+            memcpy(ln.h_up, table.data(), table.size() * sizeof(DevSub));
+            HIP_TRY(c, hipMemcpyAsync(ln.d_subs, ln.h_up, table.size() * sizeof(DevSub), hipMemcpyHostToDevice, s));
+        }
+        for (auto &ch : chunks)
+            run_check_chunk(c, ln, ln.d_subs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items,
+                            ch.buckets);
+    }
+    if ((st = check_launch(c))) return st;
+    if (ns) HIP_TRY(c, hipMemcpyAsync(ln.h_down, ln.d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, s));
+    if (!ln.done) HIP_TRY(c, hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
+    HIP_TRY(c, hipEventRecord(ln.done, s));
+    ln.busy = true;
+    return RV_OK;
+}
+
+// Wait for the lane's batch and assemble per-kernel results.  status[j]
+// (optional) receives each kernel's code; the return value is the first
+// error (with its message in c->err).
+rv_status lane_collect(rv_ctx *c, Lane &ln, rv_result *out, rv_status *status, std::string *msgs = nullptr) {
+    HIP_TRY(c, hipEventSynchronize(ln.done));
+    ln.busy = false;
+    const SubResult *hr = reinterpret_cast<const SubResult *>(ln.h_down);
+    rv_status first = RV_OK;
+    for (size_t j = 0; j < ln.jobs.size(); j++) {
+        std::string m;
+        rv_status st = assemble(*ln.jobs[j], hr + ln.res0[j], &out[j], m);
+        if (status) status[j] = st;
+        if (msgs) msgs[j] = m;
+        if (st && first == RV_OK) {
+            first = st;
+            c->err = ln.jobs.size() > 1 ? "kernel " + std::to_string(j) + ": " + m : m;
+        }
+    }
+    return first;
+}
+
+}  // namespace
+
+// ================================================================ server
+struct rv_server {
+    rv_ctx *c = nullptr;
+    size_t budget = 0;
+    Lane lanes[2];
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv;
+    struct Job { uint64_t id; rv_kernel *k; uint64_t t_submit; };
+    std::deque<Job> pending;
+    std::vector<rv_job_result> done;
+    size_t in_flight = 0;           // submitted and not yet completed
+    std::vector<uint64_t> lane_ids[2], lane_submit[2];
+    uint64_t lane_start[2] = {0, 0};
+    uint64_t next_id = 1;
+    bool stop = false;
+    std::string err;
+};
+
+namespace {
+
+void server_loop(rv_server *s) {
+    rv_ctx *c = s->c;
+    (void)hipSetDevice(c->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        bool progressed = false;
+        // completions
+        for (int l = 0; l < 2; l++) {
+            Lane &ln = s->lanes[l];
+            if (!ln.busy || hipEventQuery(ln.done) != hipSuccess) continue;
+            lk.unlock();
+            const size_t n = ln.jobs.size();
+            std::vector<rv_result> res(n);
+            std::vector<rv_status> st(n);
+            lane_collect(c, ln, res.data(), st.data());
+            const uint64_t t = now_ns();
+            lk.lock();
+            for (size_t j = 0; j < n; j++) {
+                rv_job_result r;
+                memset(&r, 0, sizeof r);
+                r.job_id = s->lane_ids[l][j];
+                r.status = st[j];
+                r.result = res[j];
+                r.t_submit_ns = s->lane_submit[l][j];
+                r.t_start_ns = s->lane_start[l];
+                r.t_done_ns = t;
+                s->done.push_back(r);
+            }
+            s->in_flight -= n;
+            progressed = true;
+            s->cv.notify_all();
+        }
+        // admission: a free lane takes the waiting jobs, first come first
+        // served, while their records fit its share of the budget
+        for (int l = 0; l < 2 && !s->pending.empty(); l++) {
+            Lane &ln = s->lanes[l];
+            if (ln.busy) continue;
+            std::vector<rv_kernel *> ks;
+            s->lane_ids[l].clear();
+            s->lane_submit[l].clear();
+            uint64_t recs = 0, buckets = 0;
+            while (!s->pending.empty()) {
+                const auto &jb = s->pending.front();
+                uint64_t r = 0, b = 0;
+                for (auto &sp : jb.k->subs) { r += jb.k->intervals[sp.interval].P; b += sp.nb; }
+                if (!ks.empty() && (recs + r > ln.L.cap_records || buckets + b > ln.L.cap_buckets)) break;
+                recs += r;
+                buckets += b;
+                ks.push_back(jb.k);
+                s->lane_ids[l].push_back(jb.id);
+                s->lane_submit[l].push_back(jb.t_submit);
+                s->pending.pop_front();
+            }
+            s->lane_start[l] = now_ns();
+            lk.unlock();
+            rv_status st = lane_enqueue(c, ln, ks.data(), ks.size());
+            lk.lock();
+            if (st) {   // device error: fail the batch
+                const uint64_t t = now_ns();
+                for (size_t j = 0; j < ks.size(); j++) {
+                    rv_job_result r;
+                    memset(&r, 0, sizeof r);
+                    r.job_id = s->lane_ids[l][j];
+                    r.status = st;
+                    r.t_submit_ns = s->lane_submit[l][j];
+                    r.t_start_ns = s->lane_start[l];
+                    r.t_done_ns = t;
+                    s->done.push_back(r);
+                }
+                s->in_flight -= ks.size();
+                ln.busy = false;
+                s->cv.notify_all();
+            }
+            progressed = true;
+        }
+        if (s->stop && s->pending.empty() && !s->lanes[0].busy && !s->lanes[1].busy) break;
+        if (!progressed) {
+            if (s->lanes[0].busy || s->lanes[1].busy) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            } else {
+                s->cv.wait_for(lk, std::chrono::milliseconds(5));
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -218,11 +462,11 @@ rv_status rv_ctx_create(rv_ctx **out, int device, void *hip_stream, void *worksp
     rv_ctx *c = new (std::nothrow) rv_ctx;
     if (!c) return RV_ERR_TOO_LARGE;
     c->device = device;
-    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    c->ws = reinterpret_cast<char *>(workspace);
     c->ws_bytes = workspace_bytes;
-    c->L = layout_workspace(workspace_bytes);
-    if (!c->L.cap_records) { delete c; return RV_ERR_TOO_LARGE; }
+    c->main.stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->main.ws = reinterpret_cast<char *>(workspace);
+    c->main.L = layout_workspace(workspace_bytes);
+    if (!c->main.L.cap_records) { delete c; return RV_ERR_TOO_LARGE; }
     if (hipSetDevice(device) != hipSuccess) { delete c; return RV_ERR_DEVICE; }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
@@ -233,13 +477,12 @@ rv_status rv_ctx_create(rv_ctx **out, int device, void *hip_stream, void *worksp
 
 rv_status rv_ctx_destroy(rv_ctx *c) {
     if (!c) return RV_ERR_INVALID;
+    if (c->serving) return fail(c, RV_ERR_STATE, "destroy the server first");
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->main.stream);
     for (auto &e : c->pending) { c->pool.push_back(e.a); c->pool.push_back(e.b); }
     for (auto e : c->pool) (void)hipEventDestroy(e);
-    if (c->d_res) (void)hipFree(c->d_res);
-    if (c->d_bsubs) (void)hipFree(c->d_bsubs);
-    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    lane_release(c->main);
     delete c;
     return RV_OK;
 }
@@ -255,12 +498,14 @@ rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel *
     rv_status st;
     try {
         st = plan_kernel(desc, DEFAULT_TARGET, *k, m);
-        if (!st) st = plan_chunks(*k, c->L, m);
+        if (!st) st = plan_chunks(*k, c->main.L, m);
     } catch (const std::bad_alloc &) {
         st = RV_ERR_TOO_LARGE;
         m = "out of host memory";
     }
     if (st) { delete k; return fail(c, st, m); }
+    k->plan_cap_records = c->main.L.cap_records;
+    k->plan_cap_buckets = c->main.L.cap_buckets;
     HIP_TRY(c, hipSetDevice(c->device));
     // one device block: kernel constants, entries, guard rows, entry prefixes, passes
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -281,7 +526,8 @@ rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel *
     k->h_subs.clear();
     for (auto &ch : k->chunks) {
         uint64_t items = 0, buckets = 0;
-        make_devsubs(*k, ch.sub_begin, ch.sub_end, ch.sub_begin, k->h_subs, items, buckets);
+        make_devsubs(*k, ch.sub_begin, ch.sub_end, 0, k->h_subs, items, buckets);
+        for (uint32_t i = ch.sub_begin; i < ch.sub_end; i++) k->h_subs[i].res = i;
     }
     std::vector<char> host(total, 0);
     memcpy(host.data() + o_kc, &k->kc, sizeof(DevKernel));
@@ -303,7 +549,7 @@ rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel *
 rv_status rv_free_kernel(rv_ctx *c, rv_kernel *k) {
     if (!c || !k) return RV_ERR_INVALID;
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipDeviceSynchronize();
     if (k->d_mem) (void)hipFree(k->d_mem);
     delete k;
     return RV_OK;
@@ -323,146 +569,87 @@ rv_status rv_kernel_get_info(rv_ctx *c, const rv_kernel *k, rv_kernel_info *out)
 rv_status rv_check(rv_ctx *c, rv_kernel *k, rv_result *out) {
     if (!c || !k || !out) return RV_ERR_INVALID;
     if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
     c->err.clear();
     HIP_TRY(c, hipSetDevice(c->device));
-    const size_t ns = k->subs.size();
-    rv_status st = ensure_res(c, std::max<size_t>(ns, 1));
+    rv_status st = lane_enqueue(c, c->main, &k, 1);
     if (st) return st;
-    st = ensure_pin(c, std::max<size_t>(ns, 1) * sizeof(SubResult));
-    if (st) return st;
-    timed(c, RV_STAGE_FILL, [&] { launch_init_results(c->d_res, ns, c->stream); });
-    for (auto &ch : k->chunks)
-        run_check_chunk(c, k->d_subs + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets);
-    if ((st = check_launch(c))) return st;
-    if (ns) HIP_TRY(c, hipMemcpyAsync(c->h_pin, c->d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return assemble(c, *k, reinterpret_cast<SubResult *>(c->h_pin), out);
+    rv_result r;
+    st = lane_collect(c, c->main, &r, nullptr);
+    if (!st) *out = r;
+    return st;
 }
 
 rv_status rv_check_batch(rv_ctx *c, rv_kernel *const *ks, size_t n, rv_result *out) {
     if (!c || (n && (!ks || !out))) return RV_ERR_INVALID;
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
     c->err.clear();
     if (!n) return RV_OK;
     HIP_TRY(c, hipSetDevice(c->device));
-    std::vector<size_t> res0(n + 1, 0);
     for (size_t j = 0; j < n; j++) {
         if (!ks[j]) return fail(c, RV_ERR_INVALID, "null kernel in batch");
         if (ks[j]->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
-        res0[j + 1] = res0[j] + ks[j]->subs.size();
     }
-    const size_t ns = res0[n];
-    // chunks across kernels: passes in (kernel, pass) order, greedy by capacity
-    struct Chunk { size_t sub_begin, sub_end; uint64_t items, buckets; };
-    std::vector<Chunk> chunks;
-    std::vector<DevSub> table;
-    table.reserve(ns);
-    Chunk cur{0, 0, 0, 0};
-    uint64_t rec_bound = 0;
-    for (size_t j = 0; j < n; j++) {
-        const rv_kernel &k = *ks[j];
-        for (uint32_t i = 0; i < k.subs.size(); i++) {
-            const IntervalPlan &I = k.intervals[k.subs[i].interval];
-            const uint32_t nb = k.subs[i].nb;
-            if (cur.sub_end > cur.sub_begin &&
-                (rec_bound + I.P > c->L.cap_records || cur.buckets + nb > c->L.cap_buckets ||
-                 cur.items + I.items >= (1ull << 31))) {
-                chunks.push_back(cur);
-                cur = Chunk{table.size(), table.size(), 0, 0};
-                rec_bound = 0;
-            }
-            make_devsubs(k, i, i + 1, (uint32_t)(res0[j] + i), table, cur.items, cur.buckets);
-            cur.sub_end = table.size();
-            rec_bound += I.P;
-        }
-    }
-    if (cur.sub_end > cur.sub_begin) chunks.push_back(cur);
-    rv_status st = ensure_res(c, std::max<size_t>(ns, 1));
+    rv_status st = lane_enqueue(c, c->main, ks, n);
     if (st) return st;
-    st = ensure_bsubs(c, std::max<size_t>(table.size(), 1));
-    if (st) return st;
-    const size_t pin_bytes = std::max(table.size() * sizeof(DevSub), ns * sizeof(SubResult));
-    st = ensure_pin(c, std::max<size_t>(pin_bytes, 64));
-    if (st) return st;
-    if (!table.empty()) {
-        memcpy(c->h_pin, table.data(), table.size() * sizeof(DevSub));
-        HIP_TRY(c, hipMemcpyAsync(c->d_bsubs, c->h_pin, table.size() * sizeof(DevSub), hipMemcpyHostToDevice,
-                                  c->stream));
-    }
-    timed(c, RV_STAGE_FILL, [&] { launch_init_results(c->d_res, ns, c->stream); });
-    for (auto &ch : chunks)
-        run_check_chunk(c, c->d_bsubs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items, ch.buckets);
-    if ((st = check_launch(c))) return st;
-    // the pinned buffer is reused for results once the upload has completed (stream order)
-    if (ns) HIP_TRY(c, hipMemcpyAsync(c->h_pin, c->d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    const SubResult *hr = reinterpret_cast<const SubResult *>(c->h_pin);
-    for (size_t j = 0; j < n; j++) {
-        st = assemble(c, *ks[j], hr + res0[j], &out[j]);
-        if (st) {
-            c->err = "kernel " + std::to_string(j) + ": " + c->err;
-            return st;
-        }
-    }
-    return RV_OK;
+    return lane_collect(c, c->main, out, nullptr);
 }
 
 rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_witness *out, size_t cap,
                            size_t *n_out) {
     if (!c || !k || !n_out || (cap && !out)) return RV_ERR_INVALID;
     if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
     c->err.clear();
     *n_out = 0;
     HIP_TRY(c, hipSetDevice(c->device));
+    Lane &ln = c->main;
     const size_t ns = k->subs.size();
-    rv_status st = ensure_res(c, std::max<size_t>(ns, 1));
+    rv_status st = grow_device(c, ln, ln.d_res, ln.res_cap, std::max<size_t>(ns, 1));
     if (st) return st;
-    st = ensure_pin(c, std::max<size_t>(std::max<size_t>(cap, 1) * sizeof(DevWitness), ns * sizeof(SubResult)));
+    st = grow_pinned(c, ln, ln.h_down, ln.down_cap, std::max<size_t>(ns, 1) * sizeof(SubResult));
     if (st) return st;
     DevWitness *d_win = nullptr;
     if (cap) HIP_TRY(c, hipMalloc(&d_win, cap * sizeof(DevWitness)));
     const unsigned long long lo = first_index, hi = first_index + cap;
     unsigned long long base = 0;
-    launch_init_results(c->d_res, ns, c->stream);
+    hipStream_t s = ln.stream;
+    launch_init_results(ln.d_res, ns, s);
+    auto bail = [&](const std::string &m) {
+        if (d_win) (void)hipFree(d_win);
+        return fail(c, RV_ERR_DEVICE, m);
+    };
     for (auto &ch : k->chunks) {
         const DevSub *subs = k->d_subs + ch.sub_begin;
         const uint32_t nsub = ch.sub_end - ch.sub_begin;
-        run_expand(c, subs, nsub, ch.items, ch.buckets);
-        launch_bucket(subs, nsub, ch.buckets, c->rec(), c->starts(), c->counts(), c->conf(), 0, c->ncu, c->stream);
-        launch_finish(subs, nsub, ch.buckets, c->conf(), c->d_res, c->stream);
+        run_expand(c, ln, subs, nsub, ch.items, ch.buckets);
+        launch_bucket(subs, nsub, ch.buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 0, c->ncu, s);
+        launch_finish(subs, nsub, ch.buckets, ln.conf(), ln.d_res, s);
         // exclusive scan of per-bucket conflict counts -> list positions (cursor area)
-        launch_scan(c->conf(), c->cursor(), nullptr, c->bsum(), ch.buckets, c->stream);
+        launch_scan(ln.conf(), ln.cursor(), nullptr, ln.bsum(), ch.buckets, s);
         const size_t nbk = (ch.buckets + 4095) / 4096;
         uint32_t total = 0;
-        hipError_t e = hipMemcpyAsync(&total, c->bsum() + nbk, 4, hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) {
-            if (d_win) (void)hipFree(d_win);
-            return fail(c, RV_ERR_DEVICE, std::string("witness collect: ") + hipGetErrorString(e));
-        }
+        hipError_t e = hipMemcpyAsync(&total, ln.bsum() + nbk, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(std::string("witness collect: ") + hipGetErrorString(e));
         if (cap && base < hi && base + total > lo)
-            launch_gather(subs, nsub, ch.buckets, c->rec(), c->starts(), c->conf(), c->cursor(), base, lo, hi, d_win,
-                          c->stream);
+            launch_gather(subs, nsub, ch.buckets, ln.rec(), ln.starts(), ln.conf(), ln.cursor(), base, lo, hi, d_win,
+                          s);
         base += total;
     }
     if ((st = check_launch(c))) { if (d_win) (void)hipFree(d_win); return st; }
-    // OOB check through the pass results
-    hipError_t e = hipMemcpyAsync(c->h_pin, c->d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-        if (d_win) (void)hipFree(d_win);
-        return fail(c, RV_ERR_DEVICE, std::string("witness collect: ") + hipGetErrorString(e));
-    }
+    hipError_t e = hipMemcpyAsync(ln.h_down, ln.d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(std::string("witness collect: ") + hipGetErrorString(e));
     rv_result tmp;
-    st = assemble(c, *k, reinterpret_cast<const SubResult *>(c->h_pin), &tmp);
-    if (st) { if (d_win) (void)hipFree(d_win); return st; }
+    std::string m;
+    st = assemble(*k, reinterpret_cast<const SubResult *>(ln.h_down), &tmp, m);
+    if (st) { if (d_win) (void)hipFree(d_win); return fail(c, st, m); }
     const size_t got = base > lo ? (size_t)std::min<unsigned long long>(cap, base - lo) : 0;
     if (got) {
         std::vector<DevWitness> hw(got);
         e = hipMemcpy(hw.data(), d_win, got * sizeof(DevWitness), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) {
-            (void)hipFree(d_win);
-            return fail(c, RV_ERR_DEVICE, std::string("witness copy: ") + hipGetErrorString(e));
-        }
+        if (e != hipSuccess) return bail(std::string("witness copy: ") + hipGetErrorString(e));
         for (size_t i = 0; i < got; i++) decode_witness(*k, k->subs[hw[i].sub].interval, hw[i].w, out[i]);
     }
     if (d_win) (void)hipFree(d_win);
@@ -474,10 +661,12 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
                            size_t *n_out) {
     if (!c || !k || !n_out || (cap && !out)) return RV_ERR_INVALID;
     if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
     c->err.clear();
     *n_out = 0;
     if (interval >= k->n_intervals) return fail(c, RV_ERR_INVALID, "no such interval");
     HIP_TRY(c, hipSetDevice(c->device));
+    Lane &ln = c->main;
     uint32_t sb = 0;
     while (sb < k->subs.size() && k->subs[sb].interval < interval) sb++;
     uint32_t se = sb;
@@ -487,32 +676,32 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
     uint64_t items = 0, buckets = 0;
     make_devsubs(*k, sb, se, 0, table, items, buckets);
     const IntervalPlan &I = k->intervals[interval];
-    if ((se - sb) * I.P > c->L.cap_records || buckets > c->L.cap_buckets)
+    if ((se - sb) * I.P > ln.L.cap_records || buckets > ln.L.cap_buckets)
         return fail(c, RV_ERR_TOO_LARGE, "interval does not fit the workspace");
-    rv_status st = ensure_res(c, se - sb);
+    rv_status st = grow_device(c, ln, ln.d_res, ln.res_cap, se - sb);
     if (st) return st;
-    st = ensure_bsubs(c, table.size());
+    st = grow_device(c, ln, ln.d_subs, ln.subs_cap, table.size());
     if (st) return st;
-    HIP_TRY(c, hipMemcpy(c->d_bsubs, table.data(), table.size() * sizeof(DevSub), hipMemcpyHostToDevice));
-    launch_init_results(c->d_res, se - sb, c->stream);
-    run_expand(c, c->d_bsubs, se - sb, items, buckets);
+    hipStream_t s = ln.stream;
+    HIP_TRY(c, hipMemcpy(ln.d_subs, table.data(), table.size() * sizeof(DevSub), hipMemcpyHostToDevice));
+    launch_init_results(ln.d_res, se - sb, s);
+    run_expand(c, ln, ln.d_subs, se - sb, items, buckets);
     if ((st = check_launch(c))) return st;
     std::vector<uint32_t> cnt(buckets);
-    HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->counts(), buckets * 4, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpyAsync(cnt.data(), ln.counts(), buckets * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
     uint64_t total = 0;
     for (uint32_t x : cnt) {
         total += x;
         if (sorted && x > (uint32_t)CAP) return fail(c, RV_ERR_UNSUPPORTED, "a bucket exceeds one on-chip slice");
     }
     if (sorted) {
-        launch_bucket(c->d_bsubs, se - sb, buckets, c->rec(), c->starts(), c->counts(), c->conf(), 1, c->ncu, c->stream);
+        launch_bucket(ln.d_subs, se - sb, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 1, c->ncu, s);
         if ((st = check_launch(c))) return st;
     }
     std::vector<unsigned long long> recs(total);
-    if (total)
-        HIP_TRY(c, hipMemcpyAsync(recs.data(), c->rec(), total * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (total) HIP_TRY(c, hipMemcpyAsync(recs.data(), ln.rec(), total * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
     const size_t m = std::min<size_t>(cap, total);
     for (size_t i = 0; i < m; i++) {
         const uint32_t hiw = (uint32_t)(recs[i] >> 32), id = (uint32_t)recs[i];
@@ -520,11 +709,11 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
         memset(&o, 0, sizeof o);
         o.interval = interval;
         decode_location(*k, interval, hiw >> 1, o.space, o.array, o.block, o.address);
-        rv_side s;
-        decode_instance(*k, interval, id, s, o.gthread, o.lidx);
-        o.dyn_phase = s.dyn_phase;
-        o.access = s.access;
-        o.loop[0] = s.loop[0]; o.loop[1] = s.loop[1]; o.loop[2] = s.loop[2];
+        rv_side sd;
+        decode_instance(*k, interval, id, sd, o.gthread, o.lidx);
+        o.dyn_phase = sd.dyn_phase;
+        o.access = sd.access;
+        o.loop[0] = sd.loop[0]; o.loop[1] = sd.loop[1]; o.loop[2] = sd.loop[2];
         o.is_write = (int32_t)(hiw & 1u);
     }
     *n_out = total;
@@ -546,6 +735,89 @@ rv_status rv_get_timing(rv_ctx *c, rv_timing *out, int reset) {
     return RV_OK;
 }
 
+// ------------------------------------------------------------- serving
+rv_status rv_server_create(rv_ctx *c, void *workspace, size_t budget_bytes, rv_server **out) {
+    if (!c || !workspace || !out) return RV_ERR_INVALID;
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context already has a server");
+    if (budget_bytes < (128u << 20)) return fail(c, RV_ERR_TOO_LARGE, "server budget below 128 MiB");
+    HIP_TRY(c, hipSetDevice(c->device));
+    rv_server *s = new (std::nothrow) rv_server;
+    if (!s) return fail(c, RV_ERR_TOO_LARGE, "out of host memory");
+    s->c = c;
+    s->budget = budget_bytes;
+    const size_t half = (budget_bytes / 2) & ~(size_t)255;
+    for (int l = 0; l < 2; l++) {
+        Lane &ln = s->lanes[l];
+        ln.ws = reinterpret_cast<char *>(workspace) + l * half;
+        ln.L = layout_workspace(half);
+        hipError_t e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
+        if (e != hipSuccess || !ln.L.cap_records) {
+            for (int q = 0; q <= l; q++)
+                if (s->lanes[q].stream) (void)hipStreamDestroy(s->lanes[q].stream);
+            delete s;
+            return fail(c, RV_ERR_DEVICE, "server lane setup failed");
+        }
+    }
+    c->serving = true;
+    s->worker = std::thread(server_loop, s);
+    *out = s;
+    return RV_OK;
+}
+
+rv_status rv_server_submit(rv_server *s, rv_kernel *k, uint64_t *job_id) {
+    if (!s || !k || !job_id) return RV_ERR_INVALID;
+    if (k->owner != s->c) return RV_ERR_STATE;
+    if (!fits(*k, s->lanes[0].L)) return RV_ERR_BUDGET;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) return RV_ERR_STATE;
+    const uint64_t id = s->next_id++;
+    s->pending.push_back({id, k, now_ns()});
+    s->in_flight++;
+    *job_id = id;
+    s->cv.notify_all();
+    return RV_OK;
+}
+
+rv_status rv_server_poll(rv_server *s, rv_job_result *out, size_t cap, size_t *n_out) {
+    if (!s || !n_out || (cap && !out)) return RV_ERR_INVALID;
+    std::lock_guard<std::mutex> g(s->mu);
+    const size_t n = std::min(cap, s->done.size());
+    for (size_t i = 0; i < n; i++) out[i] = s->done[i];
+    s->done.erase(s->done.begin(), s->done.begin() + n);
+    *n_out = n;
+    return RV_OK;
+}
+
+rv_status rv_server_drain(rv_server *s, uint64_t timeout_ms) {
+    if (!s) return RV_ERR_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+    while (s->in_flight) {
+        if (s->cv.wait_until(lk, until) == std::cv_status::timeout && s->in_flight) return RV_ERR_STATE;
+    }
+    return RV_OK;
+}
+
+rv_status rv_server_destroy(rv_server *s) {
+    if (!s) return RV_ERR_INVALID;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->c->device);
+    for (auto &ln : s->lanes) {
+        if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+        lane_release(ln);
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
+    }
+    s->c->serving = false;
+    delete s;
+    return RV_OK;
+}
+
+// ------------------------------------------------------------- self test
 rv_status rv_selftest(char *msg, size_t cap) {
     std::string m;
     auto check_div = [&](uint32_t d, uint32_t n) -> bool {

@@ -203,6 +203,8 @@ struct rv_kernel {
     uint32_t *d_entry_items = nullptr;
     rv::DevSub *d_subs = nullptr;   // all passes, begins relative to this kernel's own chunks
     std::vector<rv::DevSub> h_subs;
+    size_t plan_cap_records = 0;     // the workspace layout `chunks` was planned for
+    size_t plan_cap_buckets = 0;
     rv_ctx *owner = nullptr;
 };
 

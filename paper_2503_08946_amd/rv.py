@@ -109,6 +109,11 @@ class rv_record(ctypes.Structure):
                 ("loop", i32 * 3), ("is_write", i32)]
 
 
+class rv_job_result(ctypes.Structure):
+    _fields_ = [("job_id", u64), ("status", i32), ("reserved", i32), ("result", rv_result),
+                ("t_submit_ns", u64), ("t_start_ns", u64), ("t_done_ns", u64)]
+
+
 # --------------------------------------------------------------- library
 _lib = None
 
@@ -135,6 +140,11 @@ def lib():
             "rv_set_timing": [V, ctypes.c_int],
             "rv_get_timing": [V, P(rv_timing), ctypes.c_int],
             "rv_selftest": [ctypes.c_char_p, S],
+            "rv_server_create": [V, V, S, P(V)],
+            "rv_server_destroy": [V],
+            "rv_server_submit": [V, V, P(u64)],
+            "rv_server_poll": [V, P(rv_job_result), S, P(S)],
+            "rv_server_drain": [V, u64],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -148,7 +158,8 @@ def lib():
 
 EXPORTED = ("rv_validate_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_error", "rv_load_kernel_desc",
             "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_get_witnesses",
-            "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest")
+            "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest", "rv_server_create",
+            "rv_server_destroy", "rv_server_submit", "rv_server_poll", "rv_server_drain")
 
 
 # -------------------------------------------------------------- marshalling
@@ -390,3 +401,74 @@ class Context:
         t = rv_timing()
         self._call(lib().rv_get_timing, self.handle, ctypes.byref(t), int(reset))
         return {name: (t.ms[i], t.launches[i]) for i, name in enumerate(STAGES)}
+
+
+@dataclass
+class JobResult:
+    job_id: int
+    status: int
+    result: Optional[Result]
+    t_submit_ns: int
+    t_start_ns: int
+    t_done_ns: int
+
+    @property
+    def latency_ns(self) -> int:
+        return self.t_done_ns - self.t_submit_ns
+
+
+class Server:
+    """Continuous-batching server over a context (see rv_server_* in rv.h).
+
+    ``workspace``: a torch uint8 CUDA tensor of the budget, or None to
+    allocate ``budget_bytes``."""
+
+    def __init__(self, ctx: Context, budget_bytes: int = 1 << 30, workspace=None):
+        import torch
+        self.ctx = ctx
+        if workspace is None:
+            workspace = torch.empty(int(budget_bytes), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        self.workspace = workspace
+        h = ctypes.c_void_p()
+        ctx._call(lib().rv_server_create, ctx.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                  ctypes.byref(h))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, k: Kernel) -> int:
+        jid = ctypes.c_uint64()
+        st = lib().rv_server_submit(self.handle, k.handle, ctypes.byref(jid))
+        if st:
+            raise RVError(st, "rv_server_submit failed")
+        self._keep[jid.value] = k
+        return jid.value
+
+    def poll(self, cap: int = 4096) -> List[JobResult]:
+        buf = (rv_job_result * cap)()
+        n = ctypes.c_size_t()
+        st = lib().rv_server_poll(self.handle, buf, cap, ctypes.byref(n))
+        if st:
+            raise RVError(st, "rv_server_poll failed")
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            self._keep.pop(r.job_id, None)
+            out.append(JobResult(r.job_id, r.status, _result(r.result) if r.status == 0 else None,
+                                 r.t_submit_ns, r.t_start_ns, r.t_done_ns))
+        return out
+
+    def drain(self, timeout_ms: int = 600000):
+        st = lib().rv_server_drain(self.handle, int(timeout_ms))
+        if st:
+            raise RVError(st, "rv_server_drain timed out")
+
+    def close(self):
+        if self.handle:
+            lib().rv_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -36,9 +36,6 @@ def _dims_for(rng, n_elems: int):
 def random_kernel(rng: np.random.Generator, lo: float, hi: float, name: str = "") -> KernelDesc:
     target = math.exp(rng.uniform(math.log(lo), math.log(hi)))
     while True:
-        bdx = int(rng.integers(1, 33))
-        bdy = int(rng.integers(1, 33))
-        tpb = bdx * bdy
         n_ph = int(rng.integers(1, 7))
         accs_per_phase = [int(rng.integers(1, 9)) for _ in range(n_ph)]
         n_acc = sum(accs_per_phase)
@@ -49,6 +46,13 @@ def random_kernel(rng: np.random.Generator, lo: float, hi: float, name: str = ""
             trips = [int(rng.integers(1, 65)) for _ in range(nl)]
             loops.append(trips)
             m += int(np.prod(trips)) if trips else 1
+        # block dims drawn among those that can still reach the target
+        cap = int(1.1 * target / m)
+        if cap < 1:
+            continue
+        bdx = int(rng.integers(1, min(32, cap) + 1))
+        bdy = int(rng.integers(1, min(32, max(1, cap // bdx)) + 1))
+        tpb = bdx * bdy
         per_block = tpb * m
         nblk = target / per_block
         if nblk < 1 or nblk > 64 * 64:
