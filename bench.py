@@ -141,9 +141,10 @@ def bench_batch(args, rv, torch):
     ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
     ks = [ctx.load(d) for d in descs]
     log(f"[bench] loaded 4096 kernels")
+    batch = rv.Batch(ctx, ks)
     for i in range(args.warmup):
-        res = ctx.check_batch(ks)
-        log(f"[bench] warmup {i}: records={sum(r.n_records for r in res)}")
+        batch.run()
+        log(f"[bench] warmup {i}: records={sum(r.n_records for r in batch.results())}")
     # per-kernel plain launches, one pass over the batch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -158,13 +159,14 @@ def bench_batch(args, rv, torch):
     t0 = time.perf_counter()
     for i in range(args.steps):
         s0 = time.perf_counter()
-        res = ctx.check_batch(ks)
+        batch.run()
         lat.append(time.perf_counter() - s0)
         log(f"[bench] step {i}: {lat[-1] * 1e3:.2f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.set_timing(False)
     stages = ctx.timing(reset=True)
+    res = batch.results()
     assert [(r.n_records, r.n_conflicts) for r in res] == [(r.n_records, r.n_conflicts) for r in single]
     per_step = {k: v[0] / args.steps for k, v in stages.items()}
     log("[bench] GPU ms per step by stage: " + ", ".join(f"{k}={v:.3f}" for k, v in per_step.items()))

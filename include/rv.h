@@ -168,6 +168,8 @@ typedef struct {
     uint32_t n_chunks;         /* workspace-sized groups of passes */
     uint32_t n_buckets;        /* location buckets over all passes */
     uint64_t max_interval_instances;
+    uint32_t n_entries;        /* (interval, dynamic phase, access) expansion entries */
+    uint32_t n_flat_entries;   /* of which expanded with loop chunks across lanes (few threads) */
 } rv_kernel_info;
 
 /* A decoded record (debugging and expansion-parity tests). */
@@ -249,6 +251,28 @@ rv_status rv_debug_records(rv_ctx *ctx, rv_kernel *k, uint32_t interval, int sor
  * reset != 0, clears the accumulators. */
 rv_status rv_set_timing(rv_ctx *ctx, int enable);
 rv_status rv_get_timing(rv_ctx *ctx, rv_timing *out, int reset);
+
+/* ---------------------------------------------------------------- tuning
+ * The planner's one free parameter is the mean number of records per
+ * location bucket (`target`): it sets each interval's bucket width 2^s
+ * (s = floor(log2(target x locations / instances)), clamped to [0, 9]), so
+ * it trades the number of buckets (per-bucket overhead of the sort + scan)
+ * against slices that overflow one on-chip tile.  It applies to kernels
+ * loaded after it is set; results do not depend on it. */
+typedef struct {
+    int32_t target;          /* mean records per bucket, in [64, 4096]; default 2048 */
+    int32_t n_candidates;    /* rv_autotune: candidates measured */
+    int32_t candidates[8];
+    double ms[8];            /* rv_autotune: median wall time of one batched check per candidate */
+} rv_tuning;
+rv_status rv_ctx_get_tuning(rv_ctx *ctx, rv_tuning *out);
+rv_status rv_ctx_set_tuning(rv_ctx *ctx, const rv_tuning *t);   /* reads t->target only */
+/* Measure a batched check of descs[0..n) (host memory, as rv_load_kernel_desc
+ * takes them) under each candidate target, `trials` timed runs after one
+ * warm-up each (host wall time from launch to results on the host, median),
+ * keep the fastest in the context and report all of them in *out.  A
+ * description that fails to load or check fails the call with its code. */
+rv_status rv_autotune(rv_ctx *ctx, const rv_kernel_desc *descs, size_t n, int32_t trials, rv_tuning *out);
 
 /* ------------------------------------------------------------- serving
  * A server checks a stream of submitted kernels with continuous batching:

@@ -6,8 +6,8 @@ touch the GPU; the first call that needs the library loads it and raises if
 it is missing.
 """
 
-from .rv import (EXPORTED, STAGES, STATUS, Context, JobResult, Kernel, Marshalled, Result, RVError, Server,
+from .rv import (EXPORTED, STAGES, STATUS, Batch, Context, JobResult, Kernel, Marshalled, Result, RVError, Server,
                  Side, Witness, lib, selftest, validate)
 
-__all__ = ["EXPORTED", "STAGES", "STATUS", "Context", "JobResult", "Kernel", "Marshalled", "Result", "RVError",
+__all__ = ["EXPORTED", "STAGES", "STATUS", "Batch", "Context", "JobResult", "Kernel", "Marshalled", "Result", "RVError",
            "Server", "Side", "Witness", "lib", "selftest", "validate"]

@@ -66,6 +66,7 @@ struct rv_ctx {
     Lane main;
     std::string err;
     bool serving = false;           // a server owns the device work of this context
+    int target = DEFAULT_TARGET;    // planner: mean records per bucket for kernels loaded next
     // timing
     bool timing = false;
     struct Ev { int stage; hipEvent_t a, b; };
@@ -276,7 +277,13 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
                     cur = Chunk{table.size(), table.size(), 0, 0};
                     rec_bound = 0;
                 }
-                make_devsubs(k, i, i + 1, (uint32_t)(ln.res0[j] + i), table, cur.items, cur.buckets);
+                DevSub D = k.h_subs[i];     // the pass as loaded; begins and slot re-based here
+                D.item_begin = (uint32_t)cur.items;
+                D.bucket_begin = (uint32_t)cur.buckets;
+                D.res = (uint32_t)(ln.res0[j] + i);
+                table.push_back(D);
+                cur.items += I.items;
+                cur.buckets += nb;
                 cur.sub_end = table.size();
                 rec_bound += I.P;
             }
@@ -489,15 +496,17 @@ rv_status rv_ctx_destroy(rv_ctx *c) {
 
 const char *rv_last_error(const rv_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
-rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel **out) {
-    if (!c || !out) return RV_ERR_INVALID;
-    c->err.clear();
+}  // extern "C"
+
+namespace {
+
+rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kernel **out) {
     rv_kernel *k = new (std::nothrow) rv_kernel;
     if (!k) return fail(c, RV_ERR_TOO_LARGE, "out of host memory");
     std::string m;
     rv_status st;
     try {
-        st = plan_kernel(desc, DEFAULT_TARGET, *k, m);
+        st = plan_kernel(desc, target, *k, m);
         if (!st) st = plan_chunks(*k, c->main.L, m);
     } catch (const std::bad_alloc &) {
         st = RV_ERR_TOO_LARGE;
@@ -506,7 +515,7 @@ rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel *
     if (st) { delete k; return fail(c, st, m); }
     k->plan_cap_records = c->main.L.cap_records;
     k->plan_cap_buckets = c->main.L.cap_buckets;
-    HIP_TRY(c, hipSetDevice(c->device));
+    if (hipSetDevice(c->device) != hipSuccess) { delete k; return fail(c, RV_ERR_DEVICE, "hipSetDevice failed"); }
     // one device block: kernel constants, entries, guard rows, entry prefixes, passes
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t o_kc = 0;
@@ -546,12 +555,26 @@ rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel *
     return RV_OK;
 }
 
+void free_kernel(rv_kernel *k) {
+    if (k->d_mem) (void)hipFree(k->d_mem);
+    delete k;
+}
+
+}  // namespace
+
+extern "C" {
+
+rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel **out) {
+    if (!c || !out) return RV_ERR_INVALID;
+    c->err.clear();
+    return load_kernel(c, desc, c->target, out);
+}
+
 rv_status rv_free_kernel(rv_ctx *c, rv_kernel *k) {
     if (!c || !k) return RV_ERR_INVALID;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    if (k->d_mem) (void)hipFree(k->d_mem);
-    delete k;
+    free_kernel(k);
     return RV_OK;
 }
 
@@ -563,6 +586,10 @@ rv_status rv_kernel_get_info(rv_ctx *c, const rv_kernel *k, rv_kernel_info *out)
     out->n_chunks = (uint32_t)k->chunks.size();
     out->n_buckets = (uint32_t)k->n_buckets;
     out->max_interval_instances = k->max_interval_instances;
+    out->n_entries = (uint32_t)k->entries.size();
+    uint32_t nf = 0;
+    for (const auto &e : k->entries) nf += e.flat;
+    out->n_flat_entries = nf;
     return RV_OK;
 }
 
@@ -814,6 +841,65 @@ rv_status rv_server_destroy(rv_server *s) {
     }
     s->c->serving = false;
     delete s;
+    return RV_OK;
+}
+
+// -------------------------------------------------------------- tuning
+rv_status rv_ctx_get_tuning(rv_ctx *c, rv_tuning *out) {
+    if (!c || !out) return RV_ERR_INVALID;
+    memset(out, 0, sizeof *out);
+    out->target = c->target;
+    return RV_OK;
+}
+
+rv_status rv_ctx_set_tuning(rv_ctx *c, const rv_tuning *t) {
+    if (!c || !t) return RV_ERR_INVALID;
+    if (t->target < 64 || t->target > CAP) return fail(c, RV_ERR_INVALID, "target must be in [64, 4096]");
+    c->target = t->target;
+    return RV_OK;
+}
+
+rv_status rv_autotune(rv_ctx *c, const rv_kernel_desc *descs, size_t n, int32_t trials, rv_tuning *out) {
+    if (!c || !out || (n && !descs) || trials < 1) return RV_ERR_INVALID;
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
+    c->err.clear();
+    HIP_TRY(c, hipSetDevice(c->device));
+    static const int cand[] = {512, 1024, 2048, 3072};
+    const int nc = (int)(sizeof cand / sizeof cand[0]);
+    rv_tuning t;
+    memset(&t, 0, sizeof t);
+    t.n_candidates = nc;
+    rv_status st = RV_OK;
+    std::vector<rv_result> res(std::max<size_t>(n, 1));
+    int best = -1;
+    for (int ci = 0; ci < nc && !st; ci++) {
+        t.candidates[ci] = cand[ci];
+        std::vector<rv_kernel *> ks;
+        for (size_t j = 0; j < n && !st; j++) {
+            rv_kernel *k = nullptr;
+            st = load_kernel(c, &descs[j], cand[ci], &k);
+            if (!st) ks.push_back(k);
+        }
+        // host wall time of the whole batched check (launches, device work,
+        // result readback): the quantity the target trades off
+        std::vector<double> ms;
+        for (int r = 0; r <= trials && !st; r++) {    // run 0 warms up
+            const uint64_t t0 = now_ns();
+            st = lane_enqueue(c, c->main, ks.data(), ks.size());
+            if (!st) st = lane_collect(c, c->main, res.data(), nullptr);
+            if (!st && r) ms.push_back((double)(now_ns() - t0) * 1e-6);
+        }
+        (void)hipStreamSynchronize(c->main.stream);
+        for (auto k : ks) free_kernel(k);
+        if (st) break;
+        std::sort(ms.begin(), ms.end());
+        t.ms[ci] = ms[ms.size() / 2];
+        if (best < 0 || t.ms[ci] < t.ms[best]) best = ci;
+    }
+    if (st) return st;
+    t.target = best >= 0 ? cand[best] : c->target;
+    c->target = t.target;
+    *out = t;
     return RV_OK;
 }
 

@@ -210,20 +210,50 @@ __device__ __forceinline__ void my_items(uint32_t n, uint32_t &w0, uint32_t &w1)
 // f(slot, valid, in_bounds, location, id) for each.  A work item covers
 // `lch` consecutive loop points of `gt` threads per lane; the loop counters
 // are wave-uniform, the thread decode is per lane and per thread.
-template <class F>
-__device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t gtile, uint32_t lchunk,
-                                            F &&f) {
+// Where item `li` of an entry starts for this lane: the first loop point of
+// its chunk (lstart, and its loop counters) and the global thread of its
+// first thread group slot (g0; slot gi is g0 + gi * gstep).
+template <bool FLAT>
+struct ItemStart {
+    uint32_t lstart, g0, gstep, c0, c1, c2;
+};
+
+template <bool FLAT>
+__device__ __forceinline__ ItemStart<FLAT> item_start(CEnt &E, CKer &K, uint32_t li) {
+    ItemStart<FLAT> a;
+    const uint32_t nl = E.n_lchunks;
+    if constexpr (!FLAT) {
+        const uint32_t gtile = udiv(li, ldm(E.mg_nl));
+        const uint32_t lchunk = li - gtile * nl;
+        a.lstart = lchunk * E.lch;
+        a.g0 = gtile * E.gt * EXP_WG + threadIdx.x;
+        a.gstep = EXP_WG;
+    } else {
+        const uint32_t q = li * EXP_WG + threadIdx.x;
+        const uint32_t tg = udiv(q, ldm(E.mg_nl));
+        const bool qv = q < E.nq;
+        a.lstart = qv ? (q - tg * nl) * E.lch : 0u;
+        a.g0 = qv ? tg * E.gt : K.nthreads;     // past the last thread: every slot invalid
+        a.gstep = 1;
+    }
+    uint32_t r = a.lstart;
+    uint32_t t = udiv(r, ldm(E.mg_e2));
+    a.c2 = r - t * E.ext[2];
+    r = t;
+    t = udiv(r, ldm(E.mg_e1));
+    a.c1 = r - t * E.ext[1];
+    a.c0 = t;
+    return a;
+}
+
+template <bool FLAT, class F>
+__device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t item, F &&f) {
     const uint32_t lch = E.lch, gt = E.gt;
-    const uint32_t lstart = lchunk * lch;
+    const ItemStart<FLAT> st = item_start<FLAT>(E, K, item);
+    const uint32_t lstart = st.lstart;
     const uint32_t lcnt = min(lch, E.box - lstart);
     const uint32_t e1 = E.ext[1], e2 = E.ext[2];
-    uint32_t c0s, c1s, c2s;
-    {
-        uint32_t r = lstart;
-        c2s = r % e2; r /= e2;
-        c1s = r % e1; r /= e1;
-        c0s = r;
-    }
+    const uint32_t c0s = st.c0, c1s = st.c1, c2s = st.c2;
     uint32_t c0 = c0s, c1 = c1s, c2 = c2s;
     uint32_t gi = 0, li = 0;
     int32_t tx = 0, ty = 0, bx = 0, by = 0;
@@ -235,7 +265,7 @@ __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, 
     for (int s = 0; s < RPL; ++s) {
         const bool active = gi < gt;
         if (active && li == 0) {
-            const uint32_t g = (gtile * gt + gi) * EXP_WG + threadIdx.x;
+            const uint32_t g = st.g0 + gi * st.gstep;
             gval = g < K.nthreads;
             const uint32_t gg = gval ? g : 0u;
             const uint32_t blk = udiv(gg, ldm(K.mg_tpb));
@@ -302,46 +332,57 @@ __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, 
 }
 
 // Fast path of expand_item for entries without aux terms or guards: the
-// per-thread index bases use 24-bit multiplies, the loop terms are
-// wave-uniform (scalar unit), and the location is one add per record from the
-// flattened row (exact modulo 2^32 for in-bounds records).
-template <class F>
-__device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t gtile, uint32_t lchunk, F &&f) {
+// per-thread index bases use 24-bit multiplies, the loop terms advance by
+// precomputed steps (wave-uniform on the scalar unit unless FLAT), and the
+// location is one add per record from the flattened row (exact modulo 2^32
+// for in-bounds records).  PROVEN: the plan showed every index of the entry
+// inside its dimension over the whole launch and loop box, so the per-record
+// index evaluation and bounds test are skipped.
+template <bool FLAT, bool PROVEN, class F>
+__device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t item, F &&f) {
     const uint32_t lch = E.lch, gt = E.gt;
-    const uint32_t lstart = lchunk * lch;
+    const ItemStart<FLAT> st = item_start<FLAT>(E, K, item);
+    const uint32_t lstart = st.lstart;
     const uint32_t lcnt = min(lch, E.box - lstart);
     const uint32_t e1 = E.ext[1], e2 = E.ext[2];
-    const int32_t lo0 = E.lo[0], lo1 = E.lo[1], lo2 = E.lo[2];
-    int32_t ct[3][5], cl[3][3];
+    const uint32_t L0s = (uint32_t)E.lo[0] + st.c0, L1s = (uint32_t)E.lo[1] + st.c1, L2s = (uint32_t)E.lo[2] + st.c2;
+    // loop terms at the chunk start, and their steps when the inner loop
+    // advances (x2), when the middle one does (x1), when the outer one does
+    // (x0); all modulo 2^32
+    uint32_t la[3], lb[3], lc[3];
 #pragma unroll
     for (int r = 0; r < 3; r++) {
-        ct[r][0] = E.row[r][C_TX]; ct[r][1] = E.row[r][C_TY]; ct[r][2] = E.row[r][C_BX];
-        ct[r][3] = E.row[r][C_BY]; ct[r][4] = E.row[r][C_C0];
-        cl[r][0] = E.row[r][C_L0]; cl[r][1] = E.row[r][C_L1]; cl[r][2] = E.row[r][C_L2];
+        la[r] = PROVEN ? 0u : (uint32_t)E.row[r][C_L0];
+        lb[r] = PROVEN ? 0u : (uint32_t)E.row[r][C_L1];
+        lc[r] = PROVEN ? 0u : (uint32_t)E.row[r][C_L2];
     }
+    const uint32_t ts0 = la[0] * L0s + lb[0] * L1s + lc[0] * L2s;
+    const uint32_t ts1 = la[1] * L0s + lb[1] * L1s + lc[1] * L2s;
+    const uint32_t ts2 = la[2] * L0s + lb[2] * L1s + lc[2] * L2s;
+    const uint32_t x2_0 = lc[0], x2_1 = lc[1], x2_2 = lc[2];
+    const uint32_t x1_0 = lb[0] - lc[0] * (e2 - 1), x1_1 = lb[1] - lc[1] * (e2 - 1), x1_2 = lb[2] - lc[2] * (e2 - 1);
+    const uint32_t x0_0 = la[0] - lb[0] * (e1 - 1) - lc[0] * (e2 - 1);
+    const uint32_t x0_1 = la[1] - lb[1] * (e1 - 1) - lc[1] * (e2 - 1);
+    const uint32_t x0_2 = la[2] - lb[2] * (e1 - 1) - lc[2] * (e2 - 1);
+    const uint32_t fl0 = E.fr[C_L0], fl1 = E.fr[C_L1], fl2 = E.fr[C_L2];
+    const uint32_t tls = fl0 * L0s + fl1 * L1s + fl2 * L2s;
+    const uint32_t y2 = fl2, y1 = fl1 - fl2 * (e2 - 1), y0 = fl0 - fl1 * (e1 - 1) - fl2 * (e2 - 1);
     const uint32_t d0 = E.dim[0], d1 = E.dim[1], d2 = E.dim[2];
     const uint32_t ftx = E.fr[C_TX], fty = E.fr[C_TY], fbx = E.fr[C_BX], fby = E.fr[C_BY], fc0 = E.fr[C_C0];
-    const uint32_t fl0 = E.fr[C_L0], fl1 = E.fr[C_L1], fl2 = E.fr[C_L2];
     const uint32_t loc_mul = E.loc_mul, eoff = E.off;
     const uint32_t tpb = K.tpb, bdx = K.bdx, gdx = K.gdx, nthreads = K.nthreads, M = S.M;
     const Magic mg_tpb = ldm(K.mg_tpb), mg_gdx = ldm(K.mg_gdx), mg_bdx = ldm(K.mg_bdx);
-    uint32_t c0s, c1s, c2s;
-    {
-        uint32_t r = lstart;
-        c2s = r % e2; r /= e2;
-        c1s = r % e1; r /= e1;
-        c0s = r;
-    }
-    uint32_t c0 = c0s, c1 = c1s, c2 = c2s;
+    uint32_t c1 = st.c1, c2 = st.c2;
+    uint32_t t0 = ts0, t1 = ts1, t2 = ts2, tl = tls;
     uint32_t gi = 0, li = 0;
-    int32_t base0 = 0, base1 = 0, base2 = 0;
+    uint32_t base0 = 0, base1 = 0, base2 = 0;
     uint32_t lbase = 0, idbase = 0;
     bool gval = false;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const bool active = gi < gt;
         if (active && li == 0) {
-            const uint32_t g = (gtile * gt + gi) * EXP_WG + threadIdx.x;
+            const uint32_t g = st.g0 + gi * st.gstep;
             gval = g < nthreads;
             const uint32_t gg = gval ? g : 0u;
             const uint32_t blk = udiv(gg, mg_tpb);
@@ -350,9 +391,15 @@ __device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t 
             const uint32_t tyy = udiv(tid, mg_bdx);
             const int32_t tx = (int32_t)(tid - tyy * bdx), ty = (int32_t)tyy;
             const int32_t bx = (int32_t)(blk - byy * gdx), by = (int32_t)byy;
-            base0 = __mul24(ct[0][0], tx) + __mul24(ct[0][1], ty) + __mul24(ct[0][2], bx) + __mul24(ct[0][3], by) + ct[0][4];
-            base1 = __mul24(ct[1][0], tx) + __mul24(ct[1][1], ty) + __mul24(ct[1][2], bx) + __mul24(ct[1][3], by) + ct[1][4];
-            base2 = __mul24(ct[2][0], tx) + __mul24(ct[2][1], ty) + __mul24(ct[2][2], bx) + __mul24(ct[2][3], by) + ct[2][4];
+            if constexpr (!PROVEN) {
+                auto bse = [&](int r) {
+                    return (uint32_t)(__mul24(E.row[r][C_TX], tx) + __mul24(E.row[r][C_TY], ty) +
+                                      __mul24(E.row[r][C_BX], bx) + __mul24(E.row[r][C_BY], by) + E.row[r][C_C0]);
+                };
+                base0 = bse(0);
+                base1 = bse(1);
+                base2 = bse(2);
+            }
             lbase = blk * loc_mul + ftx * (uint32_t)tx + fty * (uint32_t)ty + fbx * (uint32_t)bx +
                     fby * (uint32_t)by + fc0;
             idbase = gg * M + eoff + lstart;
@@ -360,12 +407,12 @@ __device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t 
         bool ok = false, inb = false;
         uint32_t loc = 0, id = 0;
         if (active) {
-            const int32_t L0 = lo0 + (int32_t)c0, L1 = lo1 + (int32_t)c1, L2 = lo2 + (int32_t)c2;
-            const int32_t i0 = base0 + (cl[0][0] * L0 + cl[0][1] * L1 + cl[0][2] * L2);
-            const int32_t i1 = base1 + (cl[1][0] * L0 + cl[1][1] * L1 + cl[1][2] * L2);
-            const int32_t i2 = base2 + (cl[2][0] * L0 + cl[2][1] * L1 + cl[2][2] * L2);
-            inb = (uint32_t)i0 < d0 && (uint32_t)i1 < d1 && (uint32_t)i2 < d2;
-            loc = lbase + (fl0 * (uint32_t)L0 + fl1 * (uint32_t)L1 + fl2 * (uint32_t)L2);
+            if constexpr (PROVEN) {
+                inb = true;
+            } else {
+                inb = base0 + t0 < d0 && base1 + t1 < d1 && base2 + t2 < d2;
+            }
+            loc = lbase + tl;
             id = idbase + li;
             ok = gval && li < lcnt;
         }
@@ -375,12 +422,39 @@ __device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t 
             if (li == lch) {
                 li = 0;
                 gi++;
-                c0 = c0s; c1 = c1s; c2 = c2s;
+                c1 = st.c1; c2 = st.c2;
+                t0 = ts0; t1 = ts1; t2 = ts2; tl = tls;
             } else {
                 c2++;
-                if (c2 == e2) { c2 = 0; c1++; if (c1 == e1) { c1 = 0; c0++; } }
+                if (c2 == e2) {
+                    c2 = 0;
+                    c1++;
+                    if (c1 == e1) {
+                        c1 = 0;
+                        t0 += x0_0; t1 += x0_1; t2 += x0_2; tl += y0;
+                    } else {
+                        t0 += x1_0; t1 += x1_1; t2 += x1_2; tl += y1;
+                    }
+                } else {
+                    t0 += x2_0; t1 += x2_1; t2 += x2_2; tl += y2;
+                }
             }
         }
+    }
+}
+
+// Item `li` of entry E: the mapping and path the plan chose for the entry
+// (both branches are wave-uniform).
+template <class F>
+__device__ __forceinline__ void expand_any(CSub &S, CEnt &E, CKer &K, uint32_t li, F &&f) {
+    if (E.flat) {
+        if (E.fast == 2) expand_fast<true, true>(S, E, K, li, f);
+        else if (E.fast) expand_fast<true, false>(S, E, K, li, f);
+        else expand_item<true>(S, E, K, cptr(S.guards), li, f);
+    } else {
+        if (E.fast == 2) expand_fast<false, true>(S, E, K, li, f);
+        else if (E.fast) expand_fast<false, false>(S, E, K, li, f);
+        else expand_item<false>(S, E, K, cptr(S.guards), li, f);
     }
 }
 
@@ -414,8 +488,6 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
         CSub &S = subs[cur.sub];
         CEnt &E = cptr(S.entries)[cur.e];
         CKer &K = *cptr(S.kc);
-        const uint32_t nl = E.n_lchunks;
-        const uint32_t gtile = cur.li / nl, lchunk = cur.li - gtile * nl;
         const uint32_t span = S.khi - S.klo;
         uint32_t bk[RPL];
         uint32_t mn = 0xFFFFFFFFu, mx = 0, n = 0;
@@ -428,8 +500,7 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
             bk[s] = v ? b : 0xFFFFFFFFu;
             if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
         };
-        if (E.fast) expand_fast(S, E, K, gtile, lchunk, on_rec);
-        else expand_item(S, E, K, cptr(S.guards), gtile, lchunk, on_rec);
+        expand_any(S, E, K, cur.li, on_rec);
         block_min_max_sum<EXP_WG>(mn, mx, n, red);
         if (n) {
             if (threadIdx.x == 0) atomicAdd(&res[S.res].records, (unsigned long long)n);
@@ -542,8 +613,6 @@ __global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32
         CSub &S = subs[cur.sub];
         CEnt &E = cptr(S.entries)[cur.e];
         CKer &K = *cptr(S.kc);
-        const uint32_t nl = E.n_lchunks;
-        const uint32_t gtile = cur.li / nl, lchunk = cur.li - gtile * nl;
         const uint32_t span = S.khi - S.klo;
         const uint32_t rwbit = E.rw;
         unsigned long long r[RPL];
@@ -558,8 +627,7 @@ __global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32
             r[s] = ((unsigned long long)((loc << 1) | rwbit) << 32) | id;
             if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
         };
-        if (E.fast) expand_fast(S, E, K, gtile, lchunk, on_rec);
-        else expand_item(S, E, K, cptr(S.guards), gtile, lchunk, on_rec);
+        expand_any(S, E, K, cur.li, on_rec);
         block_min_max_sum<EXP_WG>(mn, mx, n, red);
         uint32_t *gcur = cursor + S.bucket_begin;
         if (n && mx - mn < (uint32_t)BINCAP) {

@@ -254,6 +254,29 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                     for (int v : {C_TX, C_TY, C_BX, C_BY})
                         if (E.row[j][v] <= -(1 << 23) || E.row[j][v] >= (1 << 23)) fast = false;
                 E.fast = fast ? 1u : 0u;
+                if (fast && box > 0) {
+                    // exact index range over the launch and the loop box; when
+                    // every dimension stays inside [0, dim) no record of the
+                    // entry can be out of bounds (fast = 2: no per-record test)
+                    int64_t vlo[NC] = {0}, vhi[NC] = {0};
+                    vhi[C_TX] = (int64_t)bdx - 1; vhi[C_TY] = (int64_t)bdy - 1;
+                    vhi[C_BX] = (int64_t)gdx - 1; vhi[C_BY] = (int64_t)gdy - 1;
+                    for (int l = 0; l < 3; l++) {
+                        vlo[C_L0 + l] = E.lo[l];
+                        vhi[C_L0 + l] = (int64_t)E.lo[l] + (int64_t)E.ext[l] - 1;
+                    }
+                    bool proven = true;
+                    for (int j = 0; j < 3 && proven; j++) {
+                        int64_t mn = E.row[j][C_C0], mx = E.row[j][C_C0];
+                        for (int v : {C_TX, C_TY, C_BX, C_BY, C_L0, C_L1, C_L2}) {
+                            const int64_t cf = E.row[j][v];
+                            mn += cf >= 0 ? cf * vlo[v] : cf * vhi[v];
+                            mx += cf >= 0 ? cf * vhi[v] : cf * vlo[v];
+                        }
+                        proven = mn >= 0 && mx < (int64_t)E.dim[j];
+                    }
+                    if (proven) E.fast = 2u;
+                }
                 // the flattened location row, modulo 2^32: sum over dims of stride * row
                 uint32_t stride = 1;
                 for (int v = 0; v < NC; v++) E.fr[v] = 0;
@@ -269,6 +292,20 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                     E.n_lchunks = (E.box + E.lch - 1) / E.lch;
                 } else {
                     E.lch = 1; E.gt = 1; E.n_lchunks = 0;
+                }
+                E.mg_nl = make_magic(std::max<uint32_t>(E.n_lchunks, 1));
+                E.mg_e1 = make_magic(std::max<uint32_t>(E.ext[1], 1));
+                E.mg_e2 = make_magic(std::max<uint32_t>(E.ext[2], 1));
+                {
+                    // flat mapping when it needs clearly fewer items than the
+                    // thread-major one (few threads: most lanes would idle)
+                    const uint64_t ntg = (nthreads + E.gt - 1) / E.gt;
+                    const uint64_t per = (uint64_t)EXP_WG * E.gt;
+                    const uint64_t thr_items = (uint64_t)E.n_lchunks * ((nthreads + per - 1) / per);
+                    const uint64_t nq = ntg * E.n_lchunks;
+                    const uint64_t flat_items = (nq + EXP_WG - 1) / EXP_WG;
+                    E.flat = (flat_items * 8 < thr_items * 7) ? 1u : 0u;
+                    E.nq = E.flat ? (uint32_t)nq : 0u;
                 }
                 M += box;
                 k.entries.push_back(E);
@@ -290,9 +327,13 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
         for (uint32_t e = 0; e < I.entry_count; e++) {
             DevEntry &E = k.entries[I.entry_begin + e];
             k.entry_items.push_back((uint32_t)items);
-            uint64_t per = (uint64_t)EXP_WG * E.gt;
-            uint64_t gtiles = (nthreads + per - 1) / per;
-            items += (uint64_t)E.n_lchunks * gtiles;
+            if (E.flat) {
+                items += ((uint64_t)E.nq + EXP_WG - 1) / EXP_WG;
+            } else {
+                uint64_t per = (uint64_t)EXP_WG * E.gt;
+                uint64_t gtiles = (nthreads + per - 1) / per;
+                items += (uint64_t)E.n_lchunks * gtiles;
+            }
         }
         k.entry_items.push_back((uint32_t)items);
         if (items >= (1ull << 31)) { msg = "too many work items"; return RV_ERR_TOO_LARGE; }

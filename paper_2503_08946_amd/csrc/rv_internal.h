@@ -79,10 +79,19 @@ struct DevEntry {
     uint32_t guard_count;
     uint32_t lch;              // loop points per lane per work item
     uint32_t gt;               // threads per lane per work item
-    uint32_t n_lchunks;        // work items along the loop box
+    uint32_t n_lchunks;        // loop chunks of lch points along the loop box
+    // Work-item mapping.  flat = 0: the lanes of an item are 256 consecutive
+    // thread groups at one loop chunk (loop counters wave-uniform).  flat = 1
+    // (entries with few threads): lane q of the entry takes thread group
+    // q / n_lchunks at loop chunk q % n_lchunks, so a kernel with a handful
+    // of threads still fills the lanes.
+    uint32_t flat;
+    uint32_t nq;               // flat: thread groups x loop chunks
+    Magic mg_nl, mg_e1, mg_e2; // divisions by n_lchunks, ext[1], ext[2]
     // Fast path (no aux terms, no guards, |tx..by coefficients| < 2^23): the
     // location as one affine row modulo 2^32, loc = fr . (tx,ty,bx,by,l0,l1,l2) +
-    // fr[C_C0] + block * loc_mul; exact for every in-bounds record.
+    // fr[C_C0] + block * loc_mul; exact for every in-bounds record.  2: fast
+    // and every index of the entry is proven inside its dimension.
     uint32_t fast;
     uint32_t ndim;
     uint32_t fr[NC];

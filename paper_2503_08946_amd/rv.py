@@ -100,13 +100,18 @@ class rv_timing(ctypes.Structure):
 
 class rv_kernel_info(ctypes.Structure):
     _fields_ = [("n_instances", u64), ("n_intervals", u32), ("n_subintervals", u32),
-                ("n_chunks", u32), ("n_buckets", u32), ("max_interval_instances", u64)]
+                ("n_chunks", u32), ("n_buckets", u32), ("max_interval_instances", u64),
+                ("n_entries", u32), ("n_flat_entries", u32)]
 
 
 class rv_record(ctypes.Structure):
     _fields_ = [("interval", u32), ("space", i32), ("block", u32), ("array", i32), ("address", i64),
                 ("gthread", u32), ("dyn_phase", u32), ("access", u32), ("lidx", u32),
                 ("loop", i32 * 3), ("is_write", i32)]
+
+
+class rv_tuning(ctypes.Structure):
+    _fields_ = [("target", i32), ("n_candidates", i32), ("candidates", i32 * 8), ("ms", ctypes.c_double * 8)]
 
 
 class rv_job_result(ctypes.Structure):
@@ -140,6 +145,9 @@ def lib():
             "rv_set_timing": [V, ctypes.c_int],
             "rv_get_timing": [V, P(rv_timing), ctypes.c_int],
             "rv_selftest": [ctypes.c_char_p, S],
+            "rv_ctx_get_tuning": [V, P(rv_tuning)],
+            "rv_ctx_set_tuning": [V, P(rv_tuning)],
+            "rv_autotune": [V, P(rv_kernel_desc), S, i32, P(rv_tuning)],
             "rv_server_create": [V, V, S, P(V)],
             "rv_server_destroy": [V],
             "rv_server_submit": [V, V, P(u64)],
@@ -158,7 +166,8 @@ def lib():
 
 EXPORTED = ("rv_validate_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_error", "rv_load_kernel_desc",
             "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_get_witnesses",
-            "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest", "rv_server_create",
+            "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest", "rv_ctx_get_tuning",
+            "rv_ctx_set_tuning", "rv_autotune", "rv_server_create",
             "rv_server_destroy", "rv_server_submit", "rv_server_poll", "rv_server_drain")
 
 
@@ -222,6 +231,14 @@ class Marshalled:
         d.segments, d.n_segments = segs, len(desc.segments)
         self._keep = (arrays, accesses, guards, phases, segs)
         self.desc = d
+
+    def desc_bytes(self) -> bytes:
+        """The description's contents (not its addresses), for fingerprints."""
+        d = self.desc
+        parts = [bytes(d.launch)]
+        for arr, n in zip(self._keep, (d.n_arrays, d.n_accesses, d.n_guards, d.n_phases, d.n_segments)):
+            parts.append(bytes(memoryview(arr))[:n * ctypes.sizeof(arr._type_)])
+        return b"".join(parts)
 
 
 # ------------------------------------------------------------ Python types
@@ -306,6 +323,25 @@ class Kernel:
             pass
 
 
+class Batch:
+    """The marshalled arguments of rv_check_batch for a fixed list of
+    kernels: run() calls the library and leaves the rv_result array in
+    ``out``; results() converts it."""
+
+    def __init__(self, ctx: "Context", ks: Sequence[Kernel]):
+        self.ctx = ctx
+        self.ks = list(ks)
+        n = len(self.ks)
+        self.handles = (ctypes.c_void_p * max(1, n))(*[k.handle for k in self.ks])
+        self.out = (rv_result * max(1, n))()
+
+    def run(self):
+        self.ctx._call(lib().rv_check_batch, self.ctx.handle, self.handles, len(self.ks), self.out)
+
+    def results(self) -> List[Result]:
+        return [_result(self.out[i]) for i in range(len(self.ks))]
+
+
 class Context:
     """A librv context on one device with a caller-owned workspace.
 
@@ -359,11 +395,9 @@ class Context:
         return _result(out)
 
     def check_batch(self, ks: Sequence[Kernel]) -> List[Result]:
-        n = len(ks)
-        arr = (ctypes.c_void_p * max(1, n))(*[k.handle for k in ks])
-        out = (rv_result * max(1, n))()
-        self._call(lib().rv_check_batch, self.handle, arr, n, out)
-        return [_result(out[i]) for i in range(n)]
+        b = Batch(self, ks)
+        b.run()
+        return b.results()
 
     def witnesses(self, k: Kernel, first: int = 0, cap: int = 1 << 16) -> List[Witness]:
         buf = (rv_witness * max(1, cap))()
@@ -393,6 +427,52 @@ class Context:
         out[:, 9:12] = raw["loop"]
         out[:, 12] = raw["is_write"]
         return out
+
+    # ------------------------------------------------------------- tuning
+    @property
+    def target(self) -> int:
+        t = rv_tuning()
+        self._call(lib().rv_ctx_get_tuning, self.handle, ctypes.byref(t))
+        return t.target
+
+    @target.setter
+    def target(self, value: int):
+        t = rv_tuning()
+        t.target = int(value)
+        self._call(lib().rv_ctx_set_tuning, self.handle, ctypes.byref(t))
+
+    def autotune(self, descs, trials: int = 3, cache: Optional[str] = None) -> dict:
+        """Pick the planner target for this context by timing a batched
+        check of ``descs`` under each candidate (rv_autotune).  With
+        ``cache``, a JSON file keyed by the device name and the batch's
+        description fingerprint is read first and written after a
+        measurement."""
+        import hashlib
+        import json
+        import torch
+        ms = [Marshalled(d) for d in descs]
+        fp = hashlib.sha256(b"".join(bytes(m.desc_bytes()) for m in ms)).hexdigest()[:16]
+        key = f"{torch.cuda.get_device_name(self.device)}/{fp}"
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                db = json.load(f)
+            if key in db:
+                self.target = db[key]["target"]
+                return db[key]
+        arr = (rv_kernel_desc * max(1, len(ms)))(*[m.desc for m in ms])
+        t = rv_tuning()
+        self._call(lib().rv_autotune, self.handle, arr, len(ms), int(trials), ctypes.byref(t))
+        rec = {"target": t.target,
+               "ms": {int(t.candidates[i]): t.ms[i] for i in range(t.n_candidates)}}
+        if cache:
+            db = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    db = json.load(f)
+            db[key] = rec
+            with open(cache, "w") as f:
+                json.dump(db, f, indent=1)
+        return rec
 
     def set_timing(self, on: bool):
         self._call(lib().rv_set_timing, self.handle, int(on))

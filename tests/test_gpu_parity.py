@@ -108,6 +108,35 @@ def test_expansion_record_multiset(ctx, desc):
         assert np.array_equal(a, b)
 
 
+def test_expansion_flat_mapping(ctx):
+    # kernels with a few threads and long loops: their entries spread loop
+    # chunks across the lanes of a work item
+    descs = [d for d in RA.batch_kernels(seed=4, count=64)
+             if d.instances_upper_bound() < 3_000_000][:12]
+    b = Builder((3, 1), (1, 1), "three-threads")
+    s = b.array(SHARED, (64, 64))
+    g = b.array(GLOBAL, (4096,))
+    p = b.phase([rw(s, True, aff(l0=1), aff(tx=1, l1=1), loops=((0, 64), (0, 61))),
+                 rw(g, False, aff(tx=1000, l0=1), loops=((0, 37),)),
+                 rw(g, True, aff(l0=3, tx=1), loops=((5, 9),)),
+                 rw(s, False, aff(tx=1), aff(l0=1), loops=((0, 64),), guards=(aff(40, l0=-1),))], False)
+    b.segment([p])
+    descs.append(b.build())
+    n_flat = 0
+    for desc in descs:
+        k = ctx.load(desc)
+        n_flat += k.info().n_flat_entries
+        for iv in range(oracle.n_intervals(desc)):
+            say(f"[expand-flat] {desc.name} interval {iv}")
+            ref = oracle.records(desc, iv)
+            got = ctx.debug_records(k, iv, sorted=False)
+            a = ref[np.lexsort(ref.T[::-1])]
+            b2 = got[np.lexsort(got.T[::-1])]
+            assert np.array_equal(a, b2)
+        compare(ctx, desc, list_all=False)
+    assert n_flat > 0
+
+
 @pytest.mark.parametrize("desc", [K.tiny_fixed(), K.tree_reduction(4, block=512, grid=3),
                                   K.tiled_matmul(grid=2, k_iters=2), K.half_index_global(block=256, grid=8),
                                   K.polynomial_product(64)],
