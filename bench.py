@@ -39,6 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # 8-byte record, the sort + segmented scan reads it once.  The count pass
 # only evaluates instances (no record traffic).
 ALG_BYTES = {"expand": 8.0, "sort_scan": 8.0}
+GROUP_KERNEL = {"fold": "k_fold", "sort_scan": "k_bucket"}
 
 
 def log(*a):
@@ -111,7 +112,7 @@ def traffic_for(kernel_name, records_per_launch):
         return None
 
 
-def roofline_from(stages, n_records_timed):
+def roofline_from(stages, n_records_timed, group_kernel="k_fold"):
     """Dominant kernel (by GPU time, among those with a byte count) and its
     algorithmic bandwidth: bytes per record x records per launch / average
     launch time (HIP events on the stream the kernel runs on)."""
@@ -120,7 +121,7 @@ def roofline_from(stages, n_records_timed):
     avg_ms = stages[dom][0] / launches
     recs_per_launch = n_records_timed / launches
     achieved = ALG_BYTES[dom] * recs_per_launch / (avg_ms * 1e-3) / 1e9
-    kname = {"expand": "k_scatter", "sort_scan": "k_bucket"}[dom]
+    kname = {"expand": "k_scatter", "sort_scan": group_kernel}[dom]
     traffic = traffic_for(kname, int(recs_per_launch))
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -139,6 +140,7 @@ def bench_batch(args, rv, torch):
     descs = RA.batch_kernels(seed=4, count=4096)
     log(f"[bench] generated 4096 kernels in {time.perf_counter() - t0:.1f} s")
     ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
+    ctx.group = args.group
     ks = [ctx.load(d) for d in descs]
     log(f"[bench] loaded 4096 kernels")
     batch = rv.Batch(ctx, ks)
@@ -148,8 +150,11 @@ def bench_batch(args, rv, torch):
     # per-kernel plain launches, one pass over the batch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    single = [ctx.check(k) for k in ks]
+    single = [ctx.check(k) for k in ks] if not args.no_per_kernel else None
     t_single = time.perf_counter() - t0
+    if single is None:
+        batch.run()
+        single = batch.results()
     n_records = sum(r.n_records for r in single)
     log(f"[bench] one rv_check per kernel: {t_single * 1e3:.1f} ms for the batch")
     ctx.timing(reset=True)
@@ -179,12 +184,14 @@ def bench_batch(args, rv, torch):
         "config": {"workload": "4096 random affine 2-D kernels, seed 4, records log-uniform in [1e2, 1e6], "
                                "one batched check per step",
                    "records": n_records, "kernels": len(ks),
+                   "buckets": sum(k.info().n_buckets for k in ks),
                    "kernels_with_conflicts": sum(1 for r in res if r.n_conflicts)},
         "latency_ms": {"p50": round(percentile(lat, 0.5) * 1e3, 3), "p99": round(percentile(lat, 0.99) * 1e3, 3)},
-        "per_kernel_launches": {"ms_per_batch": round(t_single * 1e3, 2), "value": n_records / t_single,
-                                "batched_speedup": round(t_single / (elapsed / args.steps), 2)},
+        "per_kernel_launches": None if args.no_per_kernel else {
+            "ms_per_batch": round(t_single * 1e3, 2), "value": n_records / t_single,
+            "batched_speedup": round(t_single / (elapsed / args.steps), 2)},
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
-        "roofline": roofline_from(stages, n_records * args.steps),
+        "roofline": roofline_from(stages, n_records * args.steps, GROUP_KERNEL[ctx.group]),
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -200,9 +207,10 @@ def bench_serve(args, rv, torch):
     descs = list(RA.serving_stream(seed=5, count=n_warm + n_jobs))
     log(f"[bench] generated {len(descs)} jobs in {time.perf_counter() - t0:.1f} s")
     ctx = rv.Context(0, workspace_bytes=1 << 30)
+    ctx.group = args.group
     ks = [ctx.load(d) for d in descs]
     log(f"[bench] loaded {len(ks)} jobs")
-    srv = rv.Server(ctx, budget_bytes=int(args.budget_gb * (1 << 30)))
+    srv = rv.Server(ctx, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch_records=args.batch_records)
     # closed-loop capacity: the warm-up jobs submitted at once
     t0 = time.perf_counter()
     for k in ks[:n_warm]:
@@ -234,9 +242,17 @@ def bench_serve(args, rv, torch):
     t_end = time.perf_counter()
     done += srv.poll(cap=n_jobs)
     assert len(done) == n_jobs and all(r.status == 0 for r in done)
+    stats = srv.stats()
     srv.close()
     lat = np.array([r.latency_ns for r in done], dtype=np.float64) / 1e6
     queue = np.array([r.t_start_ns - r.t_submit_ns for r in done], dtype=np.float64) / 1e6
+    run = np.array([r.t_done_ns - r.t_start_ns for r in done], dtype=np.float64) / 1e6
+    t_first = min(r.t_submit_ns for r in done)
+    slow = sorted(done, key=lambda r: -r.latency_ns)[:8]
+    for r in slow:
+        log(f"[bench] slow job {r.job_id}: submitted at {(r.t_submit_ns - t_first) / 1e6:.1f} ms, "
+            f"queued {(r.t_start_ns - r.t_submit_ns) / 1e6:.2f} ms, ran {(r.t_done_ns - r.t_start_ns) / 1e6:.2f} ms, "
+            f"{r.result.n_records} records")
     n_records = sum(r.result.n_records for r in done)
     elapsed = t_end - t0
     out = {
@@ -246,14 +262,19 @@ def bench_serve(args, rv, torch):
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "served check: random affine 2-D jobs, seed 5, records log-uniform in "
                                f"[1e3, 1e7], Poisson arrivals at {args.serve_load} x closed-loop capacity, "
-                               f"{args.budget_gb:g} GiB budget",
+                               f"{args.budget_gb:g} GiB budget, batches of at most {args.batch_records} records",
                    "records": n_records, "jobs": n_jobs},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
-                       "queue_p50": round(float(np.percentile(queue, 50)), 3)},
+                       "p90": round(float(np.percentile(lat, 90)), 3),
+                       "max": round(float(lat.max()), 3),
+                       "queue_p50": round(float(np.percentile(queue, 50)), 3),
+                       "queue_p99": round(float(np.percentile(queue, 99)), 3),
+                       "run_p99": round(float(np.percentile(run, 99)), 3)},
         "arrival_rate_jobs_per_s": round(rate, 1),
         "closed_loop_capacity_jobs_per_s": round(cap_jobs, 1),
         "submit_lag_ms_p99": round(float(np.percentile(lag, 99)) * 1e3, 3),
+        "server": stats,
     }
     print(json.dumps(out), flush=True)
 
@@ -267,8 +288,13 @@ def main():
     ap.add_argument("--workspace-gb", type=float, default=16.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-kernel", action="store_true",
+                    help="batch workload: skip the one-rv_check-per-kernel comparison")
+    ap.add_argument("--group", choices=("fold", "sort_scan"), default="fold",
+                    help="per-bucket grouping kernel")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="server budget (serve workload)")
     ap.add_argument("--serve-jobs", type=int, default=10000)
+    ap.add_argument("--batch-records", type=int, default=1 << 26, help="server: records per batch at most")
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / closed-loop capacity")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only copy GIB gibibytes device-to-device (a plain copy kernel of known size, "
@@ -301,6 +327,7 @@ def main():
     descs, wl_text = make_workload(args.workload)
     log(f"[bench] workload {args.workload}: {wl_text}")
     ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
+    ctx.group = args.group
     ks = [ctx.load(d) for d in descs]
     batch = len(ks) > 1
 
@@ -332,7 +359,7 @@ def main():
     p99 = percentile(lat, 0.99)
     per_step = {k: v[0] / args.steps for k, v in stages.items()}
     log("[bench] GPU ms per step by stage: " + ", ".join(f"{k}={v:.3f}" for k, v in per_step.items()))
-    roofline = roofline_from(stages, n_records * args.steps)
+    roofline = roofline_from(stages, n_records * args.steps, GROUP_KERNEL[ctx.group])
     out = {
         "metric": "access records race-checked/sec + % HBM peak; p50/p99 verify latency",
         "value": value,

@@ -195,6 +195,14 @@ typedef struct {
     uint64_t t_submit_ns, t_start_ns, t_done_ns;
 } rv_job_result;
 
+/* Counters of a server since its creation. */
+typedef struct {
+    uint64_t batches;             /* batched checks launched */
+    uint64_t jobs;                /* jobs launched */
+    uint64_t max_batch_jobs;      /* largest batch */
+    uint64_t overlapped_batches;  /* batches launched while the other lane was still running */
+} rv_server_stats;
+
 typedef struct rv_ctx rv_ctx;
 typedef struct rv_kernel rv_kernel;
 typedef struct rv_server rv_server;
@@ -253,22 +261,35 @@ rv_status rv_set_timing(rv_ctx *ctx, int enable);
 rv_status rv_get_timing(rv_ctx *ctx, rv_timing *out, int reset);
 
 /* ---------------------------------------------------------------- tuning
- * The planner's one free parameter is the mean number of records per
- * location bucket (`target`): it sets each interval's bucket width 2^s
- * (s = floor(log2(target x locations / instances)), clamped to [0, 9]), so
- * it trades the number of buckets (per-bucket overhead of the sort + scan)
- * against slices that overflow one on-chip tile.  It applies to kernels
- * loaded after it is set; results do not depend on it. */
+ * Two free parameters, neither of which changes any result:
+ *  - `target`, the planner's mean number of records per location bucket: it
+ *    sets each interval's bucket width 2^s (s = floor(log2(target x
+ *    locations / instances)), clamped to [0, 9]), trading the number of
+ *    buckets (per-bucket overhead) against slices that overflow one on-chip
+ *    tile.  It applies to kernels loaded after it is set.
+ *  - `group`, the per-bucket grouping kernel: both build, per location, the
+ *    summary (min id, max id, min write id, max write id) from which the
+ *    conflict and its witness follow (Section 2.1 step 6 reduced to one
+ *    location); FOLD reaches it with LDS atomics on per-location slots,
+ *    SORT_SCAN by sorting the bucket in LDS and scanning runs of equal
+ *    location.  It applies to the next checks. */
+enum {
+    RV_GROUP_FOLD = 0,       /* fold records into per-location LDS tables with atomics (default) */
+    RV_GROUP_SORT_SCAN = 1   /* LDS counting sort of each bucket + DPP segmented scan */
+};
 typedef struct {
     int32_t target;          /* mean records per bucket, in [64, 4096]; default 2048 */
+    int32_t group;           /* RV_GROUP_*: how a bucket's records are grouped by location */
     int32_t n_candidates;    /* rv_autotune: candidates measured */
-    int32_t candidates[8];
+    int32_t reserved;
+    int32_t candidates[8];   /* rv_autotune: target of each candidate */
+    int32_t cand_group[8];   /* rv_autotune: grouping of each candidate */
     double ms[8];            /* rv_autotune: median wall time of one batched check per candidate */
 } rv_tuning;
 rv_status rv_ctx_get_tuning(rv_ctx *ctx, rv_tuning *out);
-rv_status rv_ctx_set_tuning(rv_ctx *ctx, const rv_tuning *t);   /* reads t->target only */
+rv_status rv_ctx_set_tuning(rv_ctx *ctx, const rv_tuning *t);   /* reads target and group */
 /* Measure a batched check of descs[0..n) (host memory, as rv_load_kernel_desc
- * takes them) under each candidate target, `trials` timed runs after one
+ * takes them) under each candidate (target, group), `trials` timed runs after one
  * warm-up each (host wall time from launch to results on the host, median),
  * keep the fastest in the context and report all of them in *out.  A
  * description that fails to load or check fails the call with its code. */
@@ -279,8 +300,11 @@ rv_status rv_autotune(rv_ctx *ctx, const rv_kernel_desc *descs, size_t n, int32_
  * the caller's device memory of `budget_bytes` (>= 128 MiB) is split into
  * two lanes, each with a HIP stream of its own (default priority); a worker
  * thread gives every idle lane the waiting jobs in arrival order while their
- * records fit the lane's half of the budget, and launches them as one
- * batched check (as rv_check_batch).  Jobs that arrive while both lanes are
+ * records (instance upper bounds) fit the lane's half of the budget and
+ * max_batch_records (0: no limit; a job larger than the limit runs alone),
+ * and launches them as one batched check (as rv_check_batch).  The limit
+ * bounds how long one batch holds its jobs: a job's latency is that of its
+ * batch.  Jobs that arrive while both lanes are
  * busy join the next batch, so one lane's batch runs while the next one is
  * admitted and launched.  Each job's result is bit-identical to rv_check of
  * its kernel alone.
@@ -290,7 +314,8 @@ rv_status rv_autotune(rv_ctx *ctx, const rv_kernel_desc *descs, size_t n, int32_
  * collected for server work, and submitted kernels must stay loaded until
  * their results have been polled.  submit, poll and drain may be called from
  * any host thread. */
-rv_status rv_server_create(rv_ctx *ctx, void *workspace, size_t budget_bytes, rv_server **out);
+rv_status rv_server_create(rv_ctx *ctx, void *workspace, size_t budget_bytes, uint64_t max_batch_records,
+                           rv_server **out);
 /* Finishes the jobs already submitted, stops the worker and frees the
  * server's streams and tables (not the workspace). */
 rv_status rv_server_destroy(rv_server *s);
@@ -301,6 +326,7 @@ rv_status rv_server_submit(rv_server *s, rv_kernel *k, uint64_t *job_id);
 rv_status rv_server_poll(rv_server *s, rv_job_result *out, size_t cap, size_t *n_out);
 /* Wait until every submitted job has finished (RV_ERR_STATE on timeout). */
 rv_status rv_server_drain(rv_server *s, uint64_t timeout_ms);
+rv_status rv_server_get_stats(rv_server *s, rv_server_stats *out);
 
 /* Host-side self test of the library's integer helpers (division by
  * invariant integers, key layout); returns RV_OK or RV_ERR_STATE with a

@@ -49,6 +49,11 @@ struct Lane {
     uint32_t *cursor() const { return reinterpret_cast<uint32_t *>(ws + L.off_cursor); }
     uint32_t *conf() const { return reinterpret_cast<uint32_t *>(ws + L.off_conf); }
     uint32_t *bsum() const { return reinterpret_cast<uint32_t *>(ws + L.off_bsum); }
+    HotArea hot() const {
+        return HotArea{reinterpret_cast<uint32_t *>(ws + L.off_hot_n), reinterpret_cast<uint32_t *>(ws + L.off_hot_list),
+                       reinterpret_cast<uint32_t *>(ws + L.off_hot_done), reinterpret_cast<uint32_t *>(ws + L.off_hot_tab),
+                       (uint32_t)L.cap_hot};
+    }
 };
 
 uint64_t now_ns() {
@@ -67,6 +72,7 @@ struct rv_ctx {
     std::string err;
     bool serving = false;           // a server owns the device work of this context
     int target = DEFAULT_TARGET;    // planner: mean records per bucket for kernels loaded next
+    int group = RV_GROUP_FOLD;      // per-bucket grouping kernel
     // timing
     bool timing = false;
     struct Ev { int stage; hipEvent_t a, b; };
@@ -175,12 +181,18 @@ void run_expand(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t
           [&] { launch_scatter(subs, nsub, items, ln.rec(), ln.cursor(), c->ncu, st); });
 }
 
+// Group by location and judge: LDS-table fold or LDS sort + segmented scan.
+void run_group(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t buckets) {
+    if (c->group == RV_GROUP_SORT_SCAN)
+        launch_bucket(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 0, c->ncu, ln.stream);
+    else
+        launch_fold(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), ln.hot(), c->ncu, ln.stream);
+}
+
 void run_check_chunk(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
     hipStream_t st = ln.stream;
     run_expand(c, ln, subs, nsub, items, buckets);
-    timed(c, st, RV_STAGE_SORT_SCAN, [&] {
-        launch_bucket(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 0, c->ncu, st);
-    });
+    timed(c, st, RV_STAGE_SORT_SCAN, [&] { run_group(c, ln, subs, nsub, buckets); });
     timed(c, st, RV_STAGE_FINISH, [&] {
         launch_finish(subs, nsub, buckets, ln.conf(), ln.d_res, st);
         launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_res, st);
@@ -336,6 +348,7 @@ rv_status lane_collect(rv_ctx *c, Lane &ln, rv_result *out, rv_status *status, s
 struct rv_server {
     rv_ctx *c = nullptr;
     size_t budget = 0;
+    uint64_t batch_records = 0;     // admission stops a batch at this many records (first job always fits)
     Lane lanes[2];
     std::thread worker;
     std::mutex mu;
@@ -347,6 +360,7 @@ struct rv_server {
     std::vector<uint64_t> lane_ids[2], lane_submit[2];
     uint64_t lane_start[2] = {0, 0};
     uint64_t next_id = 1;
+    rv_server_stats stats{};
     bool stop = false;
     std::string err;
 };
@@ -398,7 +412,9 @@ void server_loop(rv_server *s) {
                 const auto &jb = s->pending.front();
                 uint64_t r = 0, b = 0;
                 for (auto &sp : jb.k->subs) { r += jb.k->intervals[sp.interval].P; b += sp.nb; }
-                if (!ks.empty() && (recs + r > ln.L.cap_records || buckets + b > ln.L.cap_buckets)) break;
+                if (!ks.empty() && (recs + r > std::min<uint64_t>(ln.L.cap_records, s->batch_records) ||
+                                    buckets + b > ln.L.cap_buckets))
+                    break;
                 recs += r;
                 buckets += b;
                 ks.push_back(jb.k);
@@ -407,6 +423,10 @@ void server_loop(rv_server *s) {
                 s->pending.pop_front();
             }
             s->lane_start[l] = now_ns();
+            s->stats.batches++;
+            s->stats.jobs += ks.size();
+            s->stats.max_batch_jobs = std::max<uint64_t>(s->stats.max_batch_jobs, ks.size());
+            if (s->lanes[1 - l].busy) s->stats.overlapped_batches++;
             lk.unlock();
             rv_status st = lane_enqueue(c, ln, ks.data(), ks.size());
             lk.lock();
@@ -650,7 +670,7 @@ rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_wit
         const DevSub *subs = k->d_subs + ch.sub_begin;
         const uint32_t nsub = ch.sub_end - ch.sub_begin;
         run_expand(c, ln, subs, nsub, ch.items, ch.buckets);
-        launch_bucket(subs, nsub, ch.buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 0, c->ncu, s);
+        run_group(c, ln, subs, nsub, ch.buckets);
         launch_finish(subs, nsub, ch.buckets, ln.conf(), ln.d_res, s);
         // exclusive scan of per-bucket conflict counts -> list positions (cursor area)
         launch_scan(ln.conf(), ln.cursor(), nullptr, ln.bsum(), ch.buckets, s);
@@ -763,7 +783,8 @@ rv_status rv_get_timing(rv_ctx *c, rv_timing *out, int reset) {
 }
 
 // ------------------------------------------------------------- serving
-rv_status rv_server_create(rv_ctx *c, void *workspace, size_t budget_bytes, rv_server **out) {
+rv_status rv_server_create(rv_ctx *c, void *workspace, size_t budget_bytes, uint64_t max_batch_records,
+                           rv_server **out) {
     if (!c || !workspace || !out) return RV_ERR_INVALID;
     if (c->serving) return fail(c, RV_ERR_STATE, "the context already has a server");
     if (budget_bytes < (128u << 20)) return fail(c, RV_ERR_TOO_LARGE, "server budget below 128 MiB");
@@ -772,13 +793,24 @@ rv_status rv_server_create(rv_ctx *c, void *workspace, size_t budget_bytes, rv_s
     if (!s) return fail(c, RV_ERR_TOO_LARGE, "out of host memory");
     s->c = c;
     s->budget = budget_bytes;
+    s->batch_records = max_batch_records ? max_batch_records : ~0ull;
     const size_t half = (budget_bytes / 2) & ~(size_t)255;
     for (int l = 0; l < 2; l++) {
         Lane &ln = s->lanes[l];
         ln.ws = reinterpret_cast<char *>(workspace) + l * half;
         ln.L = layout_workspace(half);
         hipError_t e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
+        // result slots, pass tables and their pinned staging sized up front
+        // for batches of up to 2^16 passes, so steady-state serving allocates
+        // nothing
+        constexpr size_t kPasses = 1u << 16;
+        if (e == hipSuccess && ln.L.cap_records &&
+            (grow_device(c, ln, ln.d_res, ln.res_cap, kPasses) || grow_device(c, ln, ln.d_subs, ln.subs_cap, kPasses) ||
+             grow_pinned(c, ln, ln.h_up, ln.up_cap, kPasses * sizeof(DevSub)) ||
+             grow_pinned(c, ln, ln.h_down, ln.down_cap, kPasses * sizeof(SubResult))))
+            e = hipErrorOutOfMemory;
         if (e != hipSuccess || !ln.L.cap_records) {
+            for (int q = 0; q <= l; q++) lane_release(s->lanes[q]);
             for (int q = 0; q <= l; q++)
                 if (s->lanes[q].stream) (void)hipStreamDestroy(s->lanes[q].stream);
             delete s;
@@ -825,6 +857,13 @@ rv_status rv_server_drain(rv_server *s, uint64_t timeout_ms) {
     return RV_OK;
 }
 
+rv_status rv_server_get_stats(rv_server *s, rv_server_stats *out) {
+    if (!s || !out) return RV_ERR_INVALID;
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->stats;
+    return RV_OK;
+}
+
 rv_status rv_server_destroy(rv_server *s) {
     if (!s) return RV_ERR_INVALID;
     {
@@ -849,13 +888,16 @@ rv_status rv_ctx_get_tuning(rv_ctx *c, rv_tuning *out) {
     if (!c || !out) return RV_ERR_INVALID;
     memset(out, 0, sizeof *out);
     out->target = c->target;
+    out->group = c->group;
     return RV_OK;
 }
 
 rv_status rv_ctx_set_tuning(rv_ctx *c, const rv_tuning *t) {
     if (!c || !t) return RV_ERR_INVALID;
     if (t->target < 64 || t->target > CAP) return fail(c, RV_ERR_INVALID, "target must be in [64, 4096]");
+    if (t->group != RV_GROUP_FOLD && t->group != RV_GROUP_SORT_SCAN) return fail(c, RV_ERR_INVALID, "unknown grouping");
     c->target = t->target;
+    c->group = t->group;
     return RV_OK;
 }
 
@@ -865,40 +907,52 @@ rv_status rv_autotune(rv_ctx *c, const rv_kernel_desc *descs, size_t n, int32_t 
     c->err.clear();
     HIP_TRY(c, hipSetDevice(c->device));
     static const int cand[] = {512, 1024, 2048, 3072};
-    const int nc = (int)(sizeof cand / sizeof cand[0]);
+    static const int groups[] = {RV_GROUP_FOLD, RV_GROUP_SORT_SCAN};
+    const int nc = (int)(sizeof cand / sizeof cand[0]), ng = (int)(sizeof groups / sizeof groups[0]);
     rv_tuning t;
     memset(&t, 0, sizeof t);
-    t.n_candidates = nc;
+    t.n_candidates = nc * ng;
     rv_status st = RV_OK;
     std::vector<rv_result> res(std::max<size_t>(n, 1));
     int best = -1;
+    const int saved_group = c->group;
     for (int ci = 0; ci < nc && !st; ci++) {
-        t.candidates[ci] = cand[ci];
         std::vector<rv_kernel *> ks;
         for (size_t j = 0; j < n && !st; j++) {
             rv_kernel *k = nullptr;
             st = load_kernel(c, &descs[j], cand[ci], &k);
             if (!st) ks.push_back(k);
         }
-        // host wall time of the whole batched check (launches, device work,
-        // result readback): the quantity the target trades off
-        std::vector<double> ms;
-        for (int r = 0; r <= trials && !st; r++) {    // run 0 warms up
-            const uint64_t t0 = now_ns();
-            st = lane_enqueue(c, c->main, ks.data(), ks.size());
-            if (!st) st = lane_collect(c, c->main, res.data(), nullptr);
-            if (!st && r) ms.push_back((double)(now_ns() - t0) * 1e-6);
+        for (int gi = 0; gi < ng && !st; gi++) {
+            const int q = ci * ng + gi;
+            t.candidates[q] = cand[ci];
+            t.cand_group[q] = groups[gi];
+            c->group = groups[gi];
+            // host wall time of the whole batched check (launches, device
+            // work, result readback): the quantity being traded off
+            std::vector<double> ms;
+            for (int r = 0; r <= trials && !st; r++) {    // run 0 warms up
+                const uint64_t t0 = now_ns();
+                st = lane_enqueue(c, c->main, ks.data(), ks.size());
+                if (!st) st = lane_collect(c, c->main, res.data(), nullptr);
+                if (!st && r) ms.push_back((double)(now_ns() - t0) * 1e-6);
+            }
+            if (st) break;
+            std::sort(ms.begin(), ms.end());
+            t.ms[q] = ms[ms.size() / 2];
+            if (best < 0 || t.ms[q] < t.ms[best]) best = q;
         }
         (void)hipStreamSynchronize(c->main.stream);
         for (auto k : ks) free_kernel(k);
-        if (st) break;
-        std::sort(ms.begin(), ms.end());
-        t.ms[ci] = ms[ms.size() / 2];
-        if (best < 0 || t.ms[ci] < t.ms[best]) best = ci;
     }
+    c->group = saved_group;
     if (st) return st;
-    t.target = best >= 0 ? cand[best] : c->target;
-    c->target = t.target;
+    if (best >= 0) {
+        c->target = t.candidates[best];
+        c->group = t.cand_group[best];
+    }
+    t.target = c->target;
+    t.group = c->group;
     *out = t;
     return RV_OK;
 }

@@ -28,6 +28,8 @@
 // 8 XCDs), so the bucket counters and partially written lines they share stay
 // in one L2.
 
+#include <type_traits>
+
 #include "rv_internal.h"
 
 namespace rv {
@@ -443,18 +445,52 @@ __device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t 
     }
 }
 
-// Item `li` of entry E: the mapping and path the plan chose for the entry
-// (both branches are wave-uniform).
-template <class F>
-__device__ __forceinline__ void expand_any(CSub &S, CEnt &E, CKer &K, uint32_t li, F &&f) {
-    if (E.flat) {
-        if (E.fast == 2) expand_fast<true, true>(S, E, K, li, f);
-        else if (E.fast) expand_fast<true, false>(S, E, K, li, f);
-        else expand_item<true>(S, E, K, cptr(S.guards), li, f);
-    } else {
-        if (E.fast == 2) expand_fast<false, true>(S, E, K, li, f);
-        else if (E.fast) expand_fast<false, false>(S, E, K, li, f);
-        else expand_item<false>(S, E, K, cptr(S.guards), li, f);
+// Expansion variants: FLAT x {proven fast, fast, general}.
+template <int V>
+using Variant = std::integral_constant<int, V>;
+
+template <int V, class F>
+__device__ __forceinline__ void expand_v(Variant<V>, CSub &S, CEnt &E, CKer &K, uint32_t li, F &&f) {
+    constexpr bool FLAT = V >= 3;
+    constexpr int P = V % 3;
+    if constexpr (P == 0) expand_fast<FLAT, true>(S, E, K, li, f);
+    else if constexpr (P == 1) expand_fast<FLAT, false>(S, E, K, li, f);
+    else expand_item<FLAT>(S, E, K, cptr(S.guards), li, f);
+}
+
+// Run body(S, E, K, li, variant) over this workgroup's work items.  Items of
+// one entry are consecutive, so the entry's variant is chosen (and its
+// constants loaded) once per entry rather than once per item.
+template <class Body>
+__device__ __forceinline__ void for_my_items(CSub *subs, uint32_t nsub, uint32_t nitems, Body &&body) {
+    uint32_t w0, w1;
+    my_items(nitems, w0, w1);
+    if (w0 >= w1) return;
+    Cursor cur;
+    seek(subs, nsub, w0, cur);
+    uint32_t w = w0;
+    for (;;) {
+        CSub &S = subs[cur.sub];
+        CEnt &E = cptr(S.entries)[cur.e];
+        CKer &K = *cptr(S.kc);
+        const uint32_t n = min(w1 - w, cur.e_items - cur.li);
+        const uint32_t l0 = cur.li;
+        auto run = [&](auto variant) {
+            for (uint32_t i = 0; i < n; i++) body(S, E, K, l0 + i, variant);
+        };
+        const uint32_t v = (E.flat ? 3u : 0u) + (E.fast == 2 ? 0u : E.fast ? 1u : 2u);
+        switch (v) {
+            case 0: run(Variant<0>{}); break;
+            case 1: run(Variant<1>{}); break;
+            case 2: run(Variant<2>{}); break;
+            case 3: run(Variant<3>{}); break;
+            case 4: run(Variant<4>{}); break;
+            default: run(Variant<5>{}); break;
+        }
+        w += n;
+        if (w >= w1) break;
+        cur.li = l0 + n - 1;
+        advance(subs, cur);
     }
 }
 
@@ -479,15 +515,7 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
     __shared__ uint32_t h[BINCAP];
     __shared__ uint32_t red[3 * (EXP_WG / 64)];
     CSub *subs = cptr(subs_g);
-    uint32_t w0, w1;
-    my_items(nitems, w0, w1);
-    if (w0 >= w1) return;
-    Cursor cur;
-    seek(subs, nsub, w0, cur);
-    for (uint32_t w = w0; w < w1; w++) {
-        CSub &S = subs[cur.sub];
-        CEnt &E = cptr(S.entries)[cur.e];
-        CKer &K = *cptr(S.kc);
+    for_my_items(subs, nsub, nitems, [&](CSub &S, CEnt &E, CKer &K, uint32_t li, auto variant) {
         const uint32_t span = S.khi - S.klo;
         uint32_t bk[RPL];
         uint32_t mn = 0xFFFFFFFFu, mx = 0, n = 0;
@@ -500,23 +528,27 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
             bk[s] = v ? b : 0xFFFFFFFFu;
             if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
         };
-        expand_any(S, E, K, cur.li, on_rec);
+        expand_v(variant, S, E, K, li, on_rec);
         block_min_max_sum<EXP_WG>(mn, mx, n, red);
         if (n) {
             if (threadIdx.x == 0) atomicAdd(&res[S.res].records, (unsigned long long)n);
             uint32_t *gc = counts + S.bucket_begin;
-            if (mx - mn < (uint32_t)BINCAP) {
-                const uint32_t R = mx - mn + 1;
-                for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
-                __syncthreads();
+            if (mx - mn < (uint32_t)(BINCAP * BINWIN)) {
+                // LDS bins over windows of BINCAP buckets of the tile's range
+                for (uint32_t w = mn;; w += BINCAP) {
+                    const uint32_t R = min((uint32_t)BINCAP, mx - w + 1);
+                    for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
+                    __syncthreads();
 #pragma unroll
-                for (int s = 0; s < RPL; s++) lds_rank(h, bk[s] - mn, bk[s] != 0xFFFFFFFFu);
-                __syncthreads();
-                for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) {
-                    const uint32_t c = h[i];
-                    if (c) atomicAdd(&gc[mn + i], c);
+                    for (int s = 0; s < RPL; s++) lds_rank(h, bk[s] - w, bk[s] - w < R);
+                    __syncthreads();
+                    for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) {
+                        const uint32_t c = h[i];
+                        if (c) atomicAdd(&gc[w + i], c);
+                    }
+                    __syncthreads();
+                    if (mx - w < (uint32_t)BINCAP) break;
                 }
-                __syncthreads();
             } else {
 #pragma unroll
                 for (int s = 0; s < RPL; s++) {
@@ -533,8 +565,7 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
                 }
             }
         }
-        if (w + 1 < w1) advance(subs, cur);
-    }
+    });
 }
 
 // ------------------------------------------------------------------ scans
@@ -597,22 +628,14 @@ __global__ void __launch_bounds__(SCAN_WG) k_scan_down(const uint32_t *__restric
 }
 
 // -------------------------------------------------------------- expansion
-__global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32_t nsub, uint32_t nitems,
+__global__ void __launch_bounds__(EXP_WG) __attribute__((amdgpu_waves_per_eu(5))) k_scatter(const DevSub *subs_g, uint32_t nsub, uint32_t nitems,
                                                      unsigned long long *__restrict__ rec,
                                                      uint32_t *__restrict__ cursor) {
     __shared__ uint32_t h[BINCAP];
     __shared__ uint32_t gb[BINCAP];
     __shared__ uint32_t red[3 * (EXP_WG / 64)];
     CSub *subs = cptr(subs_g);
-    uint32_t w0, w1;
-    my_items(nitems, w0, w1);
-    if (w0 >= w1) return;
-    Cursor cur;
-    seek(subs, nsub, w0, cur);
-    for (uint32_t w = w0; w < w1; w++) {
-        CSub &S = subs[cur.sub];
-        CEnt &E = cptr(S.entries)[cur.e];
-        CKer &K = *cptr(S.kc);
+    for_my_items(subs, nsub, nitems, [&](CSub &S, CEnt &E, CKer &K, uint32_t li, auto variant) {
         const uint32_t span = S.khi - S.klo;
         const uint32_t rwbit = E.rw;
         unsigned long long r[RPL];
@@ -627,32 +650,37 @@ __global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32
             r[s] = ((unsigned long long)((loc << 1) | rwbit) << 32) | id;
             if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
         };
-        expand_any(S, E, K, cur.li, on_rec);
+        expand_v(variant, S, E, K, li, on_rec);
         block_min_max_sum<EXP_WG>(mn, mx, n, red);
         uint32_t *gcur = cursor + S.bucket_begin;
-        if (n && mx - mn < (uint32_t)BINCAP) {
+        if (n && mx - mn < (uint32_t)(BINCAP * BINWIN)) {
             // Rank every record inside its bucket for this tile, reserve one run
             // per bucket in the chunk, write each record to run base + rank.
             // Waves whose records share a bucket get consecutive ranks, so the
-            // stores of a wave slot are one contiguous 512-byte run.
-            const uint32_t R = mx - mn + 1;
-            for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
-            __syncthreads();
-            uint32_t rk[RPL];
+            // stores of a wave slot are one contiguous 512-byte run.  A tile
+            // spanning more than BINCAP buckets takes them in windows.
+            for (uint32_t w = mn;; w += BINCAP) {
+                const uint32_t R = min((uint32_t)BINCAP, mx - w + 1);
+                for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
+                __syncthreads();
+                uint32_t rk[RPL];
 #pragma unroll
-            for (int s = 0; s < RPL; s++) rk[s] = lds_rank(h, bk[s] - mn, bk[s] != 0xFFFFFFFFu);
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) {
-                const uint32_t c = h[i];
-                if (c) gb[i] = atomicAdd(&gcur[mn + i], c);
+                for (int s = 0; s < RPL; s++) rk[s] = lds_rank(h, bk[s] - w, bk[s] - w < R);
+                __syncthreads();
+                for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) {
+                    const uint32_t c = h[i];
+                    if (c) gb[i] = atomicAdd(&gcur[w + i], c);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < RPL; s++)
+                    if (bk[s] - w < R) rec[gb[bk[s] - w] + rk[s]] = r[s];
+                __syncthreads();
+                if (mx - w < (uint32_t)BINCAP) break;
             }
-            __syncthreads();
-#pragma unroll
-            for (int s = 0; s < RPL; s++)
-                if (bk[s] != 0xFFFFFFFFu) rec[gb[bk[s] - mn] + rk[s]] = r[s];
-            __syncthreads();
         } else if (n) {
-            // a tile spread over more than BINCAP buckets: reserve per record
+            // a tile spread over more than BINCAP * BINWIN buckets (so many
+            // that their counters rarely collide): reserve per record
 #pragma unroll
             for (int s = 0; s < RPL; s++) {
                 const bool v = bk[s] != 0xFFFFFFFFu;
@@ -670,8 +698,7 @@ __global__ void __launch_bounds__(EXP_WG) k_scatter(const DevSub *subs_g, uint32
                 if (v) rec[pos] = r[s];
             }
         }
-        if (w + 1 < w1) advance(subs, cur);
-    }
+    });
 }
 
 // ------------------------------------------------ sort + segmented scan
@@ -723,7 +750,6 @@ __device__ __forceinline__ void seg_combine(Seg &acc, const Seg &b) {   // acc <
     acc.f |= b.f;
 }
 
-constexpr int TBL = 1 << SMAX;
 constexpr int TPER = TBL / BKT_WG;           // table entries per thread
 static_assert(TBL % BKT_WG == 0, "table split");
 
@@ -983,6 +1009,281 @@ __global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *subs_g, uint32_
     }
 }
 
+// Grouping without sorting.  Each location of a bucket owns one slot of four
+// LDS tables (min id, max id, min write id, max write id + 1: the summary the
+// segmented scan produces), and records are folded into their slot with LDS
+// atomics.  A lane first merges consecutive records of equal location in
+// registers (it loads a contiguous run), so a run of one location costs one
+// set of atomics.  The judge and the witness order (location order, from a
+// prefix sum of per-lane counts) match the sorting path exactly.
+//
+// k_fold gives each workgroup a contiguous range of buckets.  It reads the
+// range's counts 256 at a time, lists the non-empty ones in LDS (a bucket of
+// more than HOT records, a hot location, goes to the hot list for k_hot), and
+// while it folds one bucket the records of the next are already loading into
+// registers.
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Records of a lane's contiguous run of one slice: slice of n records, lane
+// `me` of NL takes [me * rpl, me * rpl + m).
+template <int NL>
+struct Run {
+    uint32_t rpl, m;
+    unsigned long long x[FOLD_RPL];
+};
+
+template <int NL>
+__device__ __forceinline__ void run_load(Run<NL> &r, const unsigned long long *__restrict__ src, uint32_t n,
+                                         uint32_t me) {
+    r.rpl = (n + NL - 1) / NL;
+    const uint32_t r0 = me * r.rpl;
+    r.m = r0 < n ? min(r.rpl, n - r0) : 0u;
+    const unsigned long long *p = src + r0;
+#pragma unroll
+    for (int i = 0; i < FOLD_RPL; i++) r.x[i] = (uint32_t)i < r.m ? p[i] : 0ull;
+}
+
+// Fold one lane's run into the tables: consecutive records of equal location
+// are merged in registers, one set of atomics per merged run.
+template <int NL>
+__device__ __forceinline__ void run_fold(const Run<NL> &r, uint32_t lo, uint32_t *t_mn, uint32_t *t_mx,
+                                         uint32_t *t_mnw, uint32_t *t_mxw1) {
+    Seg cur{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+    uint32_t pk = 0xFFFFu;
+    auto flush = [&](uint32_t k) {
+        atomicMin(&t_mn[k], cur.mn);
+        atomicMax(&t_mx[k], cur.mx);
+        if (cur.mxw1) {
+            atomicMin(&t_mnw[k], cur.mnw);
+            atomicMax(&t_mxw1[k], cur.mxw1);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < FOLD_RPL; j++) {
+        if ((uint32_t)j < r.m) {
+            const uint32_t hi = (uint32_t)(r.x[j] >> 32);
+            const uint32_t k = (hi >> 1) - lo;
+            if (k != pk) {
+                if (pk != 0xFFFFu) flush(pk);
+                cur.mn = 0xFFFFFFFFu; cur.mx = 0; cur.mnw = 0xFFFFFFFFu; cur.mxw1 = 0;
+                pk = k;
+            }
+            seg_add(cur, (uint32_t)r.x[j], hi & 1u);
+        }
+    }
+    if (pk != 0xFFFFu) flush(pk);
+}
+
+// Fold records [r_begin, r_end) of one bucket in slices of NL * FOLD_RPL.
+template <int NL>
+__device__ __forceinline__ void fold_records(const unsigned long long *__restrict__ src, uint32_t r_begin,
+                                             uint32_t r_end, uint32_t lo, uint32_t me, uint32_t *t_mn,
+                                             uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1) {
+    for (uint32_t slice = r_begin; slice < r_end; slice += NL * FOLD_RPL) {
+        Run<NL> r;
+        run_load(r, src + slice, min((uint32_t)(NL * FOLD_RPL), r_end - slice), me);
+        run_fold(r, lo, t_mn, t_mx, t_mnw, t_mxw1);
+    }
+}
+
+// The pass a bucket belongs to (bucket begins are increasing).
+__device__ __forceinline__ uint32_t sub_of_bucket(CSub *subs, uint32_t nsub, uint32_t b) {
+    uint32_t lo_s = 0, hi_s = nsub;
+    while (hi_s - lo_s > 1) {
+        const uint32_t mid = (lo_s + hi_s) >> 1;
+        if (subs[mid].bucket_begin <= b) lo_s = mid; else hi_s = mid;
+    }
+    return lo_s;
+}
+
+// Judge every location of a folded bucket and write its witnesses in
+// location order at the start of the bucket's region; returns the count.
+__device__ __forceinline__ uint32_t judge_tables(const uint32_t *t_mn, const uint32_t *t_mx, const uint32_t *t_mnw,
+                                                 const uint32_t *t_mxw1, uint32_t width, uint32_t lo, Magic mgM,
+                                                 uint32_t *wout, uint32_t *red) {
+    constexpr int TP = TBL / BKT_WG;
+    const uint32_t t = threadIdx.x;
+    bool c[TP];
+    Seg e[TP];
+    uint32_t second[TP], srw[TP];
+    uint32_t nc = 0;
+#pragma unroll
+    for (int i = 0; i < TP; i++) {
+        const uint32_t k = t * TP + i;
+        c[i] = false; second[i] = 0; srw[i] = 0;
+        e[i] = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+        if (k < width) {
+            e[i].mn = t_mn[k]; e[i].mx = t_mx[k]; e[i].mnw = t_mnw[k]; e[i].mxw1 = t_mxw1[k];
+            if (e[i].mn != 0xFFFFFFFFu) c[i] = judge(e[i], mgM, second[i], srw[i]);
+        }
+        nc += c[i] ? 1u : 0u;
+    }
+    uint32_t total;
+    uint32_t pos = block_excl_add<BKT_WG>(nc, red, &total);   // its barriers also order the table reads
+    if (total) {                                               // before anyone clears the tables again
+#pragma unroll
+        for (int i = 0; i < TP; i++)
+            if (c[i]) put_witness(wout, pos++, lo + t * TP + i, e[i], second[i], srw[i]);
+    }
+    return total;
+}
+
+__global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t nsub, uint32_t nbuckets,
+                                                  unsigned long long *__restrict__ rec,
+                                                  const uint32_t *__restrict__ starts,
+                                                  const uint32_t *__restrict__ counts, uint32_t *__restrict__ conf,
+                                                  HotArea hot) {
+    __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
+    __shared__ uint32_t l_b[BKT_WG], l_cnt[BKT_WG], l_st[BKT_WG], l_hot[BKT_WG];
+    __shared__ uint32_t red[BKT_WG / 64];
+    CSub *subs = cptr(subs_g);
+    const uint32_t t = threadIdx.x;
+    uint32_t b0, b1;
+    my_items(nbuckets, b0, b1);
+    for (uint32_t base = b0; base < b1; base += BKT_WG) {
+        // --- list this group's non-empty buckets (in order) and the hot ones
+        const uint32_t mb = base + t;
+        const bool inr = mb < b1;
+        const uint32_t c = inr ? counts[mb] : 0u;
+        const bool take = c != 0 && c <= HOT;
+        const bool is_hot = c > HOT;
+        if (inr && !take) conf[mb] = 0;
+        uint32_t both;     // listed buckets in the low half, hot ones in the high half
+        const uint32_t pos = block_excl_add<BKT_WG>((take ? 1u : 0u) | (is_hot ? 0x10000u : 0u), red, &both);
+        const uint32_t nl = both & 0xFFFFu, nh = both >> 16;
+        if (take) { l_b[pos & 0xFFFFu] = mb; l_cnt[pos & 0xFFFFu] = c; l_st[pos & 0xFFFFu] = starts[mb]; }
+        if (is_hot) {
+            const uint32_t slot = atomicAdd(hot.n, 1u);
+            l_hot[pos >> 16] = slot;
+            if (slot < hot.cap) { hot.list[slot] = mb; hot.done[slot] = 0; }
+        }
+        __syncthreads();
+        for (uint32_t j = 0; j < nh; j++) {     // clear the hot buckets' summaries
+            const uint32_t slot = l_hot[j];
+            if (slot < hot.cap) {
+                uint32_t *g = hot.tab + (size_t)slot * 4 * TBL;
+                for (uint32_t k = t; k < 4u * TBL; k += BKT_WG) g[k] = (k / TBL) % 2 == 0 ? 0xFFFFFFFFu : 0u;
+            }
+        }
+        // --- fold the listed buckets; slice 0 of the next one loads meanwhile
+        Run<BKT_WG> cur, nxt;
+        if (nl) run_load(cur, rec + l_st[0], min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[0]), t);
+        for (uint32_t i = 0; i < nl; i++) {
+            const uint32_t b = l_b[i], cnt = l_cnt[i], start = l_st[i];
+            CSub &S = subs[sub_of_bucket(subs, nsub, b)];
+            const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
+            const uint32_t width = min(1u << S.s, S.khi - lo);
+#pragma unroll
+            for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
+                const uint32_t k = t * (TBL / BKT_WG) + k2;
+                t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+            }
+            __syncthreads();
+            if (i + 1 < nl) run_load(nxt, rec + l_st[i + 1], min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[i + 1]), t);
+            run_fold(cur, lo, t_mn, t_mx, t_mnw, t_mxw1);
+            if (cnt > (uint32_t)(BKT_WG * FOLD_RPL)) fold_records<BKT_WG>(rec + start, BKT_WG * FOLD_RPL, cnt, lo, t, t_mn, t_mx, t_mnw, t_mxw1);
+            __syncthreads();
+            const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
+                                                reinterpret_cast<uint32_t *>(rec + start), red);
+            if (t == 0) conf[b] = total;
+            cur = nxt;
+        }
+        __syncthreads();     // the list is rebuilt for the next group
+    }
+}
+
+// Hot buckets: part q of a bucket (records [q * HOT, (q + 1) * HOT)) is
+// folded by one workgroup in LDS and merged into the bucket's summary in
+// global memory with atomics; the workgroup that completes the last part
+// judges the bucket and writes its witnesses.
+__global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t nsub,
+                                                 unsigned long long *__restrict__ rec,
+                                                 const uint32_t *__restrict__ starts,
+                                                 const uint32_t *__restrict__ counts, uint32_t *__restrict__ conf,
+                                                 HotArea hot) {
+    __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
+    __shared__ uint32_t red[BKT_WG / 64];
+    __shared__ uint32_t last;
+    CSub *subs = cptr(subs_g);
+    const uint32_t t = threadIdx.x;
+    const uint32_t nh = min(*hot.n, hot.cap);
+    uint32_t u = 0;      // running part index over the list
+    for (uint32_t i = 0; i < nh; i++) {
+        const uint32_t b = hot.list[i];
+        const uint32_t cnt = counts[b];
+        const uint32_t parts = (cnt + HOT - 1) / HOT;
+        // parts u .. u + parts - 1 of the list go to workgroups round-robin
+        uint32_t q = (blockIdx.x + gridDim.x - u % gridDim.x) % gridDim.x;
+        for (; q < parts; q += gridDim.x) {
+            const uint32_t start = starts[b];
+            CSub &S = subs[sub_of_bucket(subs, nsub, b)];
+            const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
+            const uint32_t width = min(1u << S.s, S.khi - lo);
+#pragma unroll
+            for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
+                const uint32_t k = t + k2 * BKT_WG;
+                t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+            }
+            __syncthreads();
+            fold_records<BKT_WG>(rec + start, q * HOT, min(cnt, (q + 1) * HOT), lo, t, t_mn, t_mx, t_mnw, t_mxw1);
+            __syncthreads();
+            uint32_t *g = hot.tab + (size_t)i * 4 * TBL;
+            for (uint32_t k = t; k < width; k += BKT_WG) {
+                if (t_mn[k] != 0xFFFFFFFFu) {
+                    atomicMin(&g[k], t_mn[k]);
+                    atomicMax(&g[TBL + k], t_mx[k]);
+                    if (t_mxw1[k]) {
+                        atomicMin(&g[2 * TBL + k], t_mnw[k]);
+                        atomicMax(&g[3 * TBL + k], t_mxw1[k]);
+                    }
+                }
+            }
+            __threadfence();
+            __syncthreads();
+            if (t == 0) last = (atomicAdd(&hot.done[i], 1u) == parts - 1) ? 1u : 0u;
+            __syncthreads();
+            if (last) {
+                __threadfence();
+                const Magic mgM = ldm(S.mgM);
+                bool cf[TBL / BKT_WG];
+                Seg e[TBL / BKT_WG];
+                uint32_t second[TBL / BKT_WG], srw[TBL / BKT_WG];
+                uint32_t nc = 0;
+#pragma unroll
+                for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
+                    const uint32_t k = t * (TBL / BKT_WG) + k2;
+                    cf[k2] = false; second[k2] = 0; srw[k2] = 0;
+                    e[k2] = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                    if (k < width) {
+                        e[k2].mn = __hip_atomic_load(&g[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        e[k2].mx = __hip_atomic_load(&g[TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        e[k2].mnw = __hip_atomic_load(&g[2 * TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        e[k2].mxw1 = __hip_atomic_load(&g[3 * TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (e[k2].mn != 0xFFFFFFFFu) cf[k2] = judge(e[k2], mgM, second[k2], srw[k2]);
+                    }
+                    nc += cf[k2] ? 1u : 0u;
+                }
+                uint32_t total;
+                uint32_t pos = block_excl_add<BKT_WG>(nc, red, &total);
+                if (total) {
+                    uint32_t *wout = reinterpret_cast<uint32_t *>(rec + start);
+#pragma unroll
+                    for (int k2 = 0; k2 < TBL / BKT_WG; k2++)
+                        if (cf[k2]) put_witness(wout, pos++, lo + t * (TBL / BKT_WG) + k2, e[k2], second[k2], srw[k2]);
+                }
+                if (t == 0) conf[b] = total;
+            }
+            __syncthreads();
+        }
+        u += parts;
+    }
+}
+
 // ------------------------------------------------------------- finishing
 __global__ void k_finish(const DevSub *subs_g, uint32_t nsub, size_t nbuckets, const uint32_t *__restrict__ conf,
                          SubResult *__restrict__ res) {
@@ -1108,6 +1409,20 @@ void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigne
     if (g > nbuckets) g = nbuckets;
     hipLaunchKernelGGL(k_bucket, dim3((unsigned)g), dim3(BKT_WG), 0, st, subs, nsub, (uint32_t)nbuckets, rec,
                        starts, counts, conf, debug_sorted);
+}
+
+void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
+                 const uint32_t *starts, const uint32_t *counts, uint32_t *conf, HotArea hot, unsigned ncu,
+                 hipStream_t st) {
+    if (!nbuckets) return;
+    static const unsigned occ = occupancy(k_fold, BKT_WG, 4);
+    static const unsigned occ_hot = occupancy(k_hot, BKT_WG, 4);
+    launch_fill_u32(hot.n, 1, 0u, st);
+    // at least 64 buckets per wave-block of a workgroup's range
+    const uint64_t groups = (nbuckets + 255) / 256;
+    hipLaunchKernelGGL(k_fold, dim3(persistent_grid(groups, ncu, occ)), dim3(BKT_WG), 0, st, subs, nsub,
+                       (uint32_t)nbuckets, rec, starts, counts, conf, hot);
+    hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
 }
 
 void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf, SubResult *res,

@@ -364,35 +364,41 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
 }
 
 WorkspaceLayout layout_workspace(size_t bytes) {
-    WorkspaceLayout L{};
     const size_t reserve = 1 << 20;
-    if (bytes < reserve + (size_t)TILE * 8 * 4) return L;
-    // records : buckets = 8 B : 16 B per 256 records
-    size_t R = (size_t)(((long double)(bytes - reserve)) / (8.0L + 16.0L / 256.0L));
-    R = std::min<size_t>(R, (size_t)0xFFF00000u);
-    size_t BC = std::max<size_t>((size_t)NBMAX, R / 256);
+    if (bytes < reserve + (size_t)TILE * 8 * 4) return WorkspaceLayout{};
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t off = al(R * 8);
-    L.off_counts = off; off = al(off + BC * 4);
-    L.off_starts = off; off = al(off + BC * 4);
-    L.off_cursor = off; off = al(off + BC * 4);
-    L.off_conf = off; off = al(off + BC * 4);
-    L.off_bsum = off; off = al(off + scan_bsum_words(BC) * 4);
-    if (off > bytes) {   // shrink the record area to fit exactly
-        size_t over = off - bytes;
-        size_t dr = (over + 7) / 8 + 64;
-        if (dr >= R) return WorkspaceLayout{};
-        R -= dr;
-        off = al(R * 8);
+    auto place = [&](size_t R) {
+        WorkspaceLayout L{};
+        const size_t BC = std::max<size_t>((size_t)NBMAX, R / 256);
+        const size_t H = R / HOT + 1;    // at most this many buckets exceed HOT records
+        size_t off = al(R * 8);
         L.off_counts = off; off = al(off + BC * 4);
         L.off_starts = off; off = al(off + BC * 4);
         L.off_cursor = off; off = al(off + BC * 4);
         L.off_conf = off; off = al(off + BC * 4);
         L.off_bsum = off; off = al(off + scan_bsum_words(BC) * 4);
+        L.off_hot_n = off; off = al(off + 4);
+        L.off_hot_list = off; off = al(off + H * 4);
+        L.off_hot_done = off; off = al(off + H * 4);
+        L.off_hot_tab = off; off = al(off + H * 4 * TBL * 4);
+        L.cap_records = R;
+        L.cap_buckets = BC;
+        L.cap_hot = H;
+        L.bytes = off;
+        return L;
+    };
+    // per record: 8 B, bucket arrays 16 B per 256 records, hot tables 8 KiB per HOT records
+    const long double per = 8.0L + 16.0L / 256.0L + (16.0L * TBL + 8.0L) / (long double)HOT;
+    size_t R = (size_t)(((long double)(bytes - reserve)) / per);
+    R = std::min<size_t>(R, (size_t)0xFFF00000u);
+    WorkspaceLayout L = place(R);
+    while (L.bytes > bytes) {   // shrink the record area until it fits
+        const size_t over = L.bytes - bytes;
+        const size_t dr = (over + 7) / 8 + 64;
+        if (dr >= R) return WorkspaceLayout{};
+        R -= dr;
+        L = place(R);
     }
-    L.cap_records = R;
-    L.cap_buckets = BC;
-    L.bytes = off;
     return L;
 }
 

@@ -16,13 +16,17 @@ namespace rv {
 constexpr int EXP_WG = 256;              // expansion workgroup (4 waves)
 constexpr int RPL = 16;                  // records per lane per work item
 constexpr int TILE = EXP_WG * RPL;       // records per expansion work item
-constexpr int BINCAP = 2048;             // buckets one expansion tile may span on the LDS path
+constexpr int BINCAP = 2048;             // LDS bins of one expansion tile (one window of buckets)
+constexpr int BINWIN = 8;                // windows a tile may take on the LDS path
 constexpr int NBMAX = 1 << 20;           // location buckets per key-range pass
 constexpr int SMAX = 9;                  // a bucket spans at most 2^SMAX locations
 constexpr int BKT_WG = 256;              // sort + scan workgroup (4 waves)
 constexpr int BKT_RPL = 16;              // records per lane in one on-chip slice
 constexpr int CAP = BKT_WG * BKT_RPL;    // records per on-chip slice
 constexpr int DEFAULT_TARGET = 2048;     // planner: mean records per bucket
+constexpr int FOLD_RPL = 8;              // fold: records per lane in one slice
+constexpr uint32_t HOT = 1u << 15;       // fold: buckets above this many records are split over workgroups
+constexpr int TBL = 1 << SMAX;           // locations of one bucket (LDS table entries)
 
 static_assert((1 << SMAX) % BKT_WG == 0, "bucket locations split evenly over sort+scan threads");
 static_assert(BINCAP % EXP_WG == 0, "tile bins split evenly over expansion threads");
@@ -172,6 +176,10 @@ struct WorkspaceLayout {
     size_t cap_records = 0;        // records per chunk
     size_t cap_buckets = 0;        // buckets per chunk
     size_t off_counts = 0, off_starts = 0, off_cursor = 0, off_conf = 0, off_bsum = 0;
+    // hot buckets (more than HOT records): their list, its length, a
+    // completion counter and a four-table location summary per entry
+    size_t cap_hot = 0;
+    size_t off_hot_n = 0, off_hot_list = 0, off_hot_done = 0, off_hot_tab = 0;
     size_t bytes = 0;
 };
 
@@ -248,6 +256,13 @@ void launch_scatter(const DevSub *subs, uint32_t nsub, uint64_t items, unsigned 
 void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
                    const uint32_t *starts, const uint32_t *counts, uint32_t *conf, int debug_sorted,
                    unsigned ncu, hipStream_t st);
+struct HotArea {
+    uint32_t *n, *list, *done, *tab;
+    uint32_t cap;
+};
+void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
+                 const uint32_t *starts, const uint32_t *counts, uint32_t *conf, HotArea hot, unsigned ncu,
+                 hipStream_t st);
 void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf,
                    SubResult *res, hipStream_t st);
 void launch_first(const DevSub *subs, uint32_t nsub, const unsigned long long *rec,

@@ -111,7 +111,15 @@ class rv_record(ctypes.Structure):
 
 
 class rv_tuning(ctypes.Structure):
-    _fields_ = [("target", i32), ("n_candidates", i32), ("candidates", i32 * 8), ("ms", ctypes.c_double * 8)]
+    _fields_ = [("target", i32), ("group", i32), ("n_candidates", i32), ("reserved", i32),
+                ("candidates", i32 * 8), ("cand_group", i32 * 8), ("ms", ctypes.c_double * 8)]
+
+
+GROUPS = {"fold": 0, "sort_scan": 1}
+
+
+class rv_server_stats(ctypes.Structure):
+    _fields_ = [("batches", u64), ("jobs", u64), ("max_batch_jobs", u64), ("overlapped_batches", u64)]
 
 
 class rv_job_result(ctypes.Structure):
@@ -148,11 +156,12 @@ def lib():
             "rv_ctx_get_tuning": [V, P(rv_tuning)],
             "rv_ctx_set_tuning": [V, P(rv_tuning)],
             "rv_autotune": [V, P(rv_kernel_desc), S, i32, P(rv_tuning)],
-            "rv_server_create": [V, V, S, P(V)],
+            "rv_server_create": [V, V, S, u64, P(V)],
             "rv_server_destroy": [V],
             "rv_server_submit": [V, V, P(u64)],
             "rv_server_poll": [V, P(rv_job_result), S, P(S)],
             "rv_server_drain": [V, u64],
+            "rv_server_get_stats": [V, P(rv_server_stats)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -168,7 +177,7 @@ EXPORTED = ("rv_validate_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_erro
             "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_get_witnesses",
             "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest", "rv_ctx_get_tuning",
             "rv_ctx_set_tuning", "rv_autotune", "rv_server_create",
-            "rv_server_destroy", "rv_server_submit", "rv_server_poll", "rv_server_drain")
+            "rv_server_destroy", "rv_server_submit", "rv_server_poll", "rv_server_drain", "rv_server_get_stats")
 
 
 # -------------------------------------------------------------- marshalling
@@ -438,7 +447,22 @@ class Context:
     @target.setter
     def target(self, value: int):
         t = rv_tuning()
+        self._call(lib().rv_ctx_get_tuning, self.handle, ctypes.byref(t))
         t.target = int(value)
+        self._call(lib().rv_ctx_set_tuning, self.handle, ctypes.byref(t))
+
+    @property
+    def group(self) -> str:
+        """Per-bucket grouping kernel: "fold" or "sort_scan"."""
+        t = rv_tuning()
+        self._call(lib().rv_ctx_get_tuning, self.handle, ctypes.byref(t))
+        return {v: k for k, v in GROUPS.items()}[t.group]
+
+    @group.setter
+    def group(self, value: str):
+        t = rv_tuning()
+        self._call(lib().rv_ctx_get_tuning, self.handle, ctypes.byref(t))
+        t.group = GROUPS[value]
         self._call(lib().rv_ctx_set_tuning, self.handle, ctypes.byref(t))
 
     def autotune(self, descs, trials: int = 3, cache: Optional[str] = None) -> dict:
@@ -458,12 +482,14 @@ class Context:
                 db = json.load(f)
             if key in db:
                 self.target = db[key]["target"]
+                self.group = db[key]["group"]
                 return db[key]
         arr = (rv_kernel_desc * max(1, len(ms)))(*[m.desc for m in ms])
         t = rv_tuning()
         self._call(lib().rv_autotune, self.handle, arr, len(ms), int(trials), ctypes.byref(t))
-        rec = {"target": t.target,
-               "ms": {int(t.candidates[i]): t.ms[i] for i in range(t.n_candidates)}}
+        names = {v: k for k, v in GROUPS.items()}
+        rec = {"target": t.target, "group": names[t.group],
+               "ms": {f"{t.candidates[i]}/{names[t.cand_group[i]]}": t.ms[i] for i in range(t.n_candidates)}}
         if cache:
             db = {}
             if os.path.exists(cache):
@@ -503,7 +529,7 @@ class Server:
     ``workspace``: a torch uint8 CUDA tensor of the budget, or None to
     allocate ``budget_bytes``."""
 
-    def __init__(self, ctx: Context, budget_bytes: int = 1 << 30, workspace=None):
+    def __init__(self, ctx: Context, budget_bytes: int = 1 << 30, workspace=None, max_batch_records: int = 1 << 26):
         import torch
         self.ctx = ctx
         if workspace is None:
@@ -511,7 +537,7 @@ class Server:
         self.workspace = workspace
         h = ctypes.c_void_p()
         ctx._call(lib().rv_server_create, ctx.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-                  ctypes.byref(h))
+                  int(max_batch_records), ctypes.byref(h))
         self.handle = h
         self._keep = {}
 
@@ -536,6 +562,12 @@ class Server:
             out.append(JobResult(r.job_id, r.status, _result(r.result) if r.status == 0 else None,
                                  r.t_submit_ns, r.t_start_ns, r.t_done_ns))
         return out
+
+    def stats(self) -> dict:
+        st = rv_server_stats()
+        if lib().rv_server_get_stats(self.handle, ctypes.byref(st)):
+            raise RVError(-1, "rv_server_get_stats failed")
+        return {name: getattr(st, name) for name, _ in rv_server_stats._fields_}
 
     def drain(self, timeout_ms: int = 600000):
         st = lib().rv_server_drain(self.handle, int(timeout_ms))

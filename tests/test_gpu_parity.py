@@ -22,10 +22,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=["fold", "sort_scan"])
+def ctx(request):
+    # every parity case runs with both per-bucket grouping kernels
     import paper_2503_08946_amd as rv
     c = rv.Context(0, workspace_bytes=1 << 30)
+    c.group = request.param
     yield c
     c.close()
 
@@ -214,6 +216,39 @@ def test_hot_location_exceeds_one_slice(ctx):
     b.segment([p])
     k, r, o = compare(ctx, b.build())
     assert r.n_records == 64 * 256 * 4 + 1 and r.n_conflicts == 1
+
+
+def test_hot_buckets_split_over_workgroups(ctx):
+    # two locations with 262,144 and 131,073 records (buckets far above one
+    # workgroup's share, folded in parts) next to ordinary buckets
+    b = Builder((256, 1), (256, 1), "hot-buckets")
+    g = b.array(GLOBAL, (4096,))
+    who = 77 * 256 + 5
+    p = b.phase([rw(g, False, aff(0), loops=((0, 4),)),
+                 rw(g, False, aff(2048), loops=((0, 2),)),
+                 rw(g, True, aff(2048), guards=(aff(-who, tx=1, bx=256), aff(who, tx=-1, bx=-256))),
+                 rw(g, True, aff(1024, tx=1))], False)
+    b.segment([p])
+    k, r, o = compare(ctx, b.build())
+    assert r.n_records == 256 * 256 * 4 + 256 * 256 * 2 + 1 + 256 * 256
+    assert r.n_conflicts == 1 + 256
+
+
+@pytest.mark.parametrize("log_dim", [22, 25])
+def test_tile_spanning_many_buckets(ctx, log_dim):
+    # pseudo-random addresses over a large global array: one expansion tile
+    # touches thousands of buckets (LDS bins in windows at 2^22, per-record
+    # reservations at 2^25)
+    b = Builder((256, 1), (1, 1), f"wide-tile-{log_dim}")
+    g = b.array(GLOBAL, (1 << log_dim,))
+    h = Aux(AUX_EMOD, 1 << log_dim, aff(13, tx=7919, l0=104729))
+    h2 = Aux(AUX_EMOD, 1 << log_dim, aff(13 + 7919, tx=7919, l0=104729))    # thread tx + 1's address
+    p = b.phase([rw(g, False, aff(aux0=1), loops=((0, 256),), aux=(h, Aux())),
+                 rw(g, True, aff(aux0=1), loops=((0, 8),), aux=(h, Aux())),
+                 rw(g, True, aff(aux0=1), loops=((0, 4),), aux=(h2, Aux()))], False)
+    b.segment([p])
+    k, r, o = compare(ctx, b.build())
+    assert r.n_conflicts > 0
 
 
 def test_key_range_passes(ctx):

@@ -52,7 +52,8 @@ def _mix():
     return descs
 
 
-def test_served_equals_alone():
+@pytest.mark.parametrize("max_batch_records", [0, 100_000])
+def test_served_equals_alone(max_batch_records):
     import paper_2503_08946_amd as rv
     descs = _mix()
     ctx = rv.Context(0, workspace_bytes=256 << 20)
@@ -64,7 +65,7 @@ def test_served_equals_alone():
         except rv.RVError as e:
             alone.append((e.status, None))
     say(f"[serve] {len(descs)} jobs checked alone")
-    srv = rv.Server(ctx, budget_bytes=256 << 20)
+    srv = rv.Server(ctx, budget_bytes=256 << 20, max_batch_records=max_batch_records)
     # submit in three waves with pauses so batches form at different points
     ids = {}
     order = list(range(len(ks))) + list(range(0, len(ks), 3))   # some kernels twice
@@ -86,6 +87,11 @@ def test_served_equals_alone():
             assert (r.result.n_records, r.result.n_conflicts) == (ref.n_records, ref.n_conflicts)
             assert _wkey(r.result.witness) == _wkey(ref.witness)
     assert alone[-3][0] == -5          # the out-of-bounds kernel fails in the mix as alone
+    st = srv.stats()
+    say(f"[serve] {st}")
+    assert st["jobs"] == len(order)
+    if max_batch_records:
+        assert st["batches"] > 3
     srv.close()
     # the context works normally again once the server is gone
     r = ctx.check(ks[0])

@@ -37,11 +37,13 @@ def test_targets_give_identical_results():
         ctx.target = target
         assert ctx.target == target
         ks = [ctx.load(d) for d in descs]
-        res = ctx.check_batch(ks)
-        for d, o, r in zip(descs, refs, res):
-            say(f"[target {target}] {d.name}")
-            assert (r.n_records, r.n_conflicts) == (o.n_records, o.n_conflicts)
-            assert _wkey(r.witness) == (_wkey(o.witnesses[0]) if o.n_conflicts else None)
+        for group in ("fold", "sort_scan"):
+            ctx.group = group
+            res = ctx.check_batch(ks)
+            for d, o, r in zip(descs, refs, res):
+                say(f"[target {target} {group}] {d.name}")
+                assert (r.n_records, r.n_conflicts) == (o.n_records, o.n_conflicts)
+                assert _wkey(r.witness) == (_wkey(o.witnesses[0]) if o.n_conflicts else None)
         for k in ks:
             k.free()
     with pytest.raises(rv.RVError):
@@ -56,14 +58,15 @@ def test_autotune_and_cache(tmp_path):
     cache = str(tmp_path / "tune.json")
     rec = ctx.autotune(descs, trials=2, cache=cache)
     say(f"[autotune] {rec}")
-    assert rec["target"] in rec["ms"]
-    assert all(v > 0 for v in rec["ms"].values())
-    assert ctx.target == rec["target"]
+    assert f"{rec['target']}/{rec['group']}" in rec["ms"]
+    assert len(rec["ms"]) == 8 and all(v > 0 for v in rec["ms"].values())
+    assert ctx.target == rec["target"] and ctx.group == rec["group"]
     db = json.load(open(cache))
     assert len(db) == 1
     ctx.target = 2048
+    ctx.group = "sort_scan" if rec["group"] == "fold" else "fold"
     again = ctx.autotune(descs, trials=2, cache=cache)     # served from the cache
-    assert again["target"] == rec["target"] and ctx.target == rec["target"]
+    assert again["target"] == rec["target"] and ctx.target == rec["target"] and ctx.group == rec["group"]
     ks = [ctx.load(d) for d in descs[:8]]
     for d, r in zip(descs[:8], ctx.check_batch(ks)):
         o = oracle.check(d, max_witnesses=1)
