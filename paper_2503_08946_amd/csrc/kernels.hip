@@ -798,17 +798,21 @@ __global__ void __launch_bounds__(BKT_WG) k_bucket(const DevSub *subs_g, uint32_
     const uint32_t t = threadIdx.x;
     const uint32_t wid = t >> 6;
 
+    uint32_t lo_s = 0;      // pass of the current bucket: buckets only increase, so walk forward
+    {
+        uint32_t hi_s = nsub;
+        while (hi_s - lo_s > 1) {
+            const uint32_t mid = (lo_s + hi_s) >> 1;
+            if (subs[mid].bucket_begin <= blockIdx.x) lo_s = mid; else hi_s = mid;
+        }
+    }
     for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
         const uint32_t cnt = counts[b];
         if (cnt == 0) {
             if (t == 0) conf[b] = 0;
             continue;
         }
-        uint32_t lo_s = 0, hi_s = nsub;
-        while (hi_s - lo_s > 1) {
-            const uint32_t mid = (lo_s + hi_s) >> 1;
-            if (subs[mid].bucket_begin <= b) lo_s = mid; else hi_s = mid;
-        }
+        while (b >= subs[lo_s].bucket_begin + subs[lo_s].nb) lo_s++;
         CSub &S = subs[lo_s];
         const Magic mgM = ldm(S.mgM);
         const uint32_t nbins = 1u << S.s;
@@ -1145,6 +1149,8 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
     const uint32_t t = threadIdx.x;
     uint32_t b0, b1;
     my_items(nbuckets, b0, b1);
+    if (b0 >= b1) return;
+    uint32_t sidx = sub_of_bucket(subs, nsub, b0);     // buckets only increase: walk forward from here
     for (uint32_t base = b0; base < b1; base += BKT_WG) {
         // --- list this group's non-empty buckets (in order) and the hot ones
         const uint32_t mb = base + t;
@@ -1175,7 +1181,8 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
         if (nl) run_load(cur, rec + l_st[0], min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[0]), t);
         for (uint32_t i = 0; i < nl; i++) {
             const uint32_t b = l_b[i], cnt = l_cnt[i], start = l_st[i];
-            CSub &S = subs[sub_of_bucket(subs, nsub, b)];
+            while (b >= subs[sidx].bucket_begin + subs[sidx].nb) sidx++;
+            CSub &S = subs[sidx];
             const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
             const uint32_t width = min(1u << S.s, S.khi - lo);
 #pragma unroll
@@ -1418,9 +1425,7 @@ void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned 
     static const unsigned occ = occupancy(k_fold, BKT_WG, 4);
     static const unsigned occ_hot = occupancy(k_hot, BKT_WG, 4);
     launch_fill_u32(hot.n, 1, 0u, st);
-    // at least 64 buckets per wave-block of a workgroup's range
-    const uint64_t groups = (nbuckets + 255) / 256;
-    hipLaunchKernelGGL(k_fold, dim3(persistent_grid(groups, ncu, occ)), dim3(BKT_WG), 0, st, subs, nsub,
+    hipLaunchKernelGGL(k_fold, dim3(persistent_grid(nbuckets, ncu, occ)), dim3(BKT_WG), 0, st, subs, nsub,
                        (uint32_t)nbuckets, rec, starts, counts, conf, hot);
     hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
 }
