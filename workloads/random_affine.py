@@ -1,15 +1,20 @@
 """Seeded random affine 2-D kernels for the batched and served workloads.
 
-Shape of one kernel (all draws from one ``PCG64`` stream per kernel):
+Shape of one kernel (all draws from one ``PCG64`` stream per kernel), in
+draw order:
 
-* blockDim (bx, by) with bx, by in [1, 32]; gridDim up to (64, 64), scaled so
-  the record count lands within 10 % of a target drawn log-uniformly in
-  ``[lo, hi]`` (shapes are redrawn until that is possible);
+* a record-count target drawn log-uniformly in ``[lo, hi]``;
 * 1-6 phases, a barrier after each but the last; 1-8 accesses per phase;
+  0-2 loops per access with trip counts in [1, 64] (this fixes the records
+  per thread, m);
+* blockDim (bx, by): bx uniform in [1, min(32, 1.1 target / m)], by uniform
+  in [1, min(32, that bound / bx)]; gridDim up to (64, 64) scaled so the
+  record count lands within 10 % of the target (everything above is redrawn
+  until that is possible);
 * 1-4 two-dimensional int arrays, each shared (256-4096 elements) or global
   (2^10-2^20 elements) with probability 1/2;
-* each access: writes with p = 1/2; 0-2 loops with trip counts in [1, 64];
-  per array dimension an index ``emod(c . v + c0, dim)`` with coefficients
+* each access: writes with p = 1/2; per array dimension an index
+  ``emod(c . v + c0, dim)`` with coefficients
   uniform in [-4, 4] over (tx, ty, bx, by, l0, l1) and ``c0`` uniform in
   [0, dim); no guards.
 
