@@ -1214,22 +1214,38 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
                                                  const uint32_t *__restrict__ counts, uint32_t *__restrict__ conf,
                                                  HotArea hot) {
     __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
+    __shared__ uint32_t h_pre[BKT_WG + 1], h_b[BKT_WG], h_cnt[BKT_WG];
     __shared__ uint32_t red[BKT_WG / 64];
     __shared__ uint32_t last;
     CSub *subs = cptr(subs_g);
     const uint32_t t = threadIdx.x;
     const uint32_t nh = min(*hot.n, hot.cap);
-    uint32_t u = 0;      // running part index over the list
-    for (uint32_t i = 0; i < nh; i++) {
-        const uint32_t b = hot.list[i];
-        const uint32_t cnt = counts[b];
+    uint32_t u = 0;      // parts of the list before this group of entries
+    for (uint32_t base = 0; base < nh; base += BKT_WG) {
+        // the group's entries and the prefix of their part counts
+        const uint32_t i = base + t;
+        uint32_t b = 0, cnt = 0;
+        if (i < nh) { b = hot.list[i]; cnt = counts[b]; }
         const uint32_t parts = (cnt + HOT - 1) / HOT;
-        // parts u .. u + parts - 1 of the list go to workgroups round-robin
-        uint32_t q = (blockIdx.x + gridDim.x - u % gridDim.x) % gridDim.x;
-        for (; q < parts; q += gridDim.x) {
-            const uint32_t start = starts[b];
-            CSub &S = subs[sub_of_bucket(subs, nsub, b)];
-            const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
+        uint32_t tot;
+        const uint32_t pre = block_excl_add<BKT_WG>(parts, red, &tot);
+        h_pre[t] = pre; h_b[t] = b; h_cnt[t] = cnt;
+        if (t == 0) h_pre[BKT_WG] = tot;
+        __syncthreads();
+        // parts u .. u + tot - 1 go to workgroups round-robin
+        for (uint32_t p = (blockIdx.x + gridDim.x - u % gridDim.x) % gridDim.x; p < tot; p += gridDim.x) {
+            uint32_t lo_e = 0, hi_e = BKT_WG;         // entry: the last with h_pre <= p
+            while (hi_e - lo_e > 1) {
+                const uint32_t mid = (lo_e + hi_e) >> 1;
+                if (h_pre[mid] <= p) lo_e = mid; else hi_e = mid;
+            }
+            while (lo_e + 1 < BKT_WG && h_pre[lo_e + 1] <= p) lo_e++;     // skip entries with no parts
+            const uint32_t e = lo_e, q = p - h_pre[e];
+            const uint32_t bk = h_b[e], bcnt = h_cnt[e];
+            const uint32_t bparts = (bcnt + HOT - 1) / HOT;
+            const uint32_t start = starts[bk];
+            CSub &S = subs[sub_of_bucket(subs, nsub, bk)];
+            const uint32_t lo = S.klo + ((bk - S.bucket_begin) << S.s);
             const uint32_t width = min(1u << S.s, S.khi - lo);
 #pragma unroll
             for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
@@ -1237,9 +1253,9 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
                 t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
             }
             __syncthreads();
-            fold_records<BKT_WG>(rec + start, q * HOT, min(cnt, (q + 1) * HOT), lo, t, t_mn, t_mx, t_mnw, t_mxw1);
+            fold_records<BKT_WG>(rec + start, q * HOT, min(bcnt, (q + 1) * HOT), lo, t, t_mn, t_mx, t_mnw, t_mxw1);
             __syncthreads();
-            uint32_t *g = hot.tab + (size_t)i * 4 * TBL;
+            uint32_t *g = hot.tab + (size_t)(base + e) * 4 * TBL;
             for (uint32_t k = t; k < width; k += BKT_WG) {
                 if (t_mn[k] != 0xFFFFFFFFu) {
                     atomicMin(&g[k], t_mn[k]);
@@ -1252,42 +1268,26 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
             }
             __threadfence();
             __syncthreads();
-            if (t == 0) last = (atomicAdd(&hot.done[i], 1u) == parts - 1) ? 1u : 0u;
+            if (t == 0) last = (atomicAdd(&hot.done[base + e], 1u) == bparts - 1) ? 1u : 0u;
             __syncthreads();
             if (last) {
                 __threadfence();
-                const Magic mgM = ldm(S.mgM);
-                bool cf[TBL / BKT_WG];
-                Seg e[TBL / BKT_WG];
-                uint32_t second[TBL / BKT_WG], srw[TBL / BKT_WG];
-                uint32_t nc = 0;
-#pragma unroll
-                for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
-                    const uint32_t k = t * (TBL / BKT_WG) + k2;
-                    cf[k2] = false; second[k2] = 0; srw[k2] = 0;
-                    e[k2] = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
-                    if (k < width) {
-                        e[k2].mn = __hip_atomic_load(&g[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        e[k2].mx = __hip_atomic_load(&g[TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        e[k2].mnw = __hip_atomic_load(&g[2 * TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        e[k2].mxw1 = __hip_atomic_load(&g[3 * TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (e[k2].mn != 0xFFFFFFFFu) cf[k2] = judge(e[k2], mgM, second[k2], srw[k2]);
-                    }
-                    nc += cf[k2] ? 1u : 0u;
+                // the summary is complete: copy it into the LDS tables and judge
+                for (uint32_t k = t; k < width; k += BKT_WG) {
+                    t_mn[k] = __hip_atomic_load(&g[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    t_mx[k] = __hip_atomic_load(&g[TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    t_mnw[k] = __hip_atomic_load(&g[2 * TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    t_mxw1[k] = __hip_atomic_load(&g[3 * TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                uint32_t total;
-                uint32_t pos = block_excl_add<BKT_WG>(nc, red, &total);
-                if (total) {
-                    uint32_t *wout = reinterpret_cast<uint32_t *>(rec + start);
-#pragma unroll
-                    for (int k2 = 0; k2 < TBL / BKT_WG; k2++)
-                        if (cf[k2]) put_witness(wout, pos++, lo + t * (TBL / BKT_WG) + k2, e[k2], second[k2], srw[k2]);
-                }
-                if (t == 0) conf[b] = total;
+                __syncthreads();
+                const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
+                                                    reinterpret_cast<uint32_t *>(rec + start), red);
+                if (t == 0) conf[bk] = total;
             }
             __syncthreads();
         }
-        u += parts;
+        u += tot;
+        __syncthreads();     // the group's LDS arrays are rebuilt next
     }
 }
 
