@@ -141,6 +141,7 @@ def bench_batch(args, rv, torch):
     log(f"[bench] generated 4096 kernels in {time.perf_counter() - t0:.1f} s")
     ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
     ctx.group = args.group
+    ctx.target = args.target
     ks = [ctx.load(d) for d in descs]
     log(f"[bench] loaded 4096 kernels")
     batch = rv.Batch(ctx, ks)
@@ -208,6 +209,7 @@ def bench_serve(args, rv, torch):
     log(f"[bench] generated {len(descs)} jobs in {time.perf_counter() - t0:.1f} s")
     ctx = rv.Context(0, workspace_bytes=1 << 30)
     ctx.group = args.group
+    ctx.target = args.target
     ks = [ctx.load(d) for d in descs]
     log(f"[bench] loaded {len(ks)} jobs")
     srv = rv.Server(ctx, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch_records=args.batch_records)
@@ -292,6 +294,7 @@ def main():
                     help="batch workload: skip the one-rv_check-per-kernel comparison")
     ap.add_argument("--group", choices=("fold", "sort_scan"), default="fold",
                     help="per-bucket grouping kernel")
+    ap.add_argument("--target", type=int, default=2048, help="planner: mean records per location bucket")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="server budget (serve workload)")
     ap.add_argument("--serve-jobs", type=int, default=10000)
     ap.add_argument("--batch-records", type=int, default=1 << 26, help="server: records per batch at most")
@@ -328,6 +331,7 @@ def main():
     log(f"[bench] workload {args.workload}: {wl_text}")
     ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
     ctx.group = args.group
+    ctx.target = args.target
     ks = [ctx.load(d) for d in descs]
     batch = len(ks) > 1
 

@@ -1047,9 +1047,14 @@ __device__ __forceinline__ void run_load(Run<NL> &r, const unsigned long long *_
     r.rpl = (n + NL - 1) / NL;
     const uint32_t r0 = me * r.rpl;
     r.m = r0 < n ? min(r.rpl, n - r0) : 0u;
-    const unsigned long long *p = src + r0;
+    // Every lane issues all FOLD_RPL loads (indices clamped into its run, or
+    // to the slice's first record), so the loads are unconditional and the
+    // compiler can leave them in flight while the previous bucket is folded.
+    // Entries at or past m are never read (run_fold stops at m).
+    const unsigned long long *p = src + (r.m ? r0 : 0u);
+    const uint32_t last = r.m ? r.m - 1 : 0u;
 #pragma unroll
-    for (int i = 0; i < FOLD_RPL; i++) r.x[i] = (uint32_t)i < r.m ? p[i] : 0ull;
+    for (int i = 0; i < FOLD_RPL; i++) r.x[i] = p[min((uint32_t)i, last)];
 }
 
 // Fold one lane's run into the tables: consecutive records of equal location
@@ -1156,8 +1161,12 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
         const uint32_t mb = base + t;
         const bool inr = mb < b1;
         const uint32_t c = inr ? counts[mb] : 0u;
-        const bool take = c != 0 && c <= HOT;
+        const bool take = c != 0 && c <= FOLD_CAP;
         const bool is_hot = c > HOT;
+        if (c > FOLD_CAP && !is_hot) {                   // medium: k_mid folds it
+            const uint32_t slot = atomicAdd(hot.mid_n, 1u);
+            if (slot < hot.mid_cap) hot.mid_list[slot] = mb;
+        }
         if (inr && !take) conf[mb] = 0;
         uint32_t both;     // listed buckets in the low half, hot ones in the high half
         const uint32_t pos = block_excl_add<BKT_WG>((take ? 1u : 0u) | (is_hot ? 0x10000u : 0u), red, &both);
@@ -1177,10 +1186,15 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
             }
         }
         // --- fold the listed buckets; slice 0 of the next one loads meanwhile
-        Run<BKT_WG> cur, nxt;
-        if (nl) run_load(cur, rec + l_st[0], min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[0]), t);
+        // Slice 0 of bucket i is loaded into `nxt` while bucket i - 1 is
+        // folded and copied into `cur` when bucket i starts, so `cur` always
+        // comes from a register copy and the loads in flight are only ever the
+        // next bucket's.
+        Run<BKT_WG> nxt;
+        if (nl) run_load(nxt, rec + l_st[0], min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[0]), t);
         for (uint32_t i = 0; i < nl; i++) {
-            const uint32_t b = l_b[i], cnt = l_cnt[i], start = l_st[i];
+            const Run<BKT_WG> cur = nxt;
+            const uint32_t b = l_b[i], start = l_st[i];
             while (b >= subs[sidx].bucket_begin + subs[sidx].nb) sidx++;
             CSub &S = subs[sidx];
             const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
@@ -1193,14 +1207,44 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
             __syncthreads();
             if (i + 1 < nl) run_load(nxt, rec + l_st[i + 1], min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[i + 1]), t);
             run_fold(cur, lo, t_mn, t_mx, t_mnw, t_mxw1);
-            if (cnt > (uint32_t)(BKT_WG * FOLD_RPL)) fold_records<BKT_WG>(rec + start, BKT_WG * FOLD_RPL, cnt, lo, t, t_mn, t_mx, t_mnw, t_mxw1);
             __syncthreads();
             const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
                                                 reinterpret_cast<uint32_t *>(rec + start), red);
             if (t == 0) conf[b] = total;
-            cur = nxt;
         }
         __syncthreads();     // the list is rebuilt for the next group
+    }
+}
+
+// Medium buckets (more records than one fold slice, at most HOT): one
+// workgroup per bucket, slice after slice.
+__global__ void __launch_bounds__(BKT_WG) k_mid(const DevSub *subs_g, uint32_t nsub,
+                                                 unsigned long long *__restrict__ rec,
+                                                 const uint32_t *__restrict__ starts,
+                                                 const uint32_t *__restrict__ counts, uint32_t *__restrict__ conf,
+                                                 HotArea hot) {
+    __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
+    __shared__ uint32_t red[BKT_WG / 64];
+    CSub *subs = cptr(subs_g);
+    const uint32_t t = threadIdx.x;
+    const uint32_t nm = min(*hot.mid_n, hot.mid_cap);
+    for (uint32_t i = blockIdx.x; i < nm; i += gridDim.x) {
+        const uint32_t b = hot.mid_list[i];
+        const uint32_t cnt = counts[b], start = starts[b];
+        CSub &S = subs[sub_of_bucket(subs, nsub, b)];
+        const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
+        const uint32_t width = min(1u << S.s, S.khi - lo);
+#pragma unroll
+        for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
+            const uint32_t k = t + k2 * BKT_WG;
+            t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+        }
+        __syncthreads();
+        fold_records<BKT_WG>(rec + start, 0, cnt, lo, t, t_mn, t_mx, t_mnw, t_mxw1);
+        __syncthreads();
+        const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
+                                            reinterpret_cast<uint32_t *>(rec + start), red);
+        if (t == 0) conf[b] = total;
     }
 }
 
@@ -1424,9 +1468,12 @@ void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned 
     if (!nbuckets) return;
     static const unsigned occ = occupancy(k_fold, BKT_WG, 4);
     static const unsigned occ_hot = occupancy(k_hot, BKT_WG, 4);
+    static const unsigned occ_mid = occupancy(k_mid, BKT_WG, 4);
     launch_fill_u32(hot.n, 1, 0u, st);
+    launch_fill_u32(hot.mid_n, 1, 0u, st);
     hipLaunchKernelGGL(k_fold, dim3(persistent_grid(nbuckets, ncu, occ)), dim3(BKT_WG), 0, st, subs, nsub,
                        (uint32_t)nbuckets, rec, starts, counts, conf, hot);
+    hipLaunchKernelGGL(k_mid, dim3(ncu * occ_mid), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
     hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
 }
 

@@ -381,6 +381,10 @@ WorkspaceLayout layout_workspace(size_t bytes) {
         L.off_hot_list = off; off = al(off + H * 4);
         L.off_hot_done = off; off = al(off + H * 4);
         L.off_hot_tab = off; off = al(off + H * 4 * TBL * 4);
+        const size_t Mc = R / FOLD_CAP + 1;   // at most this many buckets exceed one fold slice
+        L.off_mid_n = off; off = al(off + 4);
+        L.off_mid_list = off; off = al(off + Mc * 4);
+        L.cap_mid = Mc;
         L.cap_records = R;
         L.cap_buckets = BC;
         L.cap_hot = H;
@@ -388,7 +392,7 @@ WorkspaceLayout layout_workspace(size_t bytes) {
         return L;
     };
     // per record: 8 B, bucket arrays 16 B per 256 records, hot tables 8 KiB per HOT records
-    const long double per = 8.0L + 16.0L / 256.0L + (16.0L * TBL + 8.0L) / (long double)HOT;
+    const long double per = 8.0L + 16.0L / 256.0L + (16.0L * TBL + 8.0L) / (long double)HOT + 4.0L / FOLD_CAP;
     size_t R = (size_t)(((long double)(bytes - reserve)) / per);
     R = std::min<size_t>(R, (size_t)0xFFF00000u);
     WorkspaceLayout L = place(R);

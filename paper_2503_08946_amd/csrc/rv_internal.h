@@ -25,6 +25,7 @@ constexpr int BKT_RPL = 16;              // records per lane in one on-chip slic
 constexpr int CAP = BKT_WG * BKT_RPL;    // records per on-chip slice
 constexpr int DEFAULT_TARGET = 2048;     // planner: mean records per bucket
 constexpr int FOLD_RPL = 8;              // fold: records per lane in one slice
+constexpr uint32_t FOLD_CAP = 256 * FOLD_RPL;   // fold: buckets above this many records are medium
 constexpr uint32_t HOT = 1u << 15;       // fold: buckets above this many records are split over workgroups
 constexpr int TBL = 1 << SMAX;           // locations of one bucket (LDS table entries)
 
@@ -180,6 +181,9 @@ struct WorkspaceLayout {
     // completion counter and a four-table location summary per entry
     size_t cap_hot = 0;
     size_t off_hot_n = 0, off_hot_list = 0, off_hot_done = 0, off_hot_tab = 0;
+    // medium buckets (one fold slice < records <= HOT): their list and length
+    size_t cap_mid = 0;
+    size_t off_mid_n = 0, off_mid_list = 0;
     size_t bytes = 0;
 };
 
@@ -259,6 +263,8 @@ void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigne
 struct HotArea {
     uint32_t *n, *list, *done, *tab;
     uint32_t cap;
+    uint32_t *mid_n, *mid_list;
+    uint32_t mid_cap;
 };
 void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
                  const uint32_t *starts, const uint32_t *counts, uint32_t *conf, HotArea hot, unsigned ncu,
