@@ -1186,14 +1186,13 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
             }
         }
         // --- fold the listed buckets; slice 0 of the next one loads meanwhile
-        // Slice 0 of bucket i is loaded into `nxt` while bucket i - 1 is
-        // folded and copied into `cur` when bucket i starts, so `cur` always
-        // comes from a register copy and the loads in flight are only ever the
-        // next bucket's.
-        Run<BKT_WG> nxt;
-        if (nl) run_load(nxt, rec + l_st[0], min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[0]), t);
-        for (uint32_t i = 0; i < nl; i++) {
-            const Run<BKT_WG> cur = nxt;
+        // Two register sets alternate: while bucket i is folded from one, the
+        // other already holds (or is loading) bucket i + 1, and set A is
+        // reloaded with bucket i + 2 as soon as bucket i is done.  Loads are
+        // unconditional (the list index is clamped) so the compiler keeps
+        // exactly the other set in flight.
+        auto slice_of = [&](uint32_t j) { return min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[j]); };
+        auto process = [&](uint32_t i, const Run<BKT_WG> &cur) {
             const uint32_t b = l_b[i], start = l_st[i];
             while (b >= subs[sidx].bucket_begin + subs[sidx].nb) sidx++;
             CSub &S = subs[sidx];
@@ -1205,12 +1204,24 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
                 t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
             }
             __syncthreads();
-            if (i + 1 < nl) run_load(nxt, rec + l_st[i + 1], min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[i + 1]), t);
             run_fold(cur, lo, t_mn, t_mx, t_mnw, t_mxw1);
             __syncthreads();
             const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
                                                 reinterpret_cast<uint32_t *>(rec + start), red);
             if (t == 0) conf[b] = total;
+        };
+        if (nl) {
+            Run<BKT_WG> A, B;
+            run_load(A, rec + l_st[0], slice_of(0), t);
+            run_load(B, rec + l_st[min(1u, nl - 1)], slice_of(min(1u, nl - 1)), t);
+            for (uint32_t i = 0; i < nl; i += 2) {
+                process(i, A);
+                const uint32_t ja = min(i + 2, nl - 1);
+                run_load(A, rec + l_st[ja], slice_of(ja), t);
+                if (i + 1 < nl) process(i + 1, B);
+                const uint32_t jb = min(i + 3, nl - 1);
+                run_load(B, rec + l_st[jb], slice_of(jb), t);
+            }
         }
         __syncthreads();     // the list is rebuilt for the next group
     }
