@@ -1112,9 +1112,12 @@ __device__ __forceinline__ uint32_t sub_of_bucket(CSub *subs, uint32_t nsub, uin
 
 // Judge every location of a folded bucket and write its witnesses in
 // location order at the start of the bucket's region; returns the count.
-__device__ __forceinline__ uint32_t judge_tables(const uint32_t *t_mn, const uint32_t *t_mx, const uint32_t *t_mnw,
-                                                 const uint32_t *t_mxw1, uint32_t width, uint32_t lo, Magic mgM,
-                                                 uint32_t *wout, uint32_t *red) {
+// With RESET, each entry read is set back to the empty summary, so the
+// tables are ready for the next bucket once the judge's barriers are passed.
+template <bool RESET = false>
+__device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
+                                                 uint32_t width, uint32_t lo, Magic mgM, uint32_t *wout,
+                                                 uint32_t *red) {
     constexpr int TP = TBL / BKT_WG;
     const uint32_t t = threadIdx.x;
     bool c[TP];
@@ -1128,7 +1131,10 @@ __device__ __forceinline__ uint32_t judge_tables(const uint32_t *t_mn, const uin
         e[i] = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
         if (k < width) {
             e[i].mn = t_mn[k]; e[i].mx = t_mx[k]; e[i].mnw = t_mnw[k]; e[i].mxw1 = t_mxw1[k];
-            if (e[i].mn != 0xFFFFFFFFu) c[i] = judge(e[i], mgM, second[i], srw[i]);
+            if (e[i].mn != 0xFFFFFFFFu) {
+                c[i] = judge(e[i], mgM, second[i], srw[i]);
+                if (RESET) { t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0; }
+            }
         }
         nc += c[i] ? 1u : 0u;
     }
@@ -1156,6 +1162,11 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
     my_items(nbuckets, b0, b1);
     if (b0 >= b1) return;
     uint32_t sidx = sub_of_bucket(subs, nsub, b0);     // buckets only increase: walk forward from here
+#pragma unroll
+    for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
+        const uint32_t k = t * (TBL / BKT_WG) + k2;
+        t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+    }
     for (uint32_t base = b0; base < b1; base += BKT_WG) {
         // --- list this group's non-empty buckets (in order) and the hot ones
         const uint32_t mb = base + t;
@@ -1198,16 +1209,12 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
             CSub &S = subs[sidx];
             const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
             const uint32_t width = min(1u << S.s, S.khi - lo);
-#pragma unroll
-            for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
-                const uint32_t k = t * (TBL / BKT_WG) + k2;
-                t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
-            }
-            __syncthreads();
+            // the tables are empty here: cleared before the first bucket, and
+            // reset entry by entry by the previous bucket's judge
             run_fold(cur, lo, t_mn, t_mx, t_mnw, t_mxw1);
             __syncthreads();
-            const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
-                                                reinterpret_cast<uint32_t *>(rec + start), red);
+            const uint32_t total = judge_tables<true>(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
+                                                      reinterpret_cast<uint32_t *>(rec + start), red);
             if (t == 0) conf[b] = total;
         };
         if (nl) {
