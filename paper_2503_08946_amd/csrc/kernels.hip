@@ -509,6 +509,12 @@ __global__ void k_init_results(SubResult *r, size_t n) {
     }
 }
 
+// Per-wave binning in the scatter: each wave takes WBIN bins of the shared
+// area, over at most WWIN windows of its own bucket range.
+constexpr int EXP_NW = EXP_WG / 64;
+constexpr uint32_t WBIN = BINCAP / EXP_NW;
+constexpr uint32_t WWIN = 16;
+
 // --------------------------------------------------------------- count pass
 __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t nsub, uint32_t nitems,
                                                   uint32_t *__restrict__ counts, SubResult *__restrict__ res) {
@@ -631,10 +637,12 @@ __global__ void __launch_bounds__(SCAN_WG) k_scan_down(const uint32_t *__restric
 __global__ void __launch_bounds__(EXP_WG) __attribute__((amdgpu_waves_per_eu(5))) k_scatter(const DevSub *subs_g, uint32_t nsub, uint32_t nitems,
                                                      unsigned long long *__restrict__ rec,
                                                      uint32_t *__restrict__ cursor) {
-    __shared__ uint32_t h[BINCAP];
-    __shared__ uint32_t gb[BINCAP];
+    // One LDS area, used per workgroup (h, gb: BINCAP bins each) for entries
+    // of the general expansion, or per wave (WBIN bins each) for fast ones.
+    __shared__ uint32_t bins[2 * BINCAP];
     __shared__ uint32_t red[3 * (EXP_WG / 64)];
     CSub *subs = cptr(subs_g);
+    uint32_t *const hw = bins + (threadIdx.x >> 6) * 2 * WBIN, *const gw = hw + WBIN;
     for_my_items(subs, nsub, nitems, [&](CSub &S, CEnt &E, CKer &K, uint32_t li, auto variant) {
         const uint32_t span = S.khi - S.klo;
         const uint32_t rwbit = E.rw;
@@ -651,35 +659,72 @@ __global__ void __launch_bounds__(EXP_WG) __attribute__((amdgpu_waves_per_eu(5))
             if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
         };
         expand_v(variant, S, E, K, li, on_rec);
-        block_min_max_sum<EXP_WG>(mn, mx, n, red);
+        // Fast entries (structured addresses: a wave's records span few
+        // buckets) rank per wave, with no workgroup barrier; general entries
+        // rank per workgroup, whose longer runs pay off for scattered ones.
+        constexpr bool WAVE = decltype(variant)::value % 3 != 2;
+        if constexpr (WAVE) {
+            mn = wave_min(mn);
+            mx = wave_max(mx);
+            n = readlane(wave_incl_add(n), 63);
+        } else {
+            block_min_max_sum<EXP_WG>(mn, mx, n, red);
+        }
         uint32_t *gcur = cursor + S.bucket_begin;
-        if (n && mx - mn < (uint32_t)(BINCAP * BINWIN)) {
-            // Rank every record inside its bucket for this tile, reserve one run
-            // per bucket in the chunk, write each record to run base + rank.
-            // Waves whose records share a bucket get consecutive ranks, so the
-            // stores of a wave slot are one contiguous 512-byte run.  A tile
-            // spanning more than BINCAP buckets takes them in windows.
-            for (uint32_t w = mn;; w += BINCAP) {
-                const uint32_t R = min((uint32_t)BINCAP, mx - w + 1);
-                for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
-                __syncthreads();
-                uint32_t rk[RPL];
+        // Rank every record inside its bucket (per wave or per workgroup),
+        // reserve one run per bucket in the chunk, write each record to run
+        // base + rank; a wave slot whose records share a bucket writes one
+        // contiguous 512-byte run.  Windows of WBIN / BINCAP buckets.
+        if constexpr (WAVE) {
+            if (n && mx - mn < WBIN * WWIN) {
+                for (uint32_t w = mn;; w += WBIN) {
+                    const uint32_t R = min(WBIN, mx - w + 1);
+                    for (uint32_t i = lane(); i < R; i += 64) hw[i] = 0;
+                    __builtin_amdgcn_wave_barrier();
+                    uint32_t rk[RPL];
 #pragma unroll
-                for (int s = 0; s < RPL; s++) rk[s] = lds_rank(h, bk[s] - w, bk[s] - w < R);
-                __syncthreads();
-                for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) {
-                    const uint32_t c = h[i];
-                    if (c) gb[i] = atomicAdd(&gcur[w + i], c);
+                    for (int s = 0; s < RPL; s++) rk[s] = lds_rank(hw, bk[s] - w, bk[s] - w < R);
+                    __builtin_amdgcn_wave_barrier();
+                    for (uint32_t i = lane(); i < R; i += 64) {
+                        const uint32_t c = hw[i];
+                        if (c) gw[i] = atomicAdd(&gcur[w + i], c);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int s = 0; s < RPL; s++)
+                        if (bk[s] - w < R) rec[gw[bk[s] - w] + rk[s]] = r[s];
+                    __builtin_amdgcn_wave_barrier();
+                    if (mx - w < WBIN) break;
                 }
-                __syncthreads();
-#pragma unroll
-                for (int s = 0; s < RPL; s++)
-                    if (bk[s] - w < R) rec[gb[bk[s] - w] + rk[s]] = r[s];
-                __syncthreads();
-                if (mx - w < (uint32_t)BINCAP) break;
+                return;
             }
-        } else if (n) {
-            // a tile spread over more than BINCAP * BINWIN buckets (so many
+        } else {
+            if (n && mx - mn < (uint32_t)(BINCAP * BINWIN)) {
+                uint32_t *h = bins, *gb = bins + BINCAP;
+                for (uint32_t w = mn;; w += BINCAP) {
+                    const uint32_t R = min((uint32_t)BINCAP, mx - w + 1);
+                    for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) h[i] = 0;
+                    __syncthreads();
+                    uint32_t rk[RPL];
+#pragma unroll
+                    for (int s = 0; s < RPL; s++) rk[s] = lds_rank(h, bk[s] - w, bk[s] - w < R);
+                    __syncthreads();
+                    for (uint32_t i = threadIdx.x; i < R; i += EXP_WG) {
+                        const uint32_t c = h[i];
+                        if (c) gb[i] = atomicAdd(&gcur[w + i], c);
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int s = 0; s < RPL; s++)
+                        if (bk[s] - w < R) rec[gb[bk[s] - w] + rk[s]] = r[s];
+                    __syncthreads();
+                    if (mx - w < (uint32_t)BINCAP) break;
+                }
+                return;
+            }
+        }
+        if (n) {
+            // records spread over more buckets than the windows cover (so many
             // that their counters rarely collide): reserve per record
 #pragma unroll
             for (int s = 0; s < RPL; s++) {
