@@ -1102,8 +1102,53 @@ __device__ __forceinline__ void run_load(Run<NL> &r, const unsigned long long *_
     for (int i = 0; i < FOLD_RPL; i++) r.x[i] = p[min((uint32_t)i, last)];
 }
 
+// A lane's merge state: the summary of the run of equal location it is
+// accumulating (location pk, 0xFFFF: none) and the flush of that run into
+// the location's LDS slot.
+struct Merge {
+    Seg cur;
+    uint32_t pk;
+};
+
+__device__ __forceinline__ void merge_init(Merge &g) {
+    g.cur = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+    g.pk = 0xFFFFu;
+}
+
+__device__ __forceinline__ void merge_flush(Merge &g, uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw,
+                                            uint32_t *t_mxw1) {
+    if (g.pk == 0xFFFFu) return;
+    const uint32_t k = g.pk;
+    atomicMin(&t_mn[k], g.cur.mn);
+    atomicMax(&t_mx[k], g.cur.mx);
+    if (g.cur.mxw1) {
+        atomicMin(&t_mnw[k], g.cur.mnw);
+        atomicMax(&t_mxw1[k], g.cur.mxw1);
+    }
+}
+
 // Fold one lane's run into the tables: consecutive records of equal location
-// are merged in registers, one set of atomics per merged run.
+// are merged in registers, one set of atomics per merged run.  The run in
+// progress stays in `g` (the caller flushes it), so a location spanning
+// several slices costs one set of atomics.
+template <int NL>
+__device__ __forceinline__ void run_merge(const Run<NL> &r, uint32_t lo, Merge &g, uint32_t *t_mn, uint32_t *t_mx,
+                                          uint32_t *t_mnw, uint32_t *t_mxw1) {
+#pragma unroll
+    for (int j = 0; j < FOLD_RPL; j++) {
+        if ((uint32_t)j < r.m) {
+            const uint32_t hi = (uint32_t)(r.x[j] >> 32);
+            const uint32_t k = (hi >> 1) - lo;
+            if (k != g.pk) {
+                merge_flush(g, t_mn, t_mx, t_mnw, t_mxw1);
+                g.cur = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                g.pk = k;
+            }
+            seg_add(g.cur, (uint32_t)r.x[j], hi & 1u);
+        }
+    }
+}
+
 template <int NL>
 __device__ __forceinline__ void run_fold(const Run<NL> &r, uint32_t lo, uint32_t *t_mn, uint32_t *t_mx,
                                          uint32_t *t_mnw, uint32_t *t_mxw1) {
@@ -1134,15 +1179,21 @@ __device__ __forceinline__ void run_fold(const Run<NL> &r, uint32_t lo, uint32_t
 }
 
 // Fold records [r_begin, r_end) of one bucket in slices of NL * FOLD_RPL.
+// Each lane keeps its merge state from one slice to the next (its runs are
+// consecutive records of consecutive slices only in hot, single-location
+// stretches, which is where it matters: one flush per lane per call).
 template <int NL>
 __device__ __forceinline__ void fold_records(const unsigned long long *__restrict__ src, uint32_t r_begin,
                                              uint32_t r_end, uint32_t lo, uint32_t me, uint32_t *t_mn,
                                              uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1) {
+    Merge g;
+    merge_init(g);
     for (uint32_t slice = r_begin; slice < r_end; slice += NL * FOLD_RPL) {
         Run<NL> r;
         run_load(r, src + slice, min((uint32_t)(NL * FOLD_RPL), r_end - slice), me);
-        run_fold(r, lo, t_mn, t_mx, t_mnw, t_mxw1);
+        run_merge(r, lo, g, t_mn, t_mx, t_mnw, t_mxw1);
     }
+    merge_flush(g, t_mn, t_mx, t_mnw, t_mxw1);
 }
 
 // The pass a bucket belongs to (bucket begins are increasing).
