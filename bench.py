@@ -39,7 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # 8-byte record, the sort + segmented scan reads it once.  The count pass
 # only evaluates instances (no record traffic).
 ALG_BYTES = {"expand": 8.0, "sort_scan": 8.0}
-GROUP_KERNEL = {"fold": "k_fold", "sort_scan": "k_bucket"}
+# the grouping stage's kernels (fold: buckets of one slice, medium and hot
+# buckets; their HIP-event time is taken together)
+GROUP_KERNEL = {"fold": "k_fold+k_mid+k_hot", "sort_scan": "k_bucket"}
 
 
 def log(*a):
