@@ -198,16 +198,6 @@ __device__ __forceinline__ void advance(CSub *subs, Cursor &c) {
     }
 }
 
-// The contiguous run of items of this workgroup; runs of workgroups that
-// share an XCD are adjacent.
-__device__ __forceinline__ void my_items(uint32_t n, uint32_t &w0, uint32_t &w1) {
-    const uint32_t G = gridDim.x;                  // multiple of 8
-    const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
-    const uint32_t per = (n + G - 1) / G;
-    w0 = min(n, r * per);
-    w1 = min(n, w0 + per);
-}
-
 // Evaluate the RPL instance slots of this lane in one work item and call
 // f(slot, valid, in_bounds, location, id) for each.  A work item covers
 // `lch` consecutive loop points of `gt` threads per lane; the loop counters
@@ -458,39 +448,153 @@ __device__ __forceinline__ void expand_v(Variant<V>, CSub &S, CEnt &E, CKer &K, 
     else expand_item<FLAT>(S, E, K, cptr(S.guards), li, f);
 }
 
-// Run body(S, E, K, li, variant) over this workgroup's work items.  Items of
-// one entry are consecutive, so the entry's variant is chosen (and its
-// constants loaded) once per entry rather than once per item.
+// Linear work items.  A lane's records in an item of a linear entry are
+// one thread's lcnt consecutive points of the innermost loop, so each index
+// and the location are affine in the point: an index lies inside its
+// dimension at every point when it does at the first and the last (the plan
+// proved every index value fits int32, so the unsigned tests are exact), and
+// then the locations are exact and move by the same step dl in every lane.
+// lin_probe succeeds (wave-uniformly) when every record of the wave is in
+// bounds and inside the pass's key range, and
+//  * thread-major items (every live lane has the same points): at each point
+//    the lanes' records share one bucket.  Points then form runs that share
+//    a bucket; lane j < cnt holds point j's bucket, `starts` marks the first
+//    point of each run, and a run of m points holds m x popc(live) records.
+//  * flat items (lanes differ in their points): all records of the wave
+//    share one bucket (a single run starting at point 0).
+// The caller then counts or places the records with one reservation per run
+// instead of a per-record rank.
+struct LinItem {
+    uint32_t lcnt;      // records of this lane (0 past the last thread)
+    uint32_t hi, dhi;   // first record's key half (loc << 1 | rw), step per point
+    uint32_t id;        // first record's id (ids step by one)
+    uint32_t pb;        // lane j < cnt: bucket of point j (relative to the pass)
+    uint32_t cnt;       // points of the item (thread-major: every live lane's count)
+    uint32_t n;         // records of the wave
+    uint64_t live;      // lanes with records
+    uint64_t starts;    // lanes j that start a run of points
+};
+
+template <bool FLAT, bool PROVEN>
+__device__ __forceinline__ bool lin_probe(CSub &S, CEnt &E, CKer &K, uint32_t item, LinItem &L) {
+    const ItemStart<FLAT> st = item_start<FLAT>(E, K, item);
+    const bool gval = st.g0 < K.nthreads;
+    const uint32_t gg = gval ? st.g0 : 0u;
+    const uint32_t blk = udiv(gg, ldm(K.mg_tpb));
+    const uint32_t tid = gg - blk * K.tpb;
+    const uint32_t byy = udiv(blk, ldm(K.mg_gdx));
+    const uint32_t tyy = udiv(tid, ldm(K.mg_bdx));
+    const uint32_t tx = tid - tyy * K.bdx, ty = tyy, bx = blk - byy * K.gdx, by = byy;
+    const uint32_t L0 = (uint32_t)E.lo[0] + st.c0, L1 = (uint32_t)E.lo[1] + st.c1, L2 = (uint32_t)E.lo[2] + st.c2;
+    const uint32_t lcnt = gval ? min(E.lch, E.box - st.lstart) : 0u;
+    const uint32_t last = lcnt - 1u;
+    const uint32_t inner = E.linner;
+    const uint32_t loc = blk * E.loc_mul + E.fr[C_TX] * tx + E.fr[C_TY] * ty + E.fr[C_BX] * bx +
+                         E.fr[C_BY] * by + E.fr[C_C0] + E.fr[C_L0] * L0 + E.fr[C_L1] * L1 + E.fr[C_L2] * L2;
+    const uint32_t dl = E.fr[C_L0 + inner];
+    bool good = true;
+    if constexpr (!PROVEN) {
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            const uint32_t i0 = (uint32_t)E.row[r][C_TX] * tx + (uint32_t)E.row[r][C_TY] * ty +
+                                (uint32_t)E.row[r][C_BX] * bx + (uint32_t)E.row[r][C_BY] * by +
+                                (uint32_t)E.row[r][C_C0] + (uint32_t)E.row[r][C_L0] * L0 +
+                                (uint32_t)E.row[r][C_L1] * L1 + (uint32_t)E.row[r][C_L2] * L2;
+            const uint32_t iN = i0 + last * (uint32_t)E.row[r][C_L0 + inner];
+            good = good && i0 < E.dim[r] && iN < E.dim[r];
+        }
+    }
+    const uint32_t span = S.khi - S.klo;
+    const uint32_t r0 = loc - S.klo, rN = loc + last * dl - S.klo;
+    good = lcnt == 0u || (good && r0 < span && rN < span);
+    if (__ballot(!good)) return false;
+    const uint64_t live = __ballot(lcnt != 0u);
+    L.lcnt = lcnt;
+    L.hi = (loc << 1) | E.rw;
+    L.dhi = dl << 1;
+    L.id = gg * S.M + E.off + st.lstart;
+    L.live = live;
+    if (!live) {
+        L.n = 0;
+        return true;
+    }
+    const uint32_t sh = S.s;
+    if constexpr (FLAT) {
+        const uint32_t b0 = r0 >> sh, bN = rN >> sh;
+        const uint32_t mn = wave_min(lcnt ? min(b0, bN) : 0xFFFFFFFFu);
+        const uint32_t mx = wave_max(lcnt ? max(b0, bN) : 0u);
+        if (mn != mx) return false;
+        L.pb = mn;
+        L.cnt = wave_max(lcnt);
+        L.n = readlane(wave_incl_add(lcnt), 63);
+        L.starts = 1;
+    } else {
+        // every lane's point j is at rel r0 + j * dl (exact: all inside the
+        // pass), so the lanes' range at point j is [rmin, rmax] + j * dl
+        const uint32_t rmin = wave_min(lcnt ? r0 : 0xFFFFFFFFu);
+        const uint32_t rmax = wave_max(lcnt ? r0 : 0u);
+        const uint32_t cnt = readlane(lcnt, (uint32_t)__builtin_ctzll(live));
+        const uint32_t j = lane();
+        const bool pj = j < cnt;
+        const uint32_t blo = (rmin + j * dl) >> sh, bhi = (rmax + j * dl) >> sh;
+        if (__ballot(pj && blo != bhi)) return false;
+        const uint32_t bprev = (rmin + (j - 1u) * dl) >> sh;
+        L.pb = blo;
+        L.cnt = cnt;
+        L.n = cnt * (uint32_t)__popcll(live);
+        L.starts = __ballot(pj && (j == 0u || blo != bprev));
+    }
+    return true;
+}
+
+// Points in the run that lane j starts (j is a run start).
+__device__ __forceinline__ uint32_t run_points(const LinItem &L, uint32_t j) {
+    const uint64_t after = (L.starts >> j) >> 1;
+    return (after ? j + 1u + (uint32_t)__builtin_ctzll(after) : L.cnt) - j;
+}
+
+// Run body(S, E, K, li, variant) over this workgroup's work items: chunks of
+// ITEM_CHUNK consecutive items dealt out cyclically, so that items of very
+// different cost (linear items that place their records without a rank,
+// one-record-per-thread items that decode a thread per slot) spread evenly
+// over the workgroups.  Workgroups of one XCD (blockIdx.x mod 8) take
+// adjacent chunks of each round.  Items of one entry are consecutive, so the
+// entry's variant is chosen (and its constants loaded) once per entry inside
+// a chunk rather than once per item.
+constexpr uint32_t ITEM_CHUNK = 4;
+
 template <class Body>
 __device__ __forceinline__ void for_my_items(CSub *subs, uint32_t nsub, uint32_t nitems, Body &&body) {
-    uint32_t w0, w1;
-    my_items(nitems, w0, w1);
-    if (w0 >= w1) return;
-    Cursor cur;
-    seek(subs, nsub, w0, cur);
-    uint32_t w = w0;
-    for (;;) {
-        CSub &S = subs[cur.sub];
-        CEnt &E = cptr(S.entries)[cur.e];
-        CKer &K = *cptr(S.kc);
-        const uint32_t n = min(w1 - w, cur.e_items - cur.li);
-        const uint32_t l0 = cur.li;
-        auto run = [&](auto variant) {
-            for (uint32_t i = 0; i < n; i++) body(S, E, K, l0 + i, variant);
-        };
-        const uint32_t v = (E.flat ? 3u : 0u) + (E.fast == 2 ? 0u : E.fast ? 1u : 2u);
-        switch (v) {
-            case 0: run(Variant<0>{}); break;
-            case 1: run(Variant<1>{}); break;
-            case 2: run(Variant<2>{}); break;
-            case 3: run(Variant<3>{}); break;
-            case 4: run(Variant<4>{}); break;
-            default: run(Variant<5>{}); break;
+    const uint32_t G = gridDim.x;                  // multiple of 8
+    const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
+    for (uint32_t w0 = r * ITEM_CHUNK; w0 < nitems; w0 += G * ITEM_CHUNK) {
+        const uint32_t w1 = min(nitems, w0 + ITEM_CHUNK);
+        Cursor cur;
+        seek(subs, nsub, w0, cur);
+        uint32_t w = w0;
+        for (;;) {
+            CSub &S = subs[cur.sub];
+            CEnt &E = cptr(S.entries)[cur.e];
+            CKer &K = *cptr(S.kc);
+            const uint32_t n = min(w1 - w, cur.e_items - cur.li);
+            const uint32_t l0 = cur.li;
+            auto run = [&](auto variant) {
+                for (uint32_t i = 0; i < n; i++) body(S, E, K, l0 + i, variant);
+            };
+            const uint32_t v = (E.flat ? 3u : 0u) + (E.fast == 2 ? 0u : E.fast ? 1u : 2u);
+            switch (v) {
+                case 0: run(Variant<0>{}); break;
+                case 1: run(Variant<1>{}); break;
+                case 2: run(Variant<2>{}); break;
+                case 3: run(Variant<3>{}); break;
+                case 4: run(Variant<4>{}); break;
+                default: run(Variant<5>{}); break;
+            }
+            w += n;
+            if (w >= w1) break;
+            cur.li = l0 + n - 1;
+            advance(subs, cur);
         }
-        w += n;
-        if (w >= w1) break;
-        cur.li = l0 + n - 1;
-        advance(subs, cur);
     }
 }
 
@@ -521,7 +625,25 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
     __shared__ uint32_t h[BINCAP];
     __shared__ uint32_t red[3 * (EXP_WG / 64)];
     CSub *subs = cptr(subs_g);
+    uint32_t *const hw = h + (threadIdx.x >> 6) * WBIN;
     for_my_items(subs, nsub, nitems, [&](CSub &S, CEnt &E, CKer &K, uint32_t li, auto variant) {
+        // Fast entries count per wave (wave barriers only), so a wave may
+        // finish an item on its own (linear items in one bucket); general
+        // entries count per workgroup.
+        constexpr int V = decltype(variant)::value;
+        constexpr bool WAVE = V % 3 != 2;
+        uint32_t *gc = counts + S.bucket_begin;
+        if constexpr (WAVE) {
+            LinItem L;
+            if (E.lin && lin_probe<(V >= 3), (V % 3 == 0)>(S, E, K, li, L)) {
+                if (!L.n) return;
+                const uint32_t j = lane();
+                if ((L.starts >> j) & 1u)   // flat items: one run of all L.n records
+                    atomicAdd(&gc[L.pb], V >= 3 ? L.n : run_points(L, j) * (uint32_t)__popcll(L.live));
+                if (j == 0) atomicAdd(&res[S.res].records, (unsigned long long)L.n);
+                return;
+            }
+        }
         const uint32_t span = S.khi - S.klo;
         uint32_t bk[RPL];
         uint32_t mn = 0xFFFFFFFFu, mx = 0, n = 0;
@@ -535,10 +657,33 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
             if (v) { mn = min(mn, b); mx = max(mx, b); n++; }
         };
         expand_v(variant, S, E, K, li, on_rec);
-        block_min_max_sum<EXP_WG>(mn, mx, n, red);
-        if (n) {
+        if constexpr (WAVE) {
+            mn = wave_min(mn);
+            mx = wave_max(mx);
+            n = readlane(wave_incl_add(n), 63);
+            if (!n) return;
+            if (lane() == 0) atomicAdd(&res[S.res].records, (unsigned long long)n);
+            if (mx - mn < WBIN * WWIN) {
+                for (uint32_t w = mn;; w += WBIN) {
+                    const uint32_t R = min(WBIN, mx - w + 1);
+                    for (uint32_t i = lane(); i < R; i += 64) hw[i] = 0;
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int s = 0; s < RPL; s++) lds_rank(hw, bk[s] - w, bk[s] - w < R);
+                    __builtin_amdgcn_wave_barrier();
+                    for (uint32_t i = lane(); i < R; i += 64) {
+                        const uint32_t c = hw[i];
+                        if (c) atomicAdd(&gc[w + i], c);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (mx - w < WBIN) break;
+                }
+                return;
+            }
+        } else {
+            block_min_max_sum<EXP_WG>(mn, mx, n, red);
+            if (!n) return;
             if (threadIdx.x == 0) atomicAdd(&res[S.res].records, (unsigned long long)n);
-            uint32_t *gc = counts + S.bucket_begin;
             if (mx - mn < (uint32_t)(BINCAP * BINWIN)) {
                 // LDS bins over windows of BINCAP buckets of the tile's range
                 for (uint32_t w = mn;; w += BINCAP) {
@@ -555,20 +700,21 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
                     __syncthreads();
                     if (mx - w < (uint32_t)BINCAP) break;
                 }
-            } else {
+                return;
+            }
+        }
+        // records spread over more buckets than the windows cover
 #pragma unroll
-                for (int s = 0; s < RPL; s++) {
-                    const bool v = bk[s] != 0xFFFFFFFFu;
-                    const uint64_t act = __ballot(v);
-                    if (!act) continue;
-                    const uint32_t lead = (uint32_t)__builtin_ctzll(act);
-                    const uint32_t lb = readlane(bk[s], lead);
-                    if (__ballot(v && bk[s] == lb) == act) {
-                        if (lane() == lead) atomicAdd(&gc[lb], (uint32_t)__popcll(act));
-                    } else if (v) {
-                        atomicAdd(&gc[bk[s]], 1u);
-                    }
-                }
+        for (int s = 0; s < RPL; s++) {
+            const bool v = bk[s] != 0xFFFFFFFFu;
+            const uint64_t act = __ballot(v);
+            if (!act) continue;
+            const uint32_t lead = (uint32_t)__builtin_ctzll(act);
+            const uint32_t lb = readlane(bk[s], lead);
+            if (__ballot(v && bk[s] == lb) == act) {
+                if (lane() == lead) atomicAdd(&gc[lb], (uint32_t)__popcll(act));
+            } else if (v) {
+                atomicAdd(&gc[bk[s]], 1u);
             }
         }
     });
@@ -644,6 +790,49 @@ __global__ void __launch_bounds__(EXP_WG) __attribute__((amdgpu_waves_per_eu(5))
     CSub *subs = cptr(subs_g);
     uint32_t *const hw = bins + (threadIdx.x >> 6) * 2 * WBIN, *const gw = hw + WBIN;
     for_my_items(subs, nsub, nitems, [&](CSub &S, CEnt &E, CKer &K, uint32_t li, auto variant) {
+        constexpr int V = decltype(variant)::value;
+        if constexpr (V % 3 != 2) {
+            LinItem L;
+            if (E.lin && lin_probe<(V >= 3), (V % 3 == 0)>(S, E, K, li, L)) {
+                // one reservation per run of points; records go point by
+                // point, each point's lanes to consecutive addresses
+                if (!L.n) return;
+                const uint32_t j = lane();
+                uint32_t hi = L.hi, id = L.id;
+                if constexpr (V < 3) {
+                    const uint32_t P = (uint32_t)__popcll(L.live);
+                    uint32_t rb = 0;
+                    if ((L.starts >> j) & 1u) rb = atomicAdd(&cursor[S.bucket_begin + L.pb], run_points(L, j) * P);
+                    // lane j < cnt: the first slot of point j
+                    const uint64_t upto = L.starts & ((2ull << (j & 63u)) - 1ull);
+                    const uint32_t sj = upto ? 63u - (uint32_t)__builtin_clzll(upto) : 0u;
+                    const uint32_t pt = (uint32_t)__shfl((int)rb, (int)sj) + (j - sj) * P;
+                    // every lane runs the loop (point bases are read from
+                    // lanes that may hold no records); live lanes store
+                    const uint32_t mb = mbcnt(L.live);
+                    const bool mine = L.lcnt != 0u;
+                    for (uint32_t q = 0; q < L.cnt; q++) {
+                        const uint32_t at = readlane(pt, q) + mb;
+                        if (mine) rec[at] = ((unsigned long long)hi << 32) | id;
+                        hi += L.dhi;
+                        id++;
+                    }
+                } else {
+                    uint32_t base = 0;
+                    if (j == 0) base = atomicAdd(&cursor[S.bucket_begin + L.pb], L.n);
+                    base = readlane(base, 0);
+                    for (uint32_t q = 0; q < L.cnt; q++) {
+                        const bool v = q < L.lcnt;
+                        const uint64_t act = __ballot(v);
+                        if (v) rec[base + mbcnt(act)] = ((unsigned long long)hi << 32) | id;
+                        base += (uint32_t)__popcll(act);
+                        hi += L.dhi;
+                        id++;
+                    }
+                }
+                return;
+            }
+        }
         const uint32_t span = S.khi - S.klo;
         const uint32_t rwbit = E.rw;
         unsigned long long r[RPL];
@@ -1242,6 +1431,16 @@ __device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx,
             if (c[i]) put_witness(wout, pos++, lo + t * TP + i, e[i], second[i], srw[i]);
     }
     return total;
+}
+
+// The contiguous run of buckets of this workgroup; runs of workgroups that
+// share an XCD are adjacent.
+__device__ __forceinline__ void my_items(uint32_t n, uint32_t &w0, uint32_t &w1) {
+    const uint32_t G = gridDim.x;                  // multiple of 8
+    const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
+    const uint32_t per = (n + G - 1) / G;
+    w0 = min(n, r * per);
+    w1 = min(n, w0 + per);
 }
 
 __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t nsub, uint32_t nbuckets,

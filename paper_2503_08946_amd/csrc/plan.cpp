@@ -293,6 +293,16 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 } else {
                     E.lch = 1; E.gt = 1; E.n_lchunks = 0;
                 }
+                {
+                    // linear items: chunks of one thread never cross a step of
+                    // an outer loop (the innermost loop's extent is a multiple
+                    // of the chunk, or it is the only loop with extent > 1)
+                    const uint32_t inner = E.ext[2] > 1 ? 2u : E.ext[1] > 1 ? 1u : 0u;
+                    const bool only = E.box == E.ext[inner];
+                    E.linner = inner;
+                    E.lin = (E.fast != 0 && E.box > 0 && E.gt == 1 &&
+                             (only || E.ext[inner] % E.lch == 0)) ? 1u : 0u;
+                }
                 E.mg_nl = make_magic(std::max<uint32_t>(E.n_lchunks, 1));
                 E.mg_e1 = make_magic(std::max<uint32_t>(E.ext[1], 1));
                 E.mg_e2 = make_magic(std::max<uint32_t>(E.ext[2], 1));

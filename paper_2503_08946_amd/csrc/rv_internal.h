@@ -100,6 +100,11 @@ struct DevEntry {
     uint32_t fast;
     uint32_t ndim;
     uint32_t fr[NC];
+    // Linear items (fast entries, one thread per lane, lch points of the
+    // innermost non-trivial loop `linner` that never wrap inside a chunk):
+    // every index and the location are affine in the point of the chunk.
+    uint32_t lin;
+    uint32_t linner;
 };
 
 struct DevKernel {
