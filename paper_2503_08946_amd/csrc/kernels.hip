@@ -1433,15 +1433,11 @@ __device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx,
     return total;
 }
 
-// The contiguous run of buckets of this workgroup; runs of workgroups that
-// share an XCD are adjacent.
-__device__ __forceinline__ void my_items(uint32_t n, uint32_t &w0, uint32_t &w1) {
-    const uint32_t G = gridDim.x;                  // multiple of 8
-    const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
-    const uint32_t per = (n + G - 1) / G;
-    w0 = min(n, r * per);
-    w1 = min(n, w0 + per);
-}
+// The fold deals groups of FOLD_GROUP consecutive buckets out cyclically
+// (workgroups of one XCD take adjacent groups of each round), which evens
+// out buckets of different sizes across workgroups.
+constexpr uint32_t FOLD_GROUP = 64;
+static_assert(FOLD_GROUP <= BKT_WG, "one listing thread per bucket of a group");
 
 __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t nsub, uint32_t nbuckets,
                                                   unsigned long long *__restrict__ rec,
@@ -1453,19 +1449,20 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
     __shared__ uint32_t red[BKT_WG / 64];
     CSub *subs = cptr(subs_g);
     const uint32_t t = threadIdx.x;
-    uint32_t b0, b1;
-    my_items(nbuckets, b0, b1);
-    if (b0 >= b1) return;
-    uint32_t sidx = sub_of_bucket(subs, nsub, b0);     // buckets only increase: walk forward from here
+    const uint32_t G = gridDim.x;                  // multiple of 8
+    const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
+    if (r * FOLD_GROUP >= nbuckets) return;
+    uint32_t sidx = sub_of_bucket(subs, nsub, r * FOLD_GROUP);   // groups only increase: walk forward
 #pragma unroll
     for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
         const uint32_t k = t * (TBL / BKT_WG) + k2;
         t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
     }
-    for (uint32_t base = b0; base < b1; base += BKT_WG) {
+    for (uint32_t base = r * FOLD_GROUP; base < nbuckets; base += G * FOLD_GROUP) {
         // --- list this group's non-empty buckets (in order) and the hot ones
+        const uint32_t b1 = min(nbuckets, base + FOLD_GROUP);
         const uint32_t mb = base + t;
-        const bool inr = mb < b1;
+        const bool inr = t < FOLD_GROUP && mb < b1;
         const uint32_t c = inr ? counts[mb] : 0u;
         const bool take = c != 0 && c <= FOLD_CAP;
         const bool is_hot = c > HOT;

@@ -101,7 +101,7 @@ class rv_timing(ctypes.Structure):
 class rv_kernel_info(ctypes.Structure):
     _fields_ = [("n_instances", u64), ("n_intervals", u32), ("n_subintervals", u32),
                 ("n_chunks", u32), ("n_buckets", u32), ("max_interval_instances", u64),
-                ("n_entries", u32), ("n_flat_entries", u32)]
+                ("n_entries", u32), ("n_flat_entries", u32), ("n_linear_entries", u32), ("reserved", u32)]
 
 
 class rv_record(ctypes.Structure):

@@ -158,6 +158,119 @@ def test_sort_output_is_sorted_permutation(ctx, desc):
         assert np.array_equal(a, b)
 
 
+# ------------------------------------------------- linear work items
+def _records_equal(ctx, k, desc):
+    for iv in range(oracle.n_intervals(desc)):
+        ref = oracle.records(desc, iv)
+        got = ctx.debug_records(k, iv, sorted=False)
+        assert np.array_equal(ref[np.lexsort(ref.T[::-1])], got[np.lexsort(got.T[::-1])])
+
+
+def _linear_case(name):
+    # Entries whose lanes each take one thread and consecutive points of the
+    # innermost loop: the records of a chunk are placed per run of points
+    # sharing a bucket, with a fallback to the per-record rank when a chunk
+    # leaves the bounds, the key range or a common bucket.  Each case pairs
+    # accesses without thread terms (all lanes of a wave at one location per
+    # point: the run path by construction) with accesses whose lanes spread
+    # over several buckets per point (the fallback).
+    if name == "partial-chunk":          # 40 points: chunks of 16, 16, 8
+        b = Builder((64, 2), (3, 1), name)
+        s = b.array(SHARED, (2, 40))
+        t = b.array(SHARED, (2, 64, 40))
+        p = b.phase([rw(s, True, aff(ty=1), aff(l0=1), loops=((0, 40),)),
+                     rw(s, False, aff(1, ty=-1), aff(39, l0=-1), loops=((0, 40),)),
+                     rw(t, True, aff(ty=1), aff(tx=1), aff(l0=1), loops=((0, 40),)),
+                     rw(t, False, aff(1, ty=-1), aff(63, tx=-1), aff(l0=1), loops=((0, 40),))], False)
+        b.segment([p])
+    elif name == "descending":           # location falls by 33 per point, crossing buckets
+        b = Builder((128, 1), (4, 1), name)
+        g = b.array(GLOBAL, (200000,))
+        p = b.phase([rw(g, True, aff(190000, bx=128, l0=-33), loops=((0, 48),)),
+                     rw(g, False, aff(190000, bx=128, l0=-33), loops=((0, 48),)),
+                     rw(g, True, aff(100000, tx=1, bx=128, l0=-33), loops=((0, 48),)),
+                     rw(g, False, aff(100001, tx=1, bx=128, l0=-33), loops=((0, 48),))], False)
+        b.segment([p])
+    elif name == "two-loops":            # inner extent 32 (linear) and 20 (wraps: not linear)
+        b = Builder((32, 4), (2, 2), name)
+        s = b.array(SHARED, (8, 40))
+        g = b.array(GLOBAL, (64, 64))
+        p = b.phase([rw(s, True, aff(l0=1), aff(l1=1), loops=((0, 8), (0, 32))),
+                     rw(s, False, aff(l0=1), aff(l1=1), loops=((0, 8), (3, 23))),
+                     rw(g, False, aff(ty=1, by=4, l0=1), aff(tx=1, bx=32), loops=((0, 16),))], True)
+        q = b.phase([rw(g, True, aff(ty=1, by=4, l0=1), aff(tx=1, bx=32), loops=((0, 16),)),
+                     rw(g, False, aff(ty=1, by=4, l0=1), aff(63, tx=-1, bx=-32), loops=((0, 16),))], False)
+        b.segment([p, q])
+    elif name == "stride-buckets":       # 37 locations per point: runs of points per bucket
+        b = Builder((64, 1), (8, 1), name)
+        g = b.array(GLOBAL, (1 << 16,))
+        p = b.phase([rw(g, False, aff(2048, bx=4096, l0=37), loops=((0, 64),)),
+                     rw(g, True, aff(2048, bx=4096, l0=37), loops=((0, 64),)),
+                     rw(g, False, aff(tx=1, bx=4096, l0=7), loops=((0, 64),)),
+                     rw(g, True, aff(5, tx=1, bx=4096, l0=7), loops=((0, 64),))], False)
+        b.segment([p])
+    elif name == "flat-few-threads":     # 3 threads: loop chunks spread over the lanes
+        b = Builder((3, 1), (1, 1), name)
+        g = b.array(GLOBAL, (2000,))
+        p = b.phase([rw(g, True, aff(7, l0=1), loops=((0, 40),)),
+                     rw(g, False, aff(l0=1), loops=((0, 40),)),
+                     rw(g, True, aff(tx=500, l0=1), loops=((0, 500),)),
+                     rw(g, False, aff(tx=500, l0=2), loops=((0, 500),))], False)
+        b.segment([p])
+    elif name == "pass-boundary":        # chunks straddle the first key-range pass's end (2^29)
+        b = Builder((64, 1), (2, 1), name)
+        g = b.array(GLOBAL, (1 << 30,))
+        p = b.phase([rw(g, True, aff((1 << 29) - 8, bx=1, l0=1), loops=((0, 16),)),
+                     rw(g, False, aff((1 << 29) - 8, l0=1), loops=((0, 16),)),
+                     rw(g, True, aff(3 << 28, l0=1), loops=((0, 32),)),
+                     rw(g, False, aff(3 << 28, tx=3, l0=1), loops=((0, 32),))], False)
+        b.segment([p])
+    elif name == "edge-out-of-bounds":   # block 1's last threads leave the array mid-chunk: fallback
+        b = Builder((64, 1), (2, 1), name)
+        g = b.array(GLOBAL, (1990,))
+        p = b.phase([rw(g, False, aff(tx=16, bx=1024, l0=1), loops=((0, 16),))], False)
+        b.segment([p])
+    else:
+        raise ValueError(name)
+    return b.build()
+
+
+@pytest.mark.parametrize("name", ["partial-chunk", "descending", "two-loops", "stride-buckets",
+                                  "flat-few-threads", "pass-boundary"])
+def test_linear_items(ctx, name):
+    desc = _linear_case(name)
+    k, r, o = compare(ctx, desc)
+    info = k.info()
+    say(f"[linear] {name}: {info.n_linear_entries} of {info.n_entries} entries linear")
+    assert info.n_linear_entries > 0
+    if name == "two-loops":
+        assert info.n_linear_entries < info.n_entries
+    if name == "pass-boundary":
+        # the record dump needs every pass of an interval in one workspace
+        # (two passes of 2^20 buckets do not fit): counts and witnesses above
+        assert info.n_subintervals >= 2
+        return
+    _records_equal(ctx, k, desc)
+
+
+def test_linear_items_out_of_bounds(ctx):
+    import paper_2503_08946_amd as rv
+    desc = _linear_case("edge-out-of-bounds")
+    o = oracle.check(desc)
+    assert o.status == -5
+    k = ctx.load(desc)
+    assert k.info().n_linear_entries == 1
+    with pytest.raises(rv.RVError) as e:
+        ctx.check(k)
+    assert e.value.status == -5
+    # the oracle's first out-of-bounds instance: thread 60 of block 1 at l0 = 6
+    # (index 60 * 16 + 1024 + 6 = 1990)
+    iv, gthread, dphase, access, lidx = o.oob
+    assert (iv, gthread, lidx) == (0, 124, 6)
+    say(f"[linear] {e.value.message}")
+    assert f"interval {iv}, block 1, thread 60, dynamic phase {dphase}, access {access}" in e.value.message
+
+
 # ------------------------------------------------------------- edge cases
 def test_empty_kernel(ctx):
     b = Builder((4, 1), (1, 1), "empty")
