@@ -170,9 +170,10 @@ typedef struct {
     uint64_t max_interval_instances;
     uint32_t n_entries;        /* (interval, dynamic phase, access) expansion entries */
     uint32_t n_flat_entries;   /* of which expanded with loop chunks across lanes (few threads) */
-    uint32_t n_linear_entries; /* of which each lane's records in a work item are one thread's
-                                  consecutive innermost-loop points (placed per run of points
-                                  when they share buckets, without a per-record rank) */
+    uint32_t n_linear_entries; /* of which each lane's records in a work item are affine in the
+                                  slot: one thread's consecutive innermost-loop points, or one
+                                  instance each of consecutive threads differing in tx alone
+                                  (ranked per lane or per run, not per record, when they can be) */
     uint32_t reserved;         /* 0 */
 } rv_kernel_info;
 

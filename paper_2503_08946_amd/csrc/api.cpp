@@ -609,7 +609,7 @@ rv_status rv_kernel_get_info(rv_ctx *c, const rv_kernel *k, rv_kernel_info *out)
     out->max_interval_instances = k->max_interval_instances;
     out->n_entries = (uint32_t)k->entries.size();
     uint32_t nf = 0, nl = 0;
-    for (const auto &e : k->entries) { nf += e.flat; nl += e.lin; }
+    for (const auto &e : k->entries) { nf += e.flat; nl += e.lin + e.tlin; }
     out->n_flat_entries = nf;
     out->n_linear_entries = nl;
     out->reserved = 0;

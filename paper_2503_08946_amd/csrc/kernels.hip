@@ -448,6 +448,12 @@ __device__ __forceinline__ void expand_v(Variant<V>, CSub &S, CEnt &E, CKer &K, 
     else expand_item<FLAT>(S, E, K, cptr(S.guards), li, f);
 }
 
+// Per-wave binning (count pass and scatter): each wave takes WBIN bins of the
+// shared area, over at most WWIN windows of its own bucket range.
+constexpr int EXP_NW = EXP_WG / 64;
+constexpr uint32_t WBIN = BINCAP / EXP_NW;
+constexpr uint32_t WWIN = 16;
+
 // Linear work items.  A lane's records in an item of a linear entry are
 // one thread's lcnt consecutive points of the innermost loop, so each index
 // and the location are affine in the point: an index lies inside its
@@ -547,6 +553,71 @@ __device__ __forceinline__ bool lin_probe(CSub &S, CEnt &E, CKer &K, uint32_t it
     return true;
 }
 
+// Thread-linear work items (flat mapping, one instance per thread): lane q
+// takes gt consecutive threads, which differ in tx alone, so each index and
+// the location are affine in the slot (steps row[.][tx] and fr[tx], ids step
+// by the interval's per-thread count M).  tlin_probe succeeds (wave-
+// uniformly) when every record of the wave is in bounds and inside the
+// pass's key range, every live lane holds gt records, each lane's records
+// share one bucket and the wave's buckets span fewer than WBIN; a lane is
+// then ranked among the wave's lanes of its bucket with one LDS atomic.
+struct TLinItem {
+    uint32_t lcnt;          // records of this lane
+    uint32_t hi, dhi;       // first record's key half, step per slot
+    uint32_t id, did;       // first record's id, step per slot
+    uint32_t bin;           // this lane's bucket relative to the wave's first
+    uint32_t mn, R;         // the wave's first bucket (relative to the pass) and bucket span
+    uint32_t n;             // records of the wave
+};
+
+template <bool PROVEN>
+__device__ __forceinline__ bool tlin_probe(CSub &S, CEnt &E, CKer &K, uint32_t item, TLinItem &L) {
+    const ItemStart<true> st = item_start<true>(E, K, item);
+    const bool gval = st.g0 < K.nthreads;
+    const uint32_t gg = gval ? st.g0 : 0u;
+    const uint32_t blk = udiv(gg, ldm(K.mg_tpb));
+    const uint32_t tid = gg - blk * K.tpb;
+    const uint32_t byy = udiv(blk, ldm(K.mg_gdx));
+    const uint32_t tyy = udiv(tid, ldm(K.mg_bdx));
+    const uint32_t tx = tid - tyy * K.bdx, ty = tyy, bx = blk - byy * K.gdx, by = byy;
+    const uint32_t L0 = (uint32_t)E.lo[0] + st.c0, L1 = (uint32_t)E.lo[1] + st.c1, L2 = (uint32_t)E.lo[2] + st.c2;
+    const uint32_t lcnt = gval ? min(E.gt, K.nthreads - gg) : 0u;
+    const uint32_t last = lcnt - 1u;
+    const uint32_t loc = blk * E.loc_mul + E.fr[C_TX] * tx + E.fr[C_TY] * ty + E.fr[C_BX] * bx +
+                         E.fr[C_BY] * by + E.fr[C_C0] + E.fr[C_L0] * L0 + E.fr[C_L1] * L1 + E.fr[C_L2] * L2;
+    const uint32_t dl = E.fr[C_TX];
+    bool good = true;
+    if constexpr (!PROVEN) {
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            const uint32_t i0 = (uint32_t)E.row[r][C_TX] * tx + (uint32_t)E.row[r][C_TY] * ty +
+                                (uint32_t)E.row[r][C_BX] * bx + (uint32_t)E.row[r][C_BY] * by +
+                                (uint32_t)E.row[r][C_C0] + (uint32_t)E.row[r][C_L0] * L0 +
+                                (uint32_t)E.row[r][C_L1] * L1 + (uint32_t)E.row[r][C_L2] * L2;
+            const uint32_t iN = i0 + last * (uint32_t)E.row[r][C_TX];
+            good = good && i0 < E.dim[r] && iN < E.dim[r];
+        }
+    }
+    const uint32_t span = S.khi - S.klo;
+    const uint32_t r0 = loc - S.klo, rN = loc + last * dl - S.klo;
+    const uint32_t b0 = r0 >> S.s;
+    good = lcnt == 0u || (good && lcnt == E.gt && r0 < span && rN < span && b0 == (rN >> S.s));
+    if (__ballot(!good)) return false;
+    const uint32_t mn = wave_min(lcnt ? b0 : 0xFFFFFFFFu);
+    const uint32_t mx = wave_max(lcnt ? b0 : 0u);
+    L.n = readlane(wave_incl_add(lcnt), 63);
+    if (L.n && mx - mn >= WBIN) return false;
+    L.lcnt = lcnt;
+    L.hi = (loc << 1) | E.rw;
+    L.dhi = dl << 1;
+    L.id = gg * S.M + E.off;
+    L.did = S.M;
+    L.bin = b0 - mn;
+    L.mn = mn;
+    L.R = mx - mn + 1u;
+    return true;
+}
+
 // Points in the run that lane j starts (j is a run start).
 __device__ __forceinline__ uint32_t run_points(const LinItem &L, uint32_t j) {
     const uint64_t after = (L.starts >> j) >> 1;
@@ -613,12 +684,6 @@ __global__ void k_init_results(SubResult *r, size_t n) {
     }
 }
 
-// Per-wave binning in the scatter: each wave takes WBIN bins of the shared
-// area, over at most WWIN windows of its own bucket range.
-constexpr int EXP_NW = EXP_WG / 64;
-constexpr uint32_t WBIN = BINCAP / EXP_NW;
-constexpr uint32_t WWIN = 16;
-
 // --------------------------------------------------------------- count pass
 __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t nsub, uint32_t nitems,
                                                   uint32_t *__restrict__ counts, SubResult *__restrict__ res) {
@@ -633,6 +698,23 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
         constexpr int V = decltype(variant)::value;
         constexpr bool WAVE = V % 3 != 2;
         uint32_t *gc = counts + S.bucket_begin;
+        if constexpr (V == 3 || V == 4) {
+            TLinItem T;
+            if (E.tlin && tlin_probe<(V == 3)>(S, E, K, li, T)) {
+                if (!T.n) return;
+                for (uint32_t i = lane(); i < T.R; i += 64) hw[i] = 0;
+                __builtin_amdgcn_wave_barrier();
+                if (T.lcnt) atomicAdd(&hw[T.bin], T.lcnt);
+                __builtin_amdgcn_wave_barrier();
+                for (uint32_t i = lane(); i < T.R; i += 64) {
+                    const uint32_t c = hw[i];
+                    if (c) atomicAdd(&gc[T.mn + i], c);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane() == 0) atomicAdd(&res[S.res].records, (unsigned long long)T.n);
+                return;
+            }
+        }
         if constexpr (WAVE) {
             LinItem L;
             if (E.lin && lin_probe<(V >= 3), (V % 3 == 0)>(S, E, K, li, L)) {
@@ -791,6 +873,38 @@ __global__ void __launch_bounds__(EXP_WG) __attribute__((amdgpu_waves_per_eu(5))
     uint32_t *const hw = bins + (threadIdx.x >> 6) * 2 * WBIN, *const gw = hw + WBIN;
     for_my_items(subs, nsub, nitems, [&](CSub &S, CEnt &E, CKer &K, uint32_t li, auto variant) {
         constexpr int V = decltype(variant)::value;
+        if constexpr (V == 3 || V == 4) {
+            TLinItem T;
+            if (E.tlin && tlin_probe<(V == 3)>(S, E, K, li, T)) {
+                // one LDS rank per lane among the wave's lanes of its bucket,
+                // one reservation per bucket (gt records per lane); slot q of
+                // the lane ranked k goes to base + q x lanes + k, so the lanes
+                // of a bucket store to consecutive addresses
+                if (!T.n) return;
+                for (uint32_t i = lane(); i < T.R; i += 64) hw[i] = 0;
+                __builtin_amdgcn_wave_barrier();
+                uint32_t rk = 0;
+                if (T.lcnt) rk = atomicAdd(&hw[T.bin], 1u);
+                __builtin_amdgcn_wave_barrier();
+                for (uint32_t i = lane(); i < T.R; i += 64) {
+                    const uint32_t c = hw[i];
+                    if (c) gw[i] = atomicAdd(&cursor[S.bucket_begin + T.mn + i], c * E.gt);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (T.lcnt) {
+                    const uint32_t lanes = hw[T.bin];
+                    unsigned long long *p = rec + gw[T.bin] + rk;
+                    uint32_t hi = T.hi, id = T.id;
+                    for (uint32_t q = 0; q < T.lcnt; q++) {
+                        p[(size_t)q * lanes] = ((unsigned long long)hi << 32) | id;
+                        hi += T.dhi;
+                        id += T.did;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                return;
+            }
+        }
         if constexpr (V % 3 != 2) {
             LinItem L;
             if (E.lin && lin_probe<(V >= 3), (V % 3 == 0)>(S, E, K, li, L)) {

@@ -315,6 +315,12 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                     const uint64_t nq = ntg * E.n_lchunks;
                     const uint64_t flat_items = (nq + EXP_WG - 1) / EXP_WG;
                     E.flat = (flat_items * 8 < thr_items * 7) ? 1u : 0u;
+                    // thread-linear: one instance per thread and rows of a
+                    // multiple of gt threads, so the gt consecutive threads of
+                    // a lane (flat mapping) differ in tx alone and every
+                    // index and the location are affine in the slot
+                    E.tlin = (E.fast != 0 && E.box == 1 && bdx % E.gt == 0) ? 1u : 0u;
+                    if (E.tlin) E.flat = 1;
                     E.nq = E.flat ? (uint32_t)nq : 0u;
                 }
                 M += box;

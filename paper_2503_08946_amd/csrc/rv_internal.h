@@ -105,6 +105,11 @@ struct DevEntry {
     // every index and the location are affine in the point of the chunk.
     uint32_t lin;
     uint32_t linner;
+    // Thread-linear items (fast entries of one instance per thread, flat
+    // mapping, a lane's gt consecutive threads differ in tx alone): every
+    // index and the location are affine in the slot.
+    uint32_t tlin;
+    uint32_t pad0;
 };
 
 struct DevKernel {

@@ -225,6 +225,23 @@ def _linear_case(name):
                      rw(g, True, aff(3 << 28, l0=1), loops=((0, 32),)),
                      rw(g, False, aff(3 << 28, tx=3, l0=1), loops=((0, 32),))], False)
         b.segment([p])
+    elif name == "thread-linear":        # no loops: a lane takes 16 consecutive threads (tx alone varies)
+        b = Builder((64, 2), (4, 2), name)
+        g = b.array(GLOBAL, (4096,))
+        s = b.array(SHARED, (2, 64))
+        p = b.phase([rw(g, True, aff(tx=1, ty=64, bx=128, by=512)),
+                     rw(g, False, aff(5, tx=3, ty=192, bx=384, by=1536)),     # 3 locations per thread
+                     rw(s, True, aff(ty=1), aff(7)),                          # broadcast: one location
+                     rw(s, False, aff(ty=1), aff(63, tx=-1)),                 # descending
+                     rw(g, False, aff(tx=60, bx=1)),                          # lanes over many buckets
+                     rw(s, False, aff(1, ty=-1), aff(tx=1), guards=(aff(30, tx=-1),))], True)
+        q = b.phase([rw(s, True, aff(ty=1), aff(tx=1)), rw(g, True, aff(2048, tx=1, by=64))], False)
+        b.segment([p, q])
+    elif name == "thread-linear-oob":    # a lane's 16 threads run off the array
+        b = Builder((32, 1), (2, 1), name)
+        g = b.array(GLOBAL, (100,))
+        p = b.phase([rw(g, False, aff(40, tx=2, bx=4))], False)
+        b.segment([p])
     elif name == "edge-out-of-bounds":   # block 1's last threads leave the array mid-chunk: fallback
         b = Builder((64, 1), (2, 1), name)
         g = b.array(GLOBAL, (1990,))
@@ -236,7 +253,7 @@ def _linear_case(name):
 
 
 @pytest.mark.parametrize("name", ["partial-chunk", "descending", "two-loops", "stride-buckets",
-                                  "flat-few-threads", "pass-boundary"])
+                                  "flat-few-threads", "pass-boundary", "thread-linear"])
 def test_linear_items(ctx, name):
     desc = _linear_case(name)
     k, r, o = compare(ctx, desc)
@@ -251,6 +268,22 @@ def test_linear_items(ctx, name):
         assert info.n_subintervals >= 2
         return
     _records_equal(ctx, k, desc)
+
+
+def test_thread_linear_out_of_bounds(ctx):
+    import paper_2503_08946_amd as rv
+    desc = _linear_case("thread-linear-oob")
+    o = oracle.check(desc)
+    assert o.status == -5
+    k = ctx.load(desc)
+    assert k.info().n_linear_entries == 1
+    with pytest.raises(rv.RVError) as e:
+        ctx.check(k)
+    assert e.value.status == -5
+    # first out-of-bounds instance: index 40 + 2 tx + 4 bx >= 100 at tx = 30 of block 0
+    iv, gthread, dphase, access, lidx = o.oob
+    assert (iv, gthread) == (0, 30)
+    assert f"interval {iv}, block 0, thread 30, dynamic phase {dphase}, access {access}" in e.value.message
 
 
 def test_linear_items_out_of_bounds(ctx):
