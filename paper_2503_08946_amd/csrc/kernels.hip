@@ -1383,6 +1383,11 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 // Records of a lane's contiguous run of one slice: slice of n records, lane
 // `me` of NL takes [me * rpl, me * rpl + m).
+struct __attribute__((aligned(8))) RecPair {
+    unsigned long long a, b;
+};
+static_assert(FOLD_RPL % 2 == 0, "fold runs load records in pairs");
+
 template <int NL>
 struct Run {
     uint32_t rpl, m;
@@ -1395,14 +1400,22 @@ __device__ __forceinline__ void run_load(Run<NL> &r, const unsigned long long *_
     r.rpl = (n + NL - 1) / NL;
     const uint32_t r0 = me * r.rpl;
     r.m = r0 < n ? min(r.rpl, n - r0) : 0u;
-    // Every lane issues all FOLD_RPL loads (indices clamped into its run, or
-    // to the slice's first record), so the loads are unconditional and the
+    // Every lane issues all its loads (indices clamped into its run, or to
+    // the slice's first record), so the loads are unconditional and the
     // compiler can leave them in flight while the previous bucket is folded.
     // Entries at or past m are never read (run_fold stops at m).
+    // Loads go in pairs of records (16 bytes, 8-byte aligned: one dwordx4
+    // per pair), the last pair starting at the run's last even index; a pair
+    // may read one record past the lane's run, at most one past the slice
+    // (the record area keeps a record of slack at its end).
     const unsigned long long *p = src + (r.m ? r0 : 0u);
-    const uint32_t last = r.m ? r.m - 1 : 0u;
+    const uint32_t lastp = r.m ? (r.m - 1u) & ~1u : 0u;
 #pragma unroll
-    for (int i = 0; i < FOLD_RPL; i++) r.x[i] = p[min((uint32_t)i, last)];
+    for (int j = 0; j < FOLD_RPL / 2; j++) {
+        const RecPair v = *reinterpret_cast<const RecPair *>(p + min((uint32_t)(2 * j), lastp));
+        r.x[2 * j] = v.a;
+        r.x[2 * j + 1] = v.b;
+    }
 }
 
 // A lane's merge state: the summary of the run of equal location it is

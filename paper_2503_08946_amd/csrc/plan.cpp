@@ -387,7 +387,7 @@ WorkspaceLayout layout_workspace(size_t bytes) {
         WorkspaceLayout L{};
         const size_t BC = std::max<size_t>((size_t)NBMAX, R / 256);
         const size_t H = R / HOT + 1;    // at most this many buckets exceed HOT records
-        size_t off = al(R * 8);
+        size_t off = al(R * 8 + 8);      // one record of slack: the fold's pair loads may read it
         L.off_counts = off; off = al(off + BC * 4);
         L.off_starts = off; off = al(off + BC * 4);
         L.off_cursor = off; off = al(off + BC * 4);
