@@ -625,21 +625,30 @@ __device__ __forceinline__ uint32_t run_points(const LinItem &L, uint32_t j) {
 }
 
 // Run body(S, E, K, li, variant) over this workgroup's work items: chunks of
-// ITEM_CHUNK consecutive items dealt out cyclically, so that items of very
-// different cost (linear items that place their records without a rank,
+// up to ITEM_CHUNK consecutive items dealt out cyclically, so that items of
+// very different cost (linear items that place their records without a rank,
 // one-record-per-thread items that decode a thread per slot) spread evenly
-// over the workgroups.  Workgroups of one XCD (blockIdx.x mod 8) take
-// adjacent chunks of each round.  Items of one entry are consecutive, so the
-// entry's variant is chosen (and its constants loaded) once per entry inside
-// a chunk rather than once per item.
+// over the workgroups; launches with fewer items than ITEM_CHUNK per
+// workgroup take smaller chunks, so that every workgroup gets work.
+// Workgroups of one XCD (blockIdx.x mod 8) take adjacent chunks of each
+// round.  Items of one entry are consecutive, so the entry's variant is
+// chosen (and its constants loaded) once per entry inside a chunk rather
+// than once per item.
 constexpr uint32_t ITEM_CHUNK = 4;
+
+// Chunk size for n units dealt cyclically over G workgroups: at most `cap`,
+// and no more than one round's share when the units are few.
+__device__ __forceinline__ uint32_t deal_chunk(uint32_t n, uint32_t G, uint32_t cap) {
+    return max(1u, min(cap, (n + G - 1) / G));
+}
 
 template <class Body>
 __device__ __forceinline__ void for_my_items(CSub *subs, uint32_t nsub, uint32_t nitems, Body &&body) {
     const uint32_t G = gridDim.x;                  // multiple of 8
     const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
-    for (uint32_t w0 = r * ITEM_CHUNK; w0 < nitems; w0 += G * ITEM_CHUNK) {
-        const uint32_t w1 = min(nitems, w0 + ITEM_CHUNK);
+    const uint32_t ch = deal_chunk(nitems, G, ITEM_CHUNK);
+    for (uint32_t w0 = r * ch; w0 < nitems; w0 += G * ch) {
+        const uint32_t w1 = min(nitems, w0 + ch);
         Cursor cur;
         seek(subs, nsub, w0, cur);
         uint32_t w = w0;
@@ -1560,12 +1569,18 @@ __device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx,
     return total;
 }
 
-// The fold deals groups of FOLD_GROUP consecutive buckets out cyclically
-// (workgroups of one XCD take adjacent groups of each round), which evens
-// out buckets of different sizes across workgroups.
+// The fold deals groups of up to FOLD_GROUP consecutive buckets out
+// cyclically (workgroups of one XCD take adjacent groups of each round),
+// which evens out buckets of different sizes across workgroups; with few
+// buckets the groups shrink so that every workgroup gets some.
 constexpr uint32_t FOLD_GROUP = 64;
 static_assert(FOLD_GROUP <= BKT_WG, "one listing thread per bucket of a group");
 
+// GS > 0: groups of GS buckets (launches with at least GS groups per
+// workgroup); GS = 0: groups of deal_chunk(nbuckets, grid, FOLD_GROUP).  The
+// compile-time group size measured markedly faster on launches of millions
+// of sparse buckets, hence two instances.
+template <uint32_t GS>
 __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t nsub, uint32_t nbuckets,
                                                   unsigned long long *__restrict__ rec,
                                                   const uint32_t *__restrict__ starts,
@@ -1578,18 +1593,19 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
     const uint32_t t = threadIdx.x;
     const uint32_t G = gridDim.x;                  // multiple of 8
     const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
-    if (r * FOLD_GROUP >= nbuckets) return;
-    uint32_t sidx = sub_of_bucket(subs, nsub, r * FOLD_GROUP);   // groups only increase: walk forward
+    const uint32_t gsz = GS ? GS : deal_chunk(nbuckets, G, FOLD_GROUP);
+    if (r * gsz >= nbuckets) return;
+    uint32_t sidx = sub_of_bucket(subs, nsub, r * gsz);   // groups only increase: walk forward
 #pragma unroll
     for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
         const uint32_t k = t * (TBL / BKT_WG) + k2;
         t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
     }
-    for (uint32_t base = r * FOLD_GROUP; base < nbuckets; base += G * FOLD_GROUP) {
+    for (uint32_t base = r * gsz; base < nbuckets; base += G * gsz) {
         // --- list this group's non-empty buckets (in order) and the hot ones
-        const uint32_t b1 = min(nbuckets, base + FOLD_GROUP);
+        const uint32_t b1 = min(nbuckets, base + gsz);
         const uint32_t mb = base + t;
-        const bool inr = t < FOLD_GROUP && mb < b1;
+        const bool inr = t < gsz && mb < b1;
         const uint32_t c = inr ? counts[mb] : 0u;
         const bool take = c != 0 && c <= FOLD_CAP;
         const bool is_hot = c > HOT;
@@ -1903,13 +1919,18 @@ void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned 
                  const uint32_t *starts, const uint32_t *counts, uint32_t *conf, HotArea hot, unsigned ncu,
                  hipStream_t st) {
     if (!nbuckets) return;
-    static const unsigned occ = occupancy(k_fold, BKT_WG, 4);
+    static const unsigned occ = occupancy(k_fold<FOLD_GROUP>, BKT_WG, 4);
     static const unsigned occ_hot = occupancy(k_hot, BKT_WG, 4);
     static const unsigned occ_mid = occupancy(k_mid, BKT_WG, 4);
     launch_fill_u32(hot.n, 1, 0u, st);
     launch_fill_u32(hot.mid_n, 1, 0u, st);
-    hipLaunchKernelGGL(k_fold, dim3(persistent_grid(nbuckets, ncu, occ)), dim3(BKT_WG), 0, st, subs, nsub,
-                       (uint32_t)nbuckets, rec, starts, counts, conf, hot);
+    const unsigned G = persistent_grid(nbuckets, ncu, occ);
+    if (nbuckets >= (uint64_t)FOLD_GROUP * G)
+        hipLaunchKernelGGL(k_fold<FOLD_GROUP>, dim3(G), dim3(BKT_WG), 0, st, subs, nsub, (uint32_t)nbuckets, rec,
+                           starts, counts, conf, hot);
+    else
+        hipLaunchKernelGGL(k_fold<0>, dim3(G), dim3(BKT_WG), 0, st, subs, nsub, (uint32_t)nbuckets, rec, starts,
+                           counts, conf, hot);
     hipLaunchKernelGGL(k_mid, dim3(ncu * occ_mid), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
     hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
 }
