@@ -1507,16 +1507,30 @@ __device__ __forceinline__ void run_fold(const Run<NL> &r, uint32_t lo, uint32_t
 // Each lane keeps its merge state from one slice to the next (its runs are
 // consecutive records of consecutive slices only in hot, single-location
 // stretches, which is where it matters: one flush per lane per call).
+// Two register sets alternate, as in the fold: while one slice is merged
+// the next one is loading.  A slice past r_end loads nothing of its own (its
+// clamped loads read the first records, m = 0), so every load is issued
+// unconditionally.
 template <int NL>
 __device__ __forceinline__ void fold_records(const unsigned long long *__restrict__ src, uint32_t r_begin,
                                              uint32_t r_end, uint32_t lo, uint32_t me, uint32_t *t_mn,
                                              uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1) {
+    constexpr uint32_t SL = NL * FOLD_RPL;
+    if (r_begin >= r_end) return;     // the clamped loads below read at r_begin
+    auto load = [&](Run<NL> &R, uint32_t sl) {
+        const bool in = sl < r_end;
+        run_load(R, src + (in ? sl : r_begin), in ? min(SL, r_end - sl) : 0u, me);
+    };
     Merge g;
     merge_init(g);
-    for (uint32_t slice = r_begin; slice < r_end; slice += NL * FOLD_RPL) {
-        Run<NL> r;
-        run_load(r, src + slice, min((uint32_t)(NL * FOLD_RPL), r_end - slice), me);
-        run_merge(r, lo, g, t_mn, t_mx, t_mnw, t_mxw1);
+    Run<NL> A, B;
+    load(A, r_begin);
+    load(B, r_begin + SL);
+    for (uint32_t sl = r_begin; sl < r_end; sl += 2 * SL) {
+        run_merge(A, lo, g, t_mn, t_mx, t_mnw, t_mxw1);
+        load(A, sl + 2 * SL);
+        run_merge(B, lo, g, t_mn, t_mx, t_mnw, t_mxw1);
+        load(B, sl + 3 * SL);
     }
     merge_flush(g, t_mn, t_mx, t_mnw, t_mxw1);
 }
