@@ -7,8 +7,14 @@
 //   k_scatter  expansion: evaluate the instances again, build the 8-byte
 //              records (location << 1 | rw, instance id) and write them
 //              grouped by bucket through an LDS-staged counting sort (the
-//              most significant radix digit of the location key)   [writes 8 B / record]
-//   k_bucket   per bucket: load the records on chip, LDS radix sort on the
+//              most significant radix digit of the location key); linear
+//              items reserve per run of points or per lane      [writes 8 B / record]
+//   k_fold     (default grouping) per bucket: fold each location's summary
+//              (min id, max id, min write id, max write id + 1) in LDS
+//              tables with atomics, judge every location, write canonical
+//              witnesses in location order; k_mid / k_hot take buckets
+//              above one slice / above 32K records                 [reads 8 B / record]
+//   k_bucket   (sort + scan grouping) per bucket: load the records on chip, LDS radix sort on the
 //              bucket's low key bits, segmented scan (ballot heads, DPP
 //              reductions) giving per location (min id, max id, min write
 //              id, max write id + 1); flag conflicting locations, count them
@@ -22,11 +28,11 @@
 //
 // Plan tables are read through the constant address space: they are
 // read-only during a launch, so the compiler keeps them in scalar registers
-// (s_load) even across the atomics of the loops.  Count and scatter run as
-// persistent grids whose workgroups own contiguous runs of work items;
-// adjacent runs go to the same XCD (workgroups are dealt round-robin over the
-// 8 XCDs), so the bucket counters and partially written lines they share stay
-// in one L2.
+// (s_load) even across the atomics of the loops.  Count, scatter and fold
+// run as persistent grids that deal their work items (buckets for the fold)
+// out in small chunks, cyclically; within a round, adjacent chunks go to the
+// same XCD (workgroups are dealt round-robin over the 8 XCDs), so the bucket
+// counters and partially written lines they share stay in one L2.
 
 #include <type_traits>
 
