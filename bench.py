@@ -318,7 +318,7 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU: the checker runs on a single GPU and has no multi-GPU path",
               file=sys.stderr)
         raise SystemExit(2)
 
