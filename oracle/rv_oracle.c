@@ -45,7 +45,13 @@
  *     and the largest-id record the largest: one of the two differs from
  *     first's thread.
  *
- * Arithmetic is int64 throughout.  qsort is the only library step.
+ * Arithmetic is exact int64: every product and sum is checked, and a value
+ * that would leave int64 stops the check with status -4 (the instance is
+ * reported as for an out-of-bounds index).  The paper's sets range over
+ * unbounded integers; int64 holds every value of a description whose
+ * variables and coefficients are int32 unless a sum of several large
+ * products overflows, which is reported instead of wrapped.  qsort is the
+ * only library step.
  */
 
 #include <stdint.h>
@@ -116,12 +122,14 @@ typedef struct {
 } orc_witness;
 
 typedef struct {
-    int64_t status;          /* 0 ok, -1 invalid description, -5 index out of bounds, -10 no memory */
+    int64_t status;          /* 0 ok, -1 invalid description, -4 a value left int64,
+                                -5 index out of bounds, -10 no memory */
     int64_t n_records;
     int64_t n_conflicts;     /* conflicting locations */
     int64_t n_pairs;         /* unordered distinct-thread pairs with >= 1 write (diagnostic) */
     int64_t n_intervals;
-    int64_t oob[5];          /* interval, gthread, dynamic phase, access, loop index */
+    int64_t oob[5];          /* interval, gthread, dynamic phase, access, loop index of the
+                                instance behind status -5 or -4 */
     int64_t n_witness;       /* witnesses written (<= capacity) */
 } orc_result;
 
@@ -165,7 +173,11 @@ static int kern_parse(const int64_t *w, int64_t len, kern_t *k) {
         a->dim[0] = p[2]; a->dim[1] = p[3]; a->dim[2] = p[4];
         if (a->space != 0 && a->space != 1) return -1;
         if (a->ndim < 1 || a->ndim > 3) return -1;
-        for (int d = 0; d < a->ndim; d++) if (a->dim[d] < 1) return -1;
+        int64_t elems = 1;
+        for (int d = 0; d < a->ndim; d++) {
+            if (a->dim[d] < 1) return -1;
+            if (__builtin_mul_overflow(elems, a->dim[d], &elems)) return -1;   /* flat index fits int64 */
+        }
     }
     for (int64_t i = 0; i < k->n_accesses; i++, p += ACC_W) {
         acc_t *a = &k->accesses[i];
@@ -227,20 +239,34 @@ static int kern_parse(const int64_t *w, int64_t len, kern_t *k) {
 }
 
 /* ------------------------------------------------------------- arithmetic */
-static int64_t eval_aff(const aff_t *a, const int64_t *v) {
+/* Checked int64 operations: *ovf is set when the exact result leaves int64. */
+static int64_t add_ck(int64_t a, int64_t b, int *ovf) {
+    int64_t r;
+    if (__builtin_add_overflow(a, b, &r)) *ovf = 1;
+    return r;
+}
+
+static int64_t mul_ck(int64_t a, int64_t b, int *ovf) {
+    int64_t r;
+    if (__builtin_mul_overflow(a, b, &r)) *ovf = 1;
+    return r;
+}
+
+static int64_t eval_aff(const aff_t *a, const int64_t *v, int *ovf) {
     int64_t s = a->c0;
-    for (int i = 0; i < NV; i++) s += a->coef[i] * v[i];
+    for (int i = 0; i < NV; i++) s = add_ck(s, mul_ck(a->coef[i], v[i], ovf), ovf);
     return s;
 }
 
-static int64_t floor_div(int64_t n, int64_t d) {      /* d >= 1 */
+static int64_t floor_div(int64_t n, int64_t d) {      /* d >= 1: no overflow */
     int64_t q = n / d;                               /* C truncates toward zero */
     if ((n % d != 0) && (n < 0)) q -= 1;
     return q;
 }
 
 static int64_t euclid_mod(int64_t n, int64_t d) {     /* result in [0, d) */
-    return n - d * floor_div(n, d);
+    int64_t r = n % d;                               /* same sign as n, |r| < d */
+    return r < 0 ? r + d : r;
 }
 
 /* ------------------------------------------------------------ enumeration */
@@ -284,7 +310,11 @@ static int enumerate_interval(const kern_t *k, int64_t iv, recvec_t *out, int64_
                     const arr_t *ar = &k->arrays[ac->array];
                     int64_t ext[3] = {1, 1, 1};
                     for (int l = 0; l < ac->nloops; l++) ext[l] = ac->hi[l] - ac->lo[l];
-                    const int64_t box = ext[0] * ext[1] * ext[2];
+                    int64_t box;
+                    if (__builtin_mul_overflow(ext[0], ext[1], &box) || __builtin_mul_overflow(box, ext[2], &box)) {
+                        oob[0] = iv; oob[1] = gthread; oob[2] = d; oob[3] = a; oob[4] = 0;
+                        return -4;
+                    }
                     for (int64_t li = 0; li < box; li++) {
                         int64_t v[NV] = {0};
                         v[V_TX] = tx; v[V_TY] = ty; v[V_BX] = bx; v[V_BY] = by; v[V_K] = k->dyn_k[d];
@@ -295,23 +325,32 @@ static int enumerate_interval(const kern_t *k, int64_t iv, recvec_t *out, int64_
                             rem /= ext[l];
                         }
                         for (int l = 0; l < 3; l++) v[V_L0 + l] = lv[l];
+                        int ovf = 0;
                         for (int x = 0; x < 2; x++) {
                             const aux_t *u = &ac->aux[x];
-                            if (u->kind == 1) v[V_AUX0 + x] = floor_div(eval_aff(&u->e, v), u->d);
-                            else if (u->kind == 2) v[V_AUX0 + x] = euclid_mod(eval_aff(&u->e, v), u->d);
+                            if (u->kind == 1) v[V_AUX0 + x] = floor_div(eval_aff(&u->e, v, &ovf), u->d);
+                            else if (u->kind == 2) v[V_AUX0 + x] = euclid_mod(eval_aff(&u->e, v, &ovf), u->d);
                         }
                         int ok = 1;
-                        for (int64_t g = ac->guard_begin; g < ac->guard_begin + ac->guard_count; g++)
-                            if (eval_aff(&k->guards[g], v) < 0) { ok = 0; break; }
+                        for (int64_t g = ac->guard_begin; g < ac->guard_begin + ac->guard_count && ok; g++)
+                            if (eval_aff(&k->guards[g], v, &ovf) < 0) ok = 0;
+                        if (ovf) {
+                            oob[0] = iv; oob[1] = gthread; oob[2] = d; oob[3] = a; oob[4] = li;
+                            return -4;
+                        }
                         if (!ok) continue;
                         int64_t flat = 0;
                         for (int dd = 0; dd < ar->ndim; dd++) {
-                            int64_t ix = eval_aff(&ac->idx[dd], v);
+                            int64_t ix = eval_aff(&ac->idx[dd], v, &ovf);
+                            if (ovf) {
+                                oob[0] = iv; oob[1] = gthread; oob[2] = d; oob[3] = a; oob[4] = li;
+                                return -4;
+                            }
                             if (ix < 0 || ix >= ar->dim[dd]) {
                                 oob[0] = iv; oob[1] = gthread; oob[2] = d; oob[3] = a; oob[4] = li;
                                 return -5;
                             }
-                            flat = flat * ar->dim[dd] + ix;
+                            flat = flat * ar->dim[dd] + ix;      /* < product of dims: checked at parse */
                         }
                         rec_t r;
                         r.space = ar->space;

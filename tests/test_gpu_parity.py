@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from cases import linear_case
 from workloads import kernels as K
 from workloads import random_affine as RA
 from workloads.desc import AUX_EMOD, AUX_FLOORDIV, GLOBAL, SHARED, Aux, Builder, aff, rw
@@ -166,96 +167,10 @@ def _records_equal(ctx, k, desc):
         assert np.array_equal(ref[np.lexsort(ref.T[::-1])], got[np.lexsort(got.T[::-1])])
 
 
-def _linear_case(name):
-    # Entries whose lanes each take one thread and consecutive points of the
-    # innermost loop: the records of a chunk are placed per run of points
-    # sharing a bucket, with a fallback to the per-record rank when a chunk
-    # leaves the bounds, the key range or a common bucket.  Each case pairs
-    # accesses without thread terms (all lanes of a wave at one location per
-    # point: the run path by construction) with accesses whose lanes spread
-    # over several buckets per point (the fallback).
-    if name == "partial-chunk":          # 40 points: chunks of 16, 16, 8
-        b = Builder((64, 2), (3, 1), name)
-        s = b.array(SHARED, (2, 40))
-        t = b.array(SHARED, (2, 64, 40))
-        p = b.phase([rw(s, True, aff(ty=1), aff(l0=1), loops=((0, 40),)),
-                     rw(s, False, aff(1, ty=-1), aff(39, l0=-1), loops=((0, 40),)),
-                     rw(t, True, aff(ty=1), aff(tx=1), aff(l0=1), loops=((0, 40),)),
-                     rw(t, False, aff(1, ty=-1), aff(63, tx=-1), aff(l0=1), loops=((0, 40),))], False)
-        b.segment([p])
-    elif name == "descending":           # location falls by 33 per point, crossing buckets
-        b = Builder((128, 1), (4, 1), name)
-        g = b.array(GLOBAL, (200000,))
-        p = b.phase([rw(g, True, aff(190000, bx=128, l0=-33), loops=((0, 48),)),
-                     rw(g, False, aff(190000, bx=128, l0=-33), loops=((0, 48),)),
-                     rw(g, True, aff(100000, tx=1, bx=128, l0=-33), loops=((0, 48),)),
-                     rw(g, False, aff(100001, tx=1, bx=128, l0=-33), loops=((0, 48),))], False)
-        b.segment([p])
-    elif name == "two-loops":            # inner extent 32 (linear) and 20 (wraps: not linear)
-        b = Builder((32, 4), (2, 2), name)
-        s = b.array(SHARED, (8, 40))
-        g = b.array(GLOBAL, (64, 64))
-        p = b.phase([rw(s, True, aff(l0=1), aff(l1=1), loops=((0, 8), (0, 32))),
-                     rw(s, False, aff(l0=1), aff(l1=1), loops=((0, 8), (3, 23))),
-                     rw(g, False, aff(ty=1, by=4, l0=1), aff(tx=1, bx=32), loops=((0, 16),))], True)
-        q = b.phase([rw(g, True, aff(ty=1, by=4, l0=1), aff(tx=1, bx=32), loops=((0, 16),)),
-                     rw(g, False, aff(ty=1, by=4, l0=1), aff(63, tx=-1, bx=-32), loops=((0, 16),))], False)
-        b.segment([p, q])
-    elif name == "stride-buckets":       # 37 locations per point: runs of points per bucket
-        b = Builder((64, 1), (8, 1), name)
-        g = b.array(GLOBAL, (1 << 16,))
-        p = b.phase([rw(g, False, aff(2048, bx=4096, l0=37), loops=((0, 64),)),
-                     rw(g, True, aff(2048, bx=4096, l0=37), loops=((0, 64),)),
-                     rw(g, False, aff(tx=1, bx=4096, l0=7), loops=((0, 64),)),
-                     rw(g, True, aff(5, tx=1, bx=4096, l0=7), loops=((0, 64),))], False)
-        b.segment([p])
-    elif name == "flat-few-threads":     # 3 threads: loop chunks spread over the lanes
-        b = Builder((3, 1), (1, 1), name)
-        g = b.array(GLOBAL, (2000,))
-        p = b.phase([rw(g, True, aff(7, l0=1), loops=((0, 40),)),
-                     rw(g, False, aff(l0=1), loops=((0, 40),)),
-                     rw(g, True, aff(tx=500, l0=1), loops=((0, 500),)),
-                     rw(g, False, aff(tx=500, l0=2), loops=((0, 500),))], False)
-        b.segment([p])
-    elif name == "pass-boundary":        # chunks straddle the first key-range pass's end (2^29)
-        b = Builder((64, 1), (2, 1), name)
-        g = b.array(GLOBAL, (1 << 30,))
-        p = b.phase([rw(g, True, aff((1 << 29) - 8, bx=1, l0=1), loops=((0, 16),)),
-                     rw(g, False, aff((1 << 29) - 8, l0=1), loops=((0, 16),)),
-                     rw(g, True, aff(3 << 28, l0=1), loops=((0, 32),)),
-                     rw(g, False, aff(3 << 28, tx=3, l0=1), loops=((0, 32),))], False)
-        b.segment([p])
-    elif name == "thread-linear":        # no loops: a lane takes 16 consecutive threads (tx alone varies)
-        b = Builder((64, 2), (4, 2), name)
-        g = b.array(GLOBAL, (4096,))
-        s = b.array(SHARED, (2, 64))
-        p = b.phase([rw(g, True, aff(tx=1, ty=64, bx=128, by=512)),
-                     rw(g, False, aff(5, tx=3, ty=192, bx=384, by=1536)),     # 3 locations per thread
-                     rw(s, True, aff(ty=1), aff(7)),                          # broadcast: one location
-                     rw(s, False, aff(ty=1), aff(63, tx=-1)),                 # descending
-                     rw(g, False, aff(tx=60, bx=1)),                          # lanes over many buckets
-                     rw(s, False, aff(1, ty=-1), aff(tx=1), guards=(aff(30, tx=-1),))], True)
-        q = b.phase([rw(s, True, aff(ty=1), aff(tx=1)), rw(g, True, aff(2048, tx=1, by=64))], False)
-        b.segment([p, q])
-    elif name == "thread-linear-oob":    # a lane's 16 threads run off the array
-        b = Builder((32, 1), (2, 1), name)
-        g = b.array(GLOBAL, (100,))
-        p = b.phase([rw(g, False, aff(40, tx=2, bx=4))], False)
-        b.segment([p])
-    elif name == "edge-out-of-bounds":   # block 1's last threads leave the array mid-chunk: fallback
-        b = Builder((64, 1), (2, 1), name)
-        g = b.array(GLOBAL, (1990,))
-        p = b.phase([rw(g, False, aff(tx=16, bx=1024, l0=1), loops=((0, 16),))], False)
-        b.segment([p])
-    else:
-        raise ValueError(name)
-    return b.build()
-
-
 @pytest.mark.parametrize("name", ["partial-chunk", "descending", "two-loops", "stride-buckets",
                                   "flat-few-threads", "pass-boundary", "thread-linear"])
 def test_linear_items(ctx, name):
-    desc = _linear_case(name)
+    desc = linear_case(name)
     k, r, o = compare(ctx, desc)
     info = k.info()
     say(f"[linear] {name}: {info.n_linear_entries} of {info.n_entries} entries linear")
@@ -272,7 +187,7 @@ def test_linear_items(ctx, name):
 
 def test_thread_linear_out_of_bounds(ctx):
     import paper_2503_08946_amd as rv
-    desc = _linear_case("thread-linear-oob")
+    desc = linear_case("thread-linear-oob")
     o = oracle.check(desc)
     assert o.status == -5
     k = ctx.load(desc)
@@ -288,7 +203,7 @@ def test_thread_linear_out_of_bounds(ctx):
 
 def test_linear_items_out_of_bounds(ctx):
     import paper_2503_08946_amd as rv
-    desc = _linear_case("edge-out-of-bounds")
+    desc = linear_case("edge-out-of-bounds")
     o = oracle.check(desc)
     assert o.status == -5
     k = ctx.load(desc)

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 from brute import brute_check
+from cases import rand_small
 from workloads import kernels as K
 from workloads import random_affine as RA
 from workloads.desc import AUX_EMOD, AUX_FLOORDIV, GLOBAL, SHARED, Aux, Builder, aff, rw
@@ -126,64 +127,11 @@ def test_brute_tiny_random(seed):
         _brute_compare(desc)
 
 
-def _rand_small(rng, i):
-    """Small random kernels exercising every description feature: 2-D blocks
-    and grids, shared and global arrays of 1-3 dims, floordiv and emod aux
-    terms, loops, the segment variable, guards, repeated segments and
-    barrier-free phases."""
-    bdx, bdy = int(rng.integers(1, 5)), int(rng.integers(1, 4))
-    gdx, gdy = int(rng.integers(1, 3)), int(rng.integers(1, 3))
-    b = Builder((bdx, bdy), (gdx, gdy), f"rand-small-{i}")
-    n_arr = int(rng.integers(1, 4))
-    for a in range(n_arr):
-        nd = int(rng.integers(1, 4))
-        dims = tuple(int(rng.integers(1, 5)) for _ in range(nd))
-        b.array(SHARED if rng.random() < 0.5 else GLOBAL, dims)
-    pids = []
-    n_ph = int(rng.integers(1, 4))
-    for p in range(n_ph):
-        acc = []
-        for _ in range(int(rng.integers(1, 4))):
-            arr = int(rng.integers(0, n_arr))
-            dims = b.arrays[arr].dims
-            nl = int(rng.integers(0, 3))
-            loops = tuple((int(lo), int(lo) + int(rng.integers(0, 3))) for lo in rng.integers(-1, 2, size=nl))
-
-            def rnd_e(use_aux):
-                terms = dict(tx=rng.integers(-2, 3), ty=rng.integers(-2, 3), bx=rng.integers(-2, 3),
-                             by=rng.integers(-2, 3), k=rng.integers(-1, 2))
-                for j in range(nl):
-                    terms[f"l{j}"] = rng.integers(-2, 3)
-                if use_aux:
-                    terms["aux0"] = rng.integers(-1, 2)
-                    terms["aux1"] = rng.integers(-1, 2)
-                return aff(int(rng.integers(-3, 4)), **{k: int(v) for k, v in terms.items()})
-
-            aux = (Aux(AUX_FLOORDIV, int(rng.integers(1, 4)), rnd_e(False)),
-                   Aux(AUX_EMOD, int(rng.integers(1, 5)), rnd_e(False)))
-            # per dim: emod into range so most kernels stay in bounds; aux vars mixed in
-            idx = []
-            for d, n in enumerate(dims):
-                if d == 0:
-                    idx.append(aff(aux1=1) if n >= 4 else aff(0))
-                else:
-                    idx.append(aff(0))
-            guards = tuple(rnd_e(True) for _ in range(int(rng.integers(0, 2))))
-            if dims[0] >= 4:
-                aux = (aux[0], Aux(AUX_EMOD, dims[0], rnd_e(False)))
-            acc.append(rw(arr, bool(rng.random() < 0.5), *idx, loops=loops, aux=aux, guards=guards))
-        pids.append(b.phase(acc, barrier_after=bool(rng.random() < 0.6)))
-    b.segment(pids[:1], repeat=int(rng.integers(1, 3)), k_base=int(rng.integers(0, 2)))
-    if len(pids) > 1:
-        b.segment(pids[1:], repeat=int(rng.integers(1, 3)))
-    return b.build()
-
-
 @pytest.mark.parametrize("seed", range(6))
 def test_brute_random_features(seed):
     rng = np.random.Generator(np.random.PCG64(1000 + seed))
     for i in range(25):
-        _brute_compare(_rand_small(rng, i))
+        _brute_compare(rand_small(rng, i))
 
 
 def test_brute_batch_like():
