@@ -174,6 +174,10 @@ typedef struct {
                                   slot: one thread's consecutive innermost-loop points, or one
                                   instance each of consecutive threads differing in tx alone
                                   (ranked per lane or per run, not per record, when they can be) */
+    uint32_t n_fast_entries;   /* entries with neither aux terms nor guards (affine indices) */
+    uint32_t n_proven_entries; /* of which every index is proven inside its dimension over the
+                                  launch and the loop box (no per-record bounds test); a fast
+                                  entry that is not proven has an out-of-bounds instance */
     uint32_t reserved;         /* 0 */
 } rv_kernel_info;
 
@@ -220,6 +224,14 @@ typedef struct rv_server rv_server;
  * NUL-terminated when cap > 0). */
 rv_status rv_validate_desc(const rv_kernel_desc *desc, char *msg, size_t cap);
 
+/* Plan a description on the host only (no device): the figures
+ * rv_kernel_get_info would report for it after rv_load_kernel_desc, with
+ * n_chunks = 0 (chunks depend on a context's workspace).  `target` is the
+ * planner's mean records per bucket (0: the default).  Returns the code
+ * rv_load_kernel_desc would return; on an error *out is untouched and msg
+ * (cap bytes, NUL-terminated when cap > 0) says why. */
+rv_status rv_plan_desc(const rv_kernel_desc *desc, int32_t target, rv_kernel_info *out, char *msg, size_t cap);
+
 /* Create a context on `device` (hipSetDevice numbering) issuing work on
  * `hip_stream` (a hipStream_t; NULL = the null stream).  `workspace` is
  * device memory of `workspace_bytes` (>= 64 MiB) holding the records of one
@@ -230,25 +242,51 @@ rv_status rv_ctx_destroy(rv_ctx *ctx);
 /* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
 const char *rv_last_error(const rv_ctx *ctx);
 
-/* Validate and plan a description, upload its tables; *out is owned by the
- * library until rv_free_kernel.  The description is deep-copied. */
+/* Load a kernel description: the paper's Domain, Read/Write relations and
+ * Schedule of one kernel (Section 2.1, steps 1-5; the component list of
+ * Section 2), given as host structures.  The description is validated,
+ * its schedule expanded into dynamic phases and barrier intervals, each
+ * interval's location space laid out, and the plan tables uploaded to the
+ * context's device (hipMalloc, synchronous copy).  The description is
+ * deep-copied: the caller may free it on return.  *out is owned by the
+ * library until rv_free_kernel.  Errors: RV_ERR_INVALID (malformed),
+ * RV_ERR_UNSUPPORTED (z > 1), RV_ERR_KEY_BITS, RV_ERR_RANGE (a value may
+ * leave int32), RV_ERR_TOO_LARGE (an interval of >= 2^32 instances, or one
+ * the context's workspace cannot hold), RV_ERR_DEVICE. */
 rv_status rv_load_kernel_desc(rv_ctx *ctx, const rv_kernel_desc *desc, rv_kernel **out);
 rv_status rv_free_kernel(rv_ctx *ctx, rv_kernel *k);
 rv_status rv_kernel_get_info(rv_ctx *ctx, const rv_kernel *k, rv_kernel_info *out);
 
-/* Run the check; blocks until the result is on the host (one stream sync).
- * A kernel with no records gives n_conflicts = 0 and has_witness = 0.
- * RV_ERR_OOB names the smallest out-of-bounds instance in rv_last_error. */
+/* The race check of one loaded kernel: every instance of every barrier
+ * interval is expanded into a record (the access relations restricted to
+ * the Domain, Section 2.1 steps 3-4), records are grouped by location and
+ * every location touched by two different threads in one interval with at
+ * least one write is counted (the unordered counterpart of the RaW, WaW
+ * and WaR relations of Section 2.1 step 6; a race in the sense of the
+ * Abstract and Section 1).  *out (host) receives the record and conflict
+ * counts and the witness of the smallest conflicting location.  Work runs
+ * on the context's stream and workspace; the call blocks until the result
+ * is on the host (one stream sync).  A kernel with no records gives
+ * n_conflicts = 0 and has_witness = 0.  Errors: RV_ERR_OOB (rv_last_error
+ * names the smallest out-of-bounds instance; *out untouched), RV_ERR_STATE
+ * (the context is serving, or k belongs to another context), RV_ERR_DEVICE. */
 rv_status rv_check(rv_ctx *ctx, rv_kernel *k, rv_result *out);
 
-/* Check n kernels together: their passes share the same launches (the
- * batched pipeline); out[i] is bit-identical to rv_check(ks[i]).  Returns
- * the first error; kernels before it have valid results. */
+/* The check of Section 2.1 step 6 (as rv_check) for n loaded kernels at
+ * once: ks[0..n) (host array of handles of this context), out[0..n) (host
+ * results).  Their intervals share the same launches; out[i] is
+ * bit-identical to rv_check(ks[i]).  Returns the first error (its message
+ * names the kernel); kernels before it have valid results. */
 rv_status rv_check_batch(rv_ctx *ctx, rv_kernel *const *ks, size_t n, rv_result *out);
 
-/* Witnesses of k with list index in [first_index, first_index + cap), in
- * location order; *n_out = number written.  Re-runs the check in collect
- * mode (the result is deterministic, so windows are consistent). */
+/* The conflicting locations themselves, each with its canonical pair of
+ * instances: the concrete elements of the paper's dependence relations
+ * (Section 2.1 step 6; the appendix listings print whole relations).
+ * Writes the witnesses with list index in [first_index, first_index + cap)
+ * to out (host, cap entries), in (interval, space, block, array, address)
+ * order; *n_out = number written.  Re-runs the check in collect mode (the
+ * result is deterministic, so windows are consistent); the window buffer on
+ * the device is kept by the context between calls.  Errors as rv_check. */
 rv_status rv_get_witnesses(rv_ctx *ctx, rv_kernel *k, uint64_t first_index, rv_witness *out,
                            size_t cap, size_t *n_out);
 

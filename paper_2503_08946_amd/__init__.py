@@ -7,7 +7,7 @@ it is missing.
 """
 
 from .rv import (EXPORTED, STAGES, STATUS, Batch, Context, JobResult, Kernel, Marshalled, Result, RVError, Server,
-                 Side, Witness, lib, selftest, validate)
+                 Side, Witness, lib, plan, selftest, validate)
 
 __all__ = ["EXPORTED", "STAGES", "STATUS", "Batch", "Context", "JobResult", "Kernel", "Marshalled", "Result", "RVError",
-           "Server", "Side", "Witness", "lib", "selftest", "validate"]
+           "Server", "Side", "Witness", "lib", "plan", "selftest", "validate"]

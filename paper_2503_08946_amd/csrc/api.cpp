@@ -8,6 +8,7 @@
 // the next is being admitted and launched.
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
@@ -32,6 +33,8 @@ struct Lane {
     size_t res_cap = 0;
     DevSub *d_subs = nullptr;
     size_t subs_cap = 0;
+    DevWitness *d_win = nullptr;    // witness windows (rv_get_witnesses), grown on demand
+    size_t win_cap = 0;
     void *h_up = nullptr;       // pinned: pass tables going up
     size_t up_cap = 0;
     void *h_down = nullptr;     // pinned: results coming down
@@ -42,6 +45,9 @@ struct Lane {
     std::vector<size_t> res0;
     size_t ns = 0;
     bool busy = false;
+    // message of the lane's last failing step; a server's worker thread owns
+    // its lanes' messages, so it never writes the context's
+    std::string err;
 
     unsigned long long *rec() const { return reinterpret_cast<unsigned long long *>(ws); }
     uint32_t *counts() const { return reinterpret_cast<uint32_t *>(ws + L.off_counts); }
@@ -71,9 +77,10 @@ struct rv_ctx {
     size_t ws_bytes = 0;
     Lane main;
     std::string err;
-    bool serving = false;           // a server owns the device work of this context
-    int target = DEFAULT_TARGET;    // planner: mean records per bucket for kernels loaded next
-    int group = RV_GROUP_FOLD;      // per-bucket grouping kernel
+    bool serving = false;           // a server owns the device work of this context (set and cleared
+                                    // while no worker thread runs)
+    std::atomic<int> target{DEFAULT_TARGET};   // planner: mean records per bucket for kernels loaded next
+    std::atomic<int> group{RV_GROUP_FOLD};     // per-bucket grouping kernel (read by a server's worker)
     // timing
     bool timing = false;
     struct Ev { int stage; hipEvent_t a, b; };
@@ -96,6 +103,25 @@ rv_status fail(rv_ctx *c, rv_status st, const std::string &m) {
             return fail((c), RV_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+// Lane-level steps report into the lane's own message.
+rv_status lfail(Lane &ln, rv_status st, const std::string &m) {
+    ln.err = m;
+    return st;
+}
+
+#define HIP_TRY_L(ln, call)                                                                    \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return lfail((ln), RV_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// The context's main lane failed: its message becomes the context's.
+rv_status main_fail(rv_ctx *c, rv_status st) {
+    if (st) c->err = c->main.err;
+    return st;
+}
+
 hipEvent_t get_event(rv_ctx *c) {
     if (!c->pool.empty()) {
         hipEvent_t e = c->pool.back();
@@ -109,7 +135,7 @@ hipEvent_t get_event(rv_ctx *c) {
 
 template <class F>
 void timed(rv_ctx *c, hipStream_t st, int stage, F &&f) {
-    if (!c->timing || c->serving) { f(); return; }
+    if (c->serving || !c->timing) { f(); return; }
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) { f(); return; }
     (void)hipEventRecord(a, st);
@@ -133,24 +159,24 @@ rv_status drain_timing(rv_ctx *c) {
 }
 
 template <class T>
-rv_status grow_device(rv_ctx *c, Lane &ln, T *&p, size_t &cap, size_t n) {
+rv_status grow_device(Lane &ln, T *&p, size_t &cap, size_t n) {
     if (n <= cap) return RV_OK;
-    HIP_TRY(c, hipStreamSynchronize(ln.stream));
-    if (p) HIP_TRY(c, hipFree(p));
+    HIP_TRY_L(ln, hipStreamSynchronize(ln.stream));
+    if (p) HIP_TRY_L(ln, hipFree(p));
     p = nullptr;
     const size_t nc = std::max<size_t>(n, 2 * cap);
-    HIP_TRY(c, hipMalloc(reinterpret_cast<void **>(&p), nc * sizeof(T)));
+    HIP_TRY_L(ln, hipMalloc(reinterpret_cast<void **>(&p), nc * sizeof(T)));
     cap = nc;
     return RV_OK;
 }
 
-rv_status grow_pinned(rv_ctx *c, Lane &ln, void *&p, size_t &cap, size_t bytes) {
+rv_status grow_pinned(Lane &ln, void *&p, size_t &cap, size_t bytes) {
     if (bytes <= cap) return RV_OK;
-    HIP_TRY(c, hipStreamSynchronize(ln.stream));
-    if (p) HIP_TRY(c, hipHostFree(p));
+    HIP_TRY_L(ln, hipStreamSynchronize(ln.stream));
+    if (p) HIP_TRY_L(ln, hipHostFree(p));
     p = nullptr;
     const size_t nc = std::max<size_t>(bytes, 2 * cap);
-    HIP_TRY(c, hipHostMalloc(&p, nc, hipHostMallocDefault));
+    HIP_TRY_L(ln, hipHostMalloc(&p, nc, hipHostMallocDefault));
     cap = nc;
     return RV_OK;
 }
@@ -158,16 +184,18 @@ rv_status grow_pinned(rv_ctx *c, Lane &ln, void *&p, size_t &cap, size_t bytes) 
 void lane_release(Lane &ln) {
     if (ln.d_res) (void)hipFree(ln.d_res);
     if (ln.d_subs) (void)hipFree(ln.d_subs);
+    if (ln.d_win) (void)hipFree(ln.d_win);
     if (ln.h_up) (void)hipHostFree(ln.h_up);
     if (ln.h_down) (void)hipHostFree(ln.h_down);
     if (ln.done) (void)hipEventDestroy(ln.done);
-    ln.d_res = nullptr; ln.d_subs = nullptr; ln.h_up = nullptr; ln.h_down = nullptr; ln.done = nullptr;
-    ln.res_cap = ln.subs_cap = ln.up_cap = ln.down_cap = 0;
+    ln.d_res = nullptr; ln.d_subs = nullptr; ln.d_win = nullptr; ln.h_up = nullptr; ln.h_down = nullptr;
+    ln.done = nullptr;
+    ln.res_cap = ln.subs_cap = ln.win_cap = ln.up_cap = ln.down_cap = 0;
 }
 
-rv_status check_launch(rv_ctx *c) {
+rv_status check_launch(Lane &ln) {
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(c, RV_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return lfail(ln, RV_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     return RV_OK;
 }
 
@@ -187,7 +215,8 @@ void run_group(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t 
     if (c->group == RV_GROUP_SORT_SCAN)
         launch_bucket(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 0, c->ncu, ln.stream);
     else
-        launch_fold(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), ln.hot(), c->ncu, ln.stream);
+        launch_fold(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), ln.hot(), ln.d_res, c->ncu,
+                    ln.stream);
 }
 
 void run_check_chunk(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
@@ -215,6 +244,10 @@ rv_status assemble(const rv_kernel &k, const SubResult *hr, rv_result *out, std:
     memset(&r, 0, sizeof r);
     unsigned long long oob = ~0ull;
     for (size_t i = 0; i < k.subs.size(); i++) {
+        if (hr[i].pad) {
+            msg = "internal: the hot-bucket lists of the grouping stage overflowed their capacity";
+            return RV_ERR_DEVICE;
+        }
         r.n_records += hr[i].records;
         r.n_conflicts += hr[i].conflicts;
         oob = std::min(oob, hr[i].oob);
@@ -257,9 +290,9 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
     for (size_t j = 0; j < n; j++) ln.res0[j + 1] = ln.res0[j] + ks[j]->subs.size();
     const size_t ns = ln.res0[n];
     ln.ns = ns;
-    rv_status st = grow_device(c, ln, ln.d_res, ln.res_cap, std::max<size_t>(ns, 1));
+    rv_status st = grow_device(ln, ln.d_res, ln.res_cap, std::max<size_t>(ns, 1));
     if (st) return st;
-    st = grow_pinned(c, ln, ln.h_down, ln.down_cap, std::max<size_t>(ns, 1) * sizeof(SubResult));
+    st = grow_pinned(ln, ln.h_down, ln.down_cap, std::max<size_t>(ns, 1) * sizeof(SubResult));
     if (st) return st;
     hipStream_t s = ln.stream;
     // A single kernel planned for this workspace uses its resident pass table.
@@ -302,31 +335,31 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
             }
         }
         if (cur.sub_end > cur.sub_begin) chunks.push_back(cur);
-        st = grow_device(c, ln, ln.d_subs, ln.subs_cap, std::max<size_t>(table.size(), 1));
+        st = grow_device(ln, ln.d_subs, ln.subs_cap, std::max<size_t>(table.size(), 1));
         if (st) return st;
-        st = grow_pinned(c, ln, ln.h_up, ln.up_cap, std::max<size_t>(table.size(), 1) * sizeof(DevSub));
+        st = grow_pinned(ln, ln.h_up, ln.up_cap, std::max<size_t>(table.size(), 1) * sizeof(DevSub));
         if (st) return st;
         if (!table.empty()) {
             memcpy(ln.h_up, table.data(), table.size() * sizeof(DevSub));
-            HIP_TRY(c, hipMemcpyAsync(ln.d_subs, ln.h_up, table.size() * sizeof(DevSub), hipMemcpyHostToDevice, s));
+            HIP_TRY_L(ln, hipMemcpyAsync(ln.d_subs, ln.h_up, table.size() * sizeof(DevSub), hipMemcpyHostToDevice, s));
         }
         for (auto &ch : chunks)
             run_check_chunk(c, ln, ln.d_subs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items,
                             ch.buckets);
     }
-    if ((st = check_launch(c))) return st;
-    if (ns) HIP_TRY(c, hipMemcpyAsync(ln.h_down, ln.d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, s));
-    if (!ln.done) HIP_TRY(c, hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
-    HIP_TRY(c, hipEventRecord(ln.done, s));
+    if ((st = check_launch(ln))) return st;
+    if (ns) HIP_TRY_L(ln, hipMemcpyAsync(ln.h_down, ln.d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, s));
+    if (!ln.done) HIP_TRY_L(ln, hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
+    HIP_TRY_L(ln, hipEventRecord(ln.done, s));
     ln.busy = true;
     return RV_OK;
 }
 
 // Wait for the lane's batch and assemble per-kernel results.  status[j]
 // (optional) receives each kernel's code; the return value is the first
-// error (with its message in c->err).
-rv_status lane_collect(rv_ctx *c, Lane &ln, rv_result *out, rv_status *status, std::string *msgs = nullptr) {
-    HIP_TRY(c, hipEventSynchronize(ln.done));
+// error (with its message in ln.err).
+rv_status lane_collect(Lane &ln, rv_result *out, rv_status *status, std::string *msgs = nullptr) {
+    HIP_TRY_L(ln, hipEventSynchronize(ln.done));
     ln.busy = false;
     const SubResult *hr = reinterpret_cast<const SubResult *>(ln.h_down);
     rv_status first = RV_OK;
@@ -337,7 +370,7 @@ rv_status lane_collect(rv_ctx *c, Lane &ln, rv_result *out, rv_status *status, s
         if (msgs) msgs[j] = m;
         if (st && first == RV_OK) {
             first = st;
-            c->err = ln.jobs.size() > 1 ? "kernel " + std::to_string(j) + ": " + m : m;
+            ln.err = ln.jobs.size() > 1 ? "kernel " + std::to_string(j) + ": " + m : m;
         }
     }
     return first;
@@ -382,9 +415,10 @@ void server_loop(rv_server *s) {
             const size_t n = ln.jobs.size();
             std::vector<rv_result> res(n);
             std::vector<rv_status> st(n);
-            lane_collect(c, ln, res.data(), st.data());
+            const rv_status first = lane_collect(ln, res.data(), st.data());
             const uint64_t t = now_ns();
             lk.lock();
+            if (first) s->err = ln.err;
             for (size_t j = 0; j < n; j++) {
                 rv_job_result r;
                 memset(&r, 0, sizeof r);
@@ -432,6 +466,7 @@ void server_loop(rv_server *s) {
             rv_status st = lane_enqueue(c, ln, ks.data(), ks.size());
             lk.lock();
             if (st) {   // device error: fail the batch
+                s->err = ln.err;
                 const uint64_t t = now_ns();
                 for (size_t j = 0; j < ks.size(); j++) {
                     rv_job_result r;
@@ -576,6 +611,23 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     return RV_OK;
 }
 
+void fill_info(const rv_kernel &k, rv_kernel_info *out) {
+    memset(out, 0, sizeof *out);
+    out->n_instances = k.n_instances;
+    out->n_intervals = k.n_intervals;
+    out->n_subintervals = (uint32_t)k.subs.size();
+    out->n_chunks = (uint32_t)k.chunks.size();
+    out->n_buckets = (uint32_t)k.n_buckets;
+    out->max_interval_instances = k.max_interval_instances;
+    out->n_entries = (uint32_t)k.entries.size();
+    for (const auto &e : k.entries) {
+        out->n_flat_entries += e.flat;
+        out->n_linear_entries += e.lin + e.tlin;
+        out->n_fast_entries += e.fast != 0;
+        out->n_proven_entries += e.fast == 2;
+    }
+}
+
 void free_kernel(rv_kernel *k) {
     if (k->d_mem) (void)hipFree(k->d_mem);
     delete k;
@@ -594,26 +646,38 @@ rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel *
 rv_status rv_free_kernel(rv_ctx *c, rv_kernel *k) {
     if (!c || !k) return RV_ERR_INVALID;
     (void)hipSetDevice(c->device);
-    (void)hipDeviceSynchronize();
+    // the context's own work on k has finished when its calls returned;
+    // wait for anything still queued on its stream (server jobs must have
+    // been polled before their kernels are freed)
+    (void)hipStreamSynchronize(c->main.stream);
     free_kernel(k);
     return RV_OK;
 }
 
 rv_status rv_kernel_get_info(rv_ctx *c, const rv_kernel *k, rv_kernel_info *out) {
     if (!c || !k || !out) return RV_ERR_INVALID;
-    out->n_instances = k->n_instances;
-    out->n_intervals = k->n_intervals;
-    out->n_subintervals = (uint32_t)k->subs.size();
-    out->n_chunks = (uint32_t)k->chunks.size();
-    out->n_buckets = (uint32_t)k->n_buckets;
-    out->max_interval_instances = k->max_interval_instances;
-    out->n_entries = (uint32_t)k->entries.size();
-    uint32_t nf = 0, nl = 0;
-    for (const auto &e : k->entries) { nf += e.flat; nl += e.lin + e.tlin; }
-    out->n_flat_entries = nf;
-    out->n_linear_entries = nl;
-    out->reserved = 0;
+    fill_info(*k, out);
     return RV_OK;
+}
+
+rv_status rv_plan_desc(const rv_kernel_desc *desc, int32_t target, rv_kernel_info *out, char *msg, size_t cap) {
+    std::string m;
+    rv_status st;
+    rv_kernel_info info;
+    try {
+        rv_kernel k;
+        st = plan_kernel(desc, target > 0 ? target : DEFAULT_TARGET, k, m);
+        if (!st) fill_info(k, &info);
+    } catch (const std::bad_alloc &) {
+        st = RV_ERR_TOO_LARGE;
+        m = "out of host memory";
+    }
+    if (!st && out) *out = info;
+    if (msg && cap) {
+        strncpy(msg, st ? m.c_str() : "", cap - 1);
+        msg[cap - 1] = 0;
+    }
+    return st;
 }
 
 rv_status rv_check(rv_ctx *c, rv_kernel *k, rv_result *out) {
@@ -623,11 +687,11 @@ rv_status rv_check(rv_ctx *c, rv_kernel *k, rv_result *out) {
     c->err.clear();
     HIP_TRY(c, hipSetDevice(c->device));
     rv_status st = lane_enqueue(c, c->main, &k, 1);
-    if (st) return st;
+    if (st) return main_fail(c, st);
     rv_result r;
-    st = lane_collect(c, c->main, &r, nullptr);
+    st = lane_collect(c->main, &r, nullptr);
     if (!st) *out = r;
-    return st;
+    return main_fail(c, st);
 }
 
 rv_status rv_check_batch(rv_ctx *c, rv_kernel *const *ks, size_t n, rv_result *out) {
@@ -641,8 +705,8 @@ rv_status rv_check_batch(rv_ctx *c, rv_kernel *const *ks, size_t n, rv_result *o
         if (ks[j]->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
     }
     rv_status st = lane_enqueue(c, c->main, ks, n);
-    if (st) return st;
-    return lane_collect(c, c->main, out, nullptr);
+    if (st) return main_fail(c, st);
+    return main_fail(c, lane_collect(c->main, out, nullptr));
 }
 
 rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_witness *out, size_t cap,
@@ -655,18 +719,20 @@ rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_wit
     HIP_TRY(c, hipSetDevice(c->device));
     Lane &ln = c->main;
     const size_t ns = k->subs.size();
-    rv_status st = grow_device(c, ln, ln.d_res, ln.res_cap, std::max<size_t>(ns, 1));
-    if (st) return st;
-    st = grow_pinned(c, ln, ln.h_down, ln.down_cap, std::max<size_t>(ns, 1) * sizeof(SubResult));
-    if (st) return st;
-    DevWitness *d_win = nullptr;
-    if (cap) HIP_TRY(c, hipMalloc(&d_win, cap * sizeof(DevWitness)));
+    rv_status st = grow_device(ln, ln.d_res, ln.res_cap, std::max<size_t>(ns, 1));
+    if (st) return main_fail(c, st);
+    st = grow_pinned(ln, ln.h_down, ln.down_cap, std::max<size_t>(ns, 1) * sizeof(SubResult));
+    if (st) return main_fail(c, st);
+    if (cap) {
+        st = grow_device(ln, ln.d_win, ln.win_cap, cap);
+        if (st) return main_fail(c, st);
+    }
+    DevWitness *d_win = ln.d_win;
     const unsigned long long lo = first_index, hi = first_index + cap;
     unsigned long long base = 0;
     hipStream_t s = ln.stream;
     launch_init_results(ln.d_res, ns, s);
     auto bail = [&](const std::string &m) {
-        if (d_win) (void)hipFree(d_win);
         return fail(c, RV_ERR_DEVICE, m);
     };
     for (auto &ch : k->chunks) {
@@ -687,14 +753,14 @@ rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_wit
                           s);
         base += total;
     }
-    if ((st = check_launch(c))) { if (d_win) (void)hipFree(d_win); return st; }
+    if ((st = check_launch(ln))) return main_fail(c, st);
     hipError_t e = hipMemcpyAsync(ln.h_down, ln.d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(std::string("witness collect: ") + hipGetErrorString(e));
     rv_result tmp;
     std::string m;
     st = assemble(*k, reinterpret_cast<const SubResult *>(ln.h_down), &tmp, m);
-    if (st) { if (d_win) (void)hipFree(d_win); return fail(c, st, m); }
+    if (st) return fail(c, st, m);
     const size_t got = base > lo ? (size_t)std::min<unsigned long long>(cap, base - lo) : 0;
     if (got) {
         std::vector<DevWitness> hw(got);
@@ -702,7 +768,6 @@ rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_wit
         if (e != hipSuccess) return bail(std::string("witness copy: ") + hipGetErrorString(e));
         for (size_t i = 0; i < got; i++) decode_witness(*k, k->subs[hw[i].sub].interval, hw[i].w, out[i]);
     }
-    if (d_win) (void)hipFree(d_win);
     *n_out = got;
     return RV_OK;
 }
@@ -728,15 +793,15 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
     const IntervalPlan &I = k->intervals[interval];
     if ((se - sb) * I.P > ln.L.cap_records || buckets > ln.L.cap_buckets)
         return fail(c, RV_ERR_TOO_LARGE, "interval does not fit the workspace");
-    rv_status st = grow_device(c, ln, ln.d_res, ln.res_cap, se - sb);
-    if (st) return st;
-    st = grow_device(c, ln, ln.d_subs, ln.subs_cap, table.size());
-    if (st) return st;
+    rv_status st = grow_device(ln, ln.d_res, ln.res_cap, se - sb);
+    if (st) return main_fail(c, st);
+    st = grow_device(ln, ln.d_subs, ln.subs_cap, table.size());
+    if (st) return main_fail(c, st);
     hipStream_t s = ln.stream;
     HIP_TRY(c, hipMemcpy(ln.d_subs, table.data(), table.size() * sizeof(DevSub), hipMemcpyHostToDevice));
     launch_init_results(ln.d_res, se - sb, s);
     run_expand(c, ln, ln.d_subs, se - sb, items, buckets);
-    if ((st = check_launch(c))) return st;
+    if ((st = check_launch(ln))) return main_fail(c, st);
     std::vector<uint32_t> cnt(buckets);
     HIP_TRY(c, hipMemcpyAsync(cnt.data(), ln.counts(), buckets * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -747,7 +812,7 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
     }
     if (sorted) {
         launch_bucket(ln.d_subs, se - sb, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 1, c->ncu, s);
-        if ((st = check_launch(c))) return st;
+        if ((st = check_launch(ln))) return main_fail(c, st);
     }
     std::vector<unsigned long long> recs(total);
     if (total) HIP_TRY(c, hipMemcpyAsync(recs.data(), ln.rec(), total * 8, hipMemcpyDeviceToHost, s));
@@ -808,9 +873,9 @@ rv_status rv_server_create(rv_ctx *c, void *workspace, size_t budget_bytes, uint
         // nothing
         constexpr size_t kPasses = 1u << 16;
         if (e == hipSuccess && ln.L.cap_records &&
-            (grow_device(c, ln, ln.d_res, ln.res_cap, kPasses) || grow_device(c, ln, ln.d_subs, ln.subs_cap, kPasses) ||
-             grow_pinned(c, ln, ln.h_up, ln.up_cap, kPasses * sizeof(DevSub)) ||
-             grow_pinned(c, ln, ln.h_down, ln.down_cap, kPasses * sizeof(SubResult))))
+            (grow_device(ln, ln.d_res, ln.res_cap, kPasses) || grow_device(ln, ln.d_subs, ln.subs_cap, kPasses) ||
+             grow_pinned(ln, ln.h_up, ln.up_cap, kPasses * sizeof(DevSub)) ||
+             grow_pinned(ln, ln.h_down, ln.down_cap, kPasses * sizeof(SubResult))))
             e = hipErrorOutOfMemory;
         if (e != hipSuccess || !ln.L.cap_records) {
             for (int q = 0; q <= l; q++) lane_release(s->lanes[q]);
@@ -936,8 +1001,8 @@ rv_status rv_autotune(rv_ctx *c, const rv_kernel_desc *descs, size_t n, int32_t 
             std::vector<double> ms;
             for (int r = 0; r <= trials && !st; r++) {    // run 0 warms up
                 const uint64_t t0 = now_ns();
-                st = lane_enqueue(c, c->main, ks.data(), ks.size());
-                if (!st) st = lane_collect(c, c->main, res.data(), nullptr);
+                st = main_fail(c, lane_enqueue(c, c->main, ks.data(), ks.size()));
+                if (!st) st = main_fail(c, lane_collect(c->main, res.data(), nullptr));
                 if (!st && r) ms.push_back((double)(now_ns() - t0) * 1e-6);
             }
             if (st) break;

@@ -330,7 +330,7 @@ __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, 
 }
 
 // Fast path of expand_item for entries without aux terms or guards: the
-// per-thread index bases use 24-bit multiplies, the loop terms advance by
+// per-thread index bases are exact modulo 2^32, the loop terms advance by
 // precomputed steps (wave-uniform on the scalar unit unless FLAT), and the
 // location is one add per record from the flattened row (exact modulo 2^32
 // for in-bounds records).  PROVEN: the plan showed every index of the entry
@@ -390,9 +390,13 @@ __device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t 
             const int32_t tx = (int32_t)(tid - tyy * bdx), ty = (int32_t)tyy;
             const int32_t bx = (int32_t)(blk - byy * gdx), by = (int32_t)byy;
             if constexpr (!PROVEN) {
+                // full 32-bit products: thread and block ids reach 2^31 - 1,
+                // and the plan proved every index value fits int32, so the
+                // sums modulo 2^32 are the exact indices
                 auto bse = [&](int r) {
-                    return (uint32_t)(__mul24(E.row[r][C_TX], tx) + __mul24(E.row[r][C_TY], ty) +
-                                      __mul24(E.row[r][C_BX], bx) + __mul24(E.row[r][C_BY], by) + E.row[r][C_C0]);
+                    return (uint32_t)E.row[r][C_TX] * (uint32_t)tx + (uint32_t)E.row[r][C_TY] * (uint32_t)ty +
+                           (uint32_t)E.row[r][C_BX] * (uint32_t)bx + (uint32_t)E.row[r][C_BY] * (uint32_t)by +
+                           (uint32_t)E.row[r][C_C0];
                 };
                 base0 = bse(0);
                 base1 = bse(1);
@@ -1733,7 +1737,7 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
                                                  unsigned long long *__restrict__ rec,
                                                  const uint32_t *__restrict__ starts,
                                                  const uint32_t *__restrict__ counts, uint32_t *__restrict__ conf,
-                                                 HotArea hot) {
+                                                 HotArea hot, SubResult *__restrict__ res) {
     __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
     __shared__ uint32_t h_pre[BKT_WG + 1], h_b[BKT_WG], h_cnt[BKT_WG];
     __shared__ uint32_t red[BKT_WG / 64];
@@ -1741,6 +1745,11 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
     CSub *subs = cptr(subs_g);
     const uint32_t t = threadIdx.x;
     const uint32_t nh = min(*hot.n, hot.cap);
+    if (blockIdx.x == 0 && (*hot.n > hot.cap || *hot.mid_n > hot.mid_cap)) {
+        // a list dropped buckets (the workspace layout sizes them so that
+        // this cannot happen): every pass of the chunk reports the failure
+        for (uint32_t j = t; j < nsub; j += BKT_WG) res[subs[j].res].pad = 1u;
+    }
     uint32_t u = 0;      // parts of the list before this group of entries
     for (uint32_t base = 0; base < nh; base += BKT_WG) {
         // the group's entries and the prefix of their part counts
@@ -1940,8 +1949,8 @@ void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigne
 }
 
 void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
-                 const uint32_t *starts, const uint32_t *counts, uint32_t *conf, HotArea hot, unsigned ncu,
-                 hipStream_t st) {
+                 const uint32_t *starts, const uint32_t *counts, uint32_t *conf, HotArea hot, SubResult *res,
+                 unsigned ncu, hipStream_t st) {
     if (!nbuckets) return;
     static const unsigned occ = occupancy(k_fold<FOLD_GROUP>, BKT_WG, 4);
     static const unsigned occ_hot = occupancy(k_hot, BKT_WG, 4);
@@ -1956,7 +1965,8 @@ void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned 
         hipLaunchKernelGGL(k_fold<0>, dim3(G), dim3(BKT_WG), 0, st, subs, nsub, (uint32_t)nbuckets, rec, starts,
                            counts, conf, hot);
     hipLaunchKernelGGL(k_mid, dim3(ncu * occ_mid), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
-    hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
+    hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot,
+                       res);
 }
 
 void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf, SubResult *res,

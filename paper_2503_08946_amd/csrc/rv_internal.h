@@ -93,10 +93,11 @@ struct DevEntry {
     uint32_t flat;
     uint32_t nq;               // flat: thread groups x loop chunks
     Magic mg_nl, mg_e1, mg_e2; // divisions by n_lchunks, ext[1], ext[2]
-    // Fast path (no aux terms, no guards, |tx..by coefficients| < 2^23): the
-    // location as one affine row modulo 2^32, loc = fr . (tx,ty,bx,by,l0,l1,l2) +
-    // fr[C_C0] + block * loc_mul; exact for every in-bounds record.  2: fast
-    // and every index of the entry is proven inside its dimension.
+    // Fast path (no aux terms, no guards): the location as one affine row
+    // modulo 2^32, loc = fr . (tx,ty,bx,by,l0,l1,l2) + fr[C_C0] + block *
+    // loc_mul; exact for every in-bounds record.  2: fast and every index of
+    // the entry is proven inside its dimension (the exact range of an affine
+    // form over the box; an entry that stays 1 has an out-of-bounds instance).
     uint32_t fast;
     uint32_t ndim;
     uint32_t fr[NC];
@@ -142,7 +143,7 @@ struct SubResult {
     unsigned long long conflicts;
     unsigned long long oob;        // (interval << 32) | instance id; ~0 when none
     uint32_t first_bucket;         // chunk-relative; ~0 when none
-    uint32_t pad;
+    uint32_t pad;                  // nonzero: an internal capacity was exceeded (the result is void)
     uint32_t w[4];                 // location, first id, second id, second is_write
 };
 static_assert(sizeof(SubResult) == 48, "SubResult layout");
@@ -277,8 +278,8 @@ struct HotArea {
     uint32_t mid_cap;
 };
 void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
-                 const uint32_t *starts, const uint32_t *counts, uint32_t *conf, HotArea hot, unsigned ncu,
-                 hipStream_t st);
+                 const uint32_t *starts, const uint32_t *counts, uint32_t *conf, HotArea hot, SubResult *res,
+                 unsigned ncu, hipStream_t st);
 void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf,
                    SubResult *res, hipStream_t st);
 void launch_first(const DevSub *subs, uint32_t nsub, const unsigned long long *rec,

@@ -101,7 +101,8 @@ class rv_timing(ctypes.Structure):
 class rv_kernel_info(ctypes.Structure):
     _fields_ = [("n_instances", u64), ("n_intervals", u32), ("n_subintervals", u32),
                 ("n_chunks", u32), ("n_buckets", u32), ("max_interval_instances", u64),
-                ("n_entries", u32), ("n_flat_entries", u32), ("n_linear_entries", u32), ("reserved", u32)]
+                ("n_entries", u32), ("n_flat_entries", u32), ("n_linear_entries", u32),
+                ("n_fast_entries", u32), ("n_proven_entries", u32), ("reserved", u32)]
 
 
 class rv_record(ctypes.Structure):
@@ -141,6 +142,7 @@ def lib():
         P, V, S = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t
         sig = {
             "rv_validate_desc": [P(rv_kernel_desc), ctypes.c_char_p, S],
+            "rv_plan_desc": [P(rv_kernel_desc), i32, P(rv_kernel_info), ctypes.c_char_p, S],
             "rv_ctx_create": [P(V), ctypes.c_int, V, V, S],
             "rv_ctx_destroy": [V],
             "rv_load_kernel_desc": [V, P(rv_kernel_desc), P(V)],
@@ -173,7 +175,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("rv_validate_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_error", "rv_load_kernel_desc",
+EXPORTED = ("rv_validate_desc", "rv_plan_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_error", "rv_load_kernel_desc",
             "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_get_witnesses",
             "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest", "rv_ctx_get_tuning",
             "rv_ctx_set_tuning", "rv_autotune", "rv_server_create",
@@ -300,6 +302,18 @@ def validate(desc) -> tuple:
     buf = ctypes.create_string_buffer(512)
     st = lib().rv_validate_desc(ctypes.byref(m.desc), buf, 512)
     return st, buf.value.decode()
+
+
+def plan(desc, target: int = 0) -> rv_kernel_info:
+    """Host-only planning (no device): the kernel's plan figures.  Raises
+    RVError with the planner's code and message for a rejected description."""
+    m = Marshalled(desc)
+    buf = ctypes.create_string_buffer(512)
+    out = rv_kernel_info()
+    st = lib().rv_plan_desc(ctypes.byref(m.desc), int(target), ctypes.byref(out), buf, 512)
+    if st:
+        raise RVError(st, buf.value.decode())
+    return out
 
 
 def selftest() -> tuple:

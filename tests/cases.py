@@ -61,6 +61,80 @@ def rand_small(rng, i):
         b.segment(pids[1:], repeat=int(rng.integers(1, 3)))
     return b.build()
 
+def rand_medium(rng, i, oob_rate=0.01):
+    """Random kernels of a few thousand to a few hundred thousand records,
+    spanning several expansion tiles and location buckets: 2-D launches up
+    to (48, 4) x (5, 3), 1-4 shared or global arrays of 1-3 dims, 0-2 loops
+    of up to 16 points, repeated segments (the segment variable k), guards,
+    floor-division and Euclidean-remainder terms, and plain affine indices
+    (the expansion's fast paths).  A plain affine index is placed inside
+    its dimension over the whole launch and loop box; with probability
+    ``oob_rate`` it is shifted out of it, so the kernel reports its first
+    out-of-bounds instance."""
+    bdx, bdy = int(rng.integers(1, 49)), int(rng.integers(1, 5))
+    gdx, gdy = int(rng.integers(1, 6)), int(rng.integers(1, 4))
+    b = Builder((bdx, bdy), (gdx, gdy), f"rand-medium-{i}")
+    n_arr = int(rng.integers(1, 5))
+    for a in range(n_arr):
+        nd = int(rng.integers(1, 4))
+        dims = tuple(int(rng.integers(4, 65)) for _ in range(nd))
+        b.array(SHARED if rng.random() < 0.5 else GLOBAL, dims)
+    n_ph = int(rng.integers(1, 5))
+    reps = int(rng.integers(1, 4))
+    vmax = dict(tx=bdx - 1, ty=bdy - 1, bx=gdx - 1, by=gdy - 1, k=reps - 1)
+    pids = []
+    for p in range(n_ph):
+        acc = []
+        for _ in range(int(rng.integers(1, 6))):
+            arr = int(rng.integers(0, n_arr))
+            dims = b.arrays[arr].dims
+            nl = int(rng.integers(0, 3))
+            trips = [int(rng.integers(1, 17)) for _ in range(nl)]
+            loops = tuple((0, t) for t in trips)
+            ranges = dict(vmax, **{f"l{j}": trips[j] - 1 for j in range(nl)})
+            names = list(ranges)
+            aux = [Aux(), Aux()]
+            free_aux = [0, 1]
+            idx = []
+            for n in dims:
+                kind = rng.random()
+                if kind < 0.55:
+                    # plain affine: coefficients in [-2, 2]; exact range over the box
+                    terms = {v: int(rng.integers(-2, 3)) for v in names if rng.random() < 0.5}
+                    lo = sum(min(0, c * ranges[v]) for v, c in terms.items())
+                    hi = sum(max(0, c * ranges[v]) for v, c in terms.items())
+                    if hi - lo < n:
+                        c0 = -lo + int(rng.integers(0, n - (hi - lo)))
+                        if rng.random() < oob_rate:
+                            c0 += n - (hi - lo) if rng.random() < 0.5 else -(hi - lo) - 1
+                        idx.append(aff(c0, **terms))
+                        continue
+                if free_aux:
+                    x = free_aux.pop(0)
+                    terms = {v: int(rng.integers(-3, 4)) for v in names}
+                    e = aff(int(rng.integers(-8, 9)), **terms)
+                    if rng.random() < 0.3:
+                        # floor division of a non-negative numerator, kept in range
+                        d = int(rng.integers(1, 5))
+                        span = sum(abs(c) * ranges[v] for v, c in terms.items())
+                        e = aff(span + 8, **terms)
+                        aux[x] = Aux(AUX_FLOORDIV, d, e)
+                        idx.append(aff(aux0=1) if x == 0 else aff(aux1=1))
+                        if (2 * span + 16) // d >= n:
+                            aux[x] = Aux(AUX_EMOD, n, e)
+                    else:
+                        aux[x] = Aux(AUX_EMOD, n, e)
+                        idx.append(aff(aux0=1) if x == 0 else aff(aux1=1))
+                else:
+                    idx.append(aff(int(rng.integers(0, n))))
+            guards = []
+            for _ in range(int(rng.integers(0, 3)) if rng.random() < 0.35 else 0):
+                terms = {v: int(rng.integers(-2, 3)) for v in names if rng.random() < 0.5}
+                guards.append(aff(int(rng.integers(-2, 2 * max(1, bdx))), **terms))
+            acc.append(rw(arr, bool(rng.random() < 0.5), *idx, loops=loops, aux=tuple(aux), guards=tuple(guards)))
+        pids.append(b.phase(acc, barrier_after=bool(rng.random() < 0.6)))
+    b.segment(pids, repeat=reps)
+    return b.build()
 
 
 def linear_case(name):
@@ -146,4 +220,18 @@ def linear_case(name):
         b.segment([p])
     else:
         raise ValueError(name)
+    return b.build()
+
+
+def large_grid(offset, dim, write_offset=None):
+    """One-thread blocks beyond 2^23 (block ids no longer fit 24 bits):
+    every block reads g[bx + offset] of g[dim]; with ``write_offset`` it also
+    writes g[bx + write_offset]."""
+    b = Builder((1, 1), ((1 << 23) + 64, 1), f"large-grid-{offset}")
+    g = b.array(GLOBAL, (dim,))
+    acc = [rw(g, False, aff(offset, bx=1))]
+    if write_offset is not None:
+        acc.append(rw(g, True, aff(write_offset, bx=1)))
+    p = b.phase(acc, False)
+    b.segment([p])
     return b.build()

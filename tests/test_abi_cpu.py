@@ -11,6 +11,7 @@ import pytest
 import paper_2503_08946_amd as rv
 from workloads import kernels as K
 from workloads import random_affine as RA
+from cases import large_grid
 from workloads.desc import AUX_EMOD, AUX_FLOORDIV, GLOBAL, SHARED, Aux, Builder, aff, rw
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -100,3 +101,26 @@ def test_context_needs_gpu_or_fails_loudly():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         rv.Context(0, 64 << 20)
+
+
+def test_plan_flags_large_grid():
+    # in bounds: the index bx + 2^23 - 64 stays below 2^24 over the whole grid,
+    # so the entry is proven (no per-record bounds test)
+    ok = rv.plan(large_grid((1 << 23) - 64, 1 << 24))
+    assert (ok.n_entries, ok.n_fast_entries, ok.n_proven_entries) == (1, 1, 1)
+    # out of bounds from block 2^23 on: the entry stays on the fast path with
+    # a per-record bounds test, whose index arithmetic must be exact for
+    # block ids up to 2^23 + 63 (a 24-bit product would wrap 2^23 to -2^23)
+    bad = rv.plan(large_grid(1 << 23, 1 << 24))
+    assert (bad.n_entries, bad.n_fast_entries, bad.n_proven_entries) == (1, 1, 0)
+    assert bad.n_instances == (1 << 23) + 64
+
+
+def test_plan_matches_validate_errors():
+    big = _one(rw(0, False, aff(0), loops=((0, 1 << 16), (0, 1 << 10))), block=(32, 32), grid=(4, 1))
+    with pytest.raises(rv.RVError) as e:
+        rv.plan(big)
+    assert e.value.status == rv.validate(big)[0] == -6
+    info = rv.plan(K.tiled_matmul(grid=16, k_iters=64, drop_dynamic=64))
+    assert info.n_instances == 1_141_112_832 and info.n_intervals == 128
+    assert info.n_chunks == 0 and info.n_fast_entries == info.n_proven_entries == info.n_entries

@@ -72,3 +72,32 @@ def test_matmul_grid64_multi_chunk(big_ctx):
     assert r.n_conflicts == 64 * 64 * CONFLICTS_PER_BLOCK
     # the smallest conflicting location is block 0's first shared element
     assert r.witness.block == 0 and r.witness.address == 0
+
+
+@pytest.mark.parametrize("drop", [-1] + K.matmul_mutants(seed=3))
+def test_matmul_grid16_mutants(big_ctx, drop):
+    # the unmutated kernel, the fixed dropped barriers {0, 1, 64, 126, 127}
+    # and three drawn from seed 3: counts against the closed forms (a dropped
+    # barrier d < 127 merges two phases of one K-iteration, or a compute phase
+    # with the next load: every As/Bs element of every block conflicts; d = 127
+    # merges the last compute phase with the C write: no conflict), and the
+    # witnesses against the oracle's list for the merged interval
+    desc = K.tiled_matmul(grid=16, k_iters=64, drop_dynamic=drop)
+    k = big_ctx.load(desc)
+    say(f"[full] grid 16 drop {drop}")
+    r = big_ctx.check(k)
+    assert r.n_records == GRID16_RECORDS
+    expect = 16 * 16 * CONFLICTS_PER_BLOCK if 0 <= drop < 127 else 0
+    assert r.n_conflicts == expect
+    if not expect:
+        assert r.witness is None
+        k.free()
+        return
+    assert r.witness.interval == drop
+    o = oracle.check(desc, max_witnesses=1 << 20, ilo=drop, ihi=drop + 1)
+    assert o.n_conflicts == expect
+    assert _wkey(r.witness) == _wkey(o.witnesses[0])
+    for first, count in ((0, 4096), (expect // 2, 512), (expect - 512, 512)):
+        got = big_ctx.witnesses(k, first, count)
+        assert [_wkey(w) for w in got] == [_wkey(w) for w in o.witnesses[first:first + count]]
+    k.free()

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from cases import linear_case
+from cases import large_grid, linear_case
 from workloads import kernels as K
 from workloads import random_affine as RA
 from workloads.desc import AUX_EMOD, AUX_FLOORDIV, GLOBAL, SHARED, Aux, Builder, aff, rw
@@ -220,6 +220,33 @@ def test_linear_items_out_of_bounds(ctx):
 
 
 # ------------------------------------------------------------- edge cases
+def test_large_grid_out_of_bounds(ctx):
+    # block ids reach 2^23 + 63: g[bx + 2^23] leaves g[2^24] from block 2^23
+    # on; the fast path's index arithmetic must see that (a 24-bit product
+    # wraps block 2^23 to -2^23 and reads index 0)
+    import paper_2503_08946_amd as rv
+    desc = large_grid(1 << 23, 1 << 24)
+    o = oracle.check(desc, max_witnesses=1)
+    assert o.status == -5 and o.oob == (0, 1 << 23, 0, 0, 0)
+    k = ctx.load(desc)
+    assert (k.info().n_fast_entries, k.info().n_proven_entries) == (1, 0)
+    with pytest.raises(rv.RVError) as e:
+        ctx.check(k)
+    assert e.value.status == -5
+    say(f"[large-grid] {e.value.message}")
+    assert f"interval 0, block {1 << 23}, thread 0, dynamic phase 0, access 0" in e.value.message
+
+
+def test_large_grid_in_bounds(ctx):
+    # the same launch in bounds, with writes: block x writes g[x + 2^23 - 64]
+    # and block x + 1 reads it, so every location but the ends conflicts
+    desc = large_grid((1 << 23) - 63, (1 << 24) + 1, write_offset=(1 << 23) - 64)
+    k, r, o = compare(ctx, desc, max_list=1 << 12)
+    assert r.n_records == 2 * ((1 << 23) + 64)
+    assert r.n_conflicts == (1 << 23) + 63
+
+
+
 def test_empty_kernel(ctx):
     b = Builder((4, 1), (1, 1), "empty")
     b.array(SHARED, (4,))

@@ -1,15 +1,20 @@
-"""Served check: each job's result in the mix equals its result alone.
+"""Served check: each job's result in the mix equals its result alone, and
+both equal the oracle's.
 
 A server over a small budget receives a seeded mix of kernels (random affine
-jobs of the served workload's shape, the pin kernels, a kernel whose index
-leaves its array and an empty kernel) and every polled result is compared
-with rv_check of the same kernel on a plain context, field by field."""
+jobs of the served workload's shape, one of about 1e7 records -- the top of
+the served size range -- the pin kernels, a kernel whose index leaves its
+array and an empty kernel) and every polled result is compared with rv_check
+of the same kernel on a plain context, field by field, and with the oracle.
+While the server runs, another thread loads kernels on the same context."""
 
 import sys
+import threading
 import time
 
 import pytest
 
+import oracle
 from workloads import kernels as K
 from workloads import random_affine as RA
 from workloads.desc import GLOBAL, SHARED, Builder, aff, rw
@@ -20,6 +25,13 @@ pytestmark = pytest.mark.gpu
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def _owkey(w):
+    return (w.interval, w.space, w.block, w.array, w.address,
+            (w.first.block, w.first.tid, w.first.dphase, w.first.access, tuple(w.first.loop), w.first.is_write),
+            (w.second.block, w.second.tid, w.second.dphase, w.second.access, tuple(w.second.loop),
+             w.second.is_write))
 
 
 def _wkey(w):
@@ -47,6 +59,7 @@ def _empty_kernel():
 
 def _mix():
     descs = list(RA.serving_stream(seed=5, count=40, lo=1e3, hi=2e6))
+    descs += list(RA.serving_stream(seed=55, count=1, lo=9e6, hi=1e7))
     descs += [K.tiny_fixed(), K.tree_reduction(2), K.tiled_matmul(grid=2, k_iters=4, drop_dynamic=3),
               K.gespmm_crc(middle_barrier=False), _oob_kernel(), _empty_kernel(), K.polynomial_product(48)]
     return descs
@@ -65,7 +78,27 @@ def test_served_equals_alone(max_batch_records):
         except rv.RVError as e:
             alone.append((e.status, None))
     say(f"[serve] {len(descs)} jobs checked alone")
+    assert max(d.instances_upper_bound() for d in descs) >= 9_000_000
+    for d, (st, ref) in zip(descs, alone):
+        o = oracle.check(d, max_witnesses=1)
+        say(f"[serve] oracle {d.name}: status {o.status} records {o.n_records}")
+        assert st == o.status
+        if st == 0:
+            assert (ref.n_records, ref.n_conflicts) == (o.n_records, o.n_conflicts)
+            assert _wkey(ref.witness) == (_owkey(o.witnesses[0]) if o.n_conflicts else None)
     srv = rv.Server(ctx, budget_bytes=256 << 20, max_batch_records=max_batch_records)
+    # a second host thread loads (and frees) kernels on the serving context
+    # while jobs run, the out-of-bounds one included
+    loads = []
+
+    def loader():
+        for d in [K.tiny_fixed(), _oob_kernel(), K.tree_reduction(1)] * 3:
+            kk = ctx.load(d)
+            loads.append(kk.info().n_instances)
+            kk.free()
+
+    th = threading.Thread(target=loader)
+    th.start()
     # submit in three waves with pauses so batches form at different points
     ids = {}
     order = list(range(len(ks))) + list(range(0, len(ks), 3))   # some kernels twice
@@ -73,6 +106,8 @@ def test_served_equals_alone(max_batch_records):
         ids[srv.submit(ks[j])] = j
         if n % 17 == 16:
             time.sleep(0.002)
+    th.join()
+    assert len(loads) == 9
     srv.drain(120000)
     got = srv.poll(cap=4096)
     assert len(got) == len(order)
