@@ -35,10 +35,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per record of each kernel: the expansion writes one
-# 8-byte record, the sort + segmented scan reads it once.  The count pass
+# Algorithmic HBM bytes per record of each kernel, as the path defines a
+# record: a 12-byte (u64 location key, u32 instance id) pair that the
+# expansion writes and the sort + segmented scan reads once.  The count pass
 # only evaluates instances (no record traffic).
-ALG_BYTES = {"expand": 8.0, "sort_scan": 8.0}
+ALG_BYTES = {"expand": 12.0, "sort_scan": 12.0}
+# What this implementation actually moves per record: keys and ids packed
+# into one 8-byte word (31-bit location, rw bit, 32-bit id).
+PACKED_BYTES = 8.0
 # the grouping stage's kernels (fold: buckets of one slice, medium and hot
 # buckets; their HIP-event time is taken together)
 GROUP_KERNEL = {"fold": "k_fold+k_mid+k_hot", "sort_scan": "k_bucket"}
@@ -64,38 +68,76 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline_kernels(descs, max_seconds):
-    """The oracle on whole kernels of the list, in order, until about
-    max_seconds of CPU time."""
+def _host_threads():
+    """Threads for the parallel oracle leg: the CPUs this process may run
+    on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_pool(jobs, threads):
+    """Run oracle.check over jobs [(desc, ilo, ihi)] on a thread pool (the C
+    oracle keeps no global state and ctypes releases the interpreter lock
+    during the call); returns (records, seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(lambda j: oracle.check(j[0], max_witnesses=1, ilo=j[1], ihi=j[2]), jobs))
+    return sum(r.n_records for r in res), time.perf_counter() - t0
+
+
+def cpu_baseline_units(units, max_seconds):
+    """The oracle as it stands, timed on the host: first single-threaded on
+    the first units until about max_seconds / 2, then on `threads` threads
+    (one unit per task, a kernel or one interval) over a sample sized to take
+    about as long.  `units` is a list of (desc, ilo, ihi, label)."""
     import oracle
     oracle.build(force=False)
-    recs = 0
+    recs1, n1 = 0, 0
     t0 = time.perf_counter()
-    n = 0
-    while n < len(descs) and time.perf_counter() - t0 < max_seconds:
-        recs += oracle.check(descs[n], max_witnesses=1).n_records
-        n += 1
-    dt = time.perf_counter() - t0
-    return {"value": recs / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
-            "sample": f"kernels 0..{n - 1} of {len(descs)} ({recs} records, {dt:.1f} s, single thread)"}
+    while n1 < len(units) and time.perf_counter() - t0 < max_seconds / 2:
+        d, lo, hi, _ = units[n1]
+        recs1 += oracle.check(d, max_witnesses=1, ilo=lo, ihi=hi).n_records
+        n1 += 1
+    dt1 = time.perf_counter() - t0
+    rate1 = recs1 / dt1
+    threads = _host_threads()
+    per_unit = dt1 / max(1, n1)
+    m = max(threads, min(len(units), int(threads * (max_seconds / 2) / max(per_unit, 1e-6))))
+    recsN, dtN = _oracle_pool([(d, lo, hi) for d, lo, hi, _ in units[:m]], threads)
+    return {"value": recsN / dtN, "unit": "records/s", "cores": threads, "kind": "oracle",
+            "sample": f"{units[0][3]} 0..{m - 1} of {len(units)} ({recsN} records, {dtN:.1f} s, "
+                      f"{threads} threads, one {units[0][3].rstrip('s')} per task)",
+            "single_thread": {"value": rate1, "cores": 1,
+                              "sample": f"{units[0][3]} 0..{n1 - 1} ({recs1} records, {dt1:.1f} s)"},
+            "host_cpu": _cpu_model(), "host_cpus_visible": os.cpu_count()}
+
+
+def cpu_baseline_kernels(descs, max_seconds):
+    """The oracle on whole kernels of the batch, in order."""
+    return cpu_baseline_units([(d, 0, 1 << 62, "kernels") for d in descs], max_seconds)
 
 
 def cpu_baseline(desc, max_seconds):
-    """The oracle (single-threaded C) on the first intervals of the workload,
-    adding intervals until about max_seconds of CPU time."""
+    """The oracle on the intervals of one kernel, in order."""
     import oracle
     oracle.build(force=False)
     n_iv = oracle.n_intervals(desc)
-    recs = 0
-    t0 = time.perf_counter()
-    iv = 0
-    while iv < n_iv and time.perf_counter() - t0 < max_seconds:
-        r = oracle.check(desc, max_witnesses=1, ilo=iv, ihi=iv + 1)
-        recs += r.n_records
-        iv += 1
-    dt = time.perf_counter() - t0
-    return {"value": recs / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
-            "sample": f"intervals 0..{iv - 1} of {n_iv} ({recs} records, {dt:.1f} s, single thread)"}
+    return cpu_baseline_units([(desc, iv, iv + 1, "intervals") for iv in range(n_iv)], max_seconds)
 
 
 def traffic_for(kernel_name, records_per_launch):
@@ -117,18 +159,23 @@ def traffic_for(kernel_name, records_per_launch):
 def roofline_from(stages, n_records_timed, group_kernel="k_fold"):
     """Dominant kernel (by GPU time, among those with a byte count) and its
     algorithmic bandwidth: bytes per record x records per launch / average
-    launch time (HIP events on the stream the kernel runs on)."""
+    launch time (HIP events on the stream the kernel runs on).  The bytes
+    per record are the path's 12-byte record; `achieved_packed` is the same
+    launch at the 8 bytes per record this implementation moves."""
     dom = max(ALG_BYTES, key=lambda k: stages[k][0])
     launches = max(1, stages[dom][1])
     avg_ms = stages[dom][0] / launches
     recs_per_launch = n_records_timed / launches
     achieved = ALG_BYTES[dom] * recs_per_launch / (avg_ms * 1e-3) / 1e9
+    packed = PACKED_BYTES * recs_per_launch / (avg_ms * 1e-3) / 1e9
     kname = {"expand": "k_scatter", "sort_scan": group_kernel}[dom]
     traffic = traffic_for(kname, int(recs_per_launch))
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
-            "alg_bytes_per_record": ALG_BYTES[dom]}
+            "alg_bytes_per_record": ALG_BYTES[dom], "records_per_launch": int(recs_per_launch),
+            "achieved_packed": round(packed, 1), "frac_packed": round(packed / HBM_PEAK_GBS, 4),
+            "packed_bytes_per_record": PACKED_BYTES}
 
 
 def percentile(xs, q):
@@ -283,6 +330,31 @@ def bench_serve(args, rv, torch):
     print(json.dumps(out), flush=True)
 
 
+def bandwidth_anchor(gib, reps=10):
+    """Achievable-bandwidth anchor: torch's own streaming kernels over a
+    buffer far larger than the last-level cache, timed with HIP events."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    out = {"bytes": 4 * n}
+    for name, fn, moved in (("read", lambda: a.sum(), 4 * n), ("write", lambda: b.fill_(2.0), 4 * n),
+                            ("copy", lambda: b.copy_(a), 8 * n)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "GB/s": round(moved / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_8TBs": round(moved / (ms * 1e-3) / 8e12, 4)}
+        log(f"[anchor] {name}: {out[name]}")
+    print(json.dumps({"bandwidth_anchor": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,10 +373,15 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=10000)
     ap.add_argument("--batch-records", type=int, default=1 << 26, help="server: records per batch at most")
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / closed-loop capacity")
+    ap.add_argument("--bandwidth-anchor", type=float, default=0.0, metavar="GIB",
+                    help="only time plain streaming kernels over GIB gibibytes (read-only reduction, write-only "
+                         "fill, copy) and exit: what this device's HBM delivers to simple kernels")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only copy GIB gibibytes device-to-device (a plain copy kernel of known size, "
                          "to scale the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.bandwidth_anchor:
+        return bandwidth_anchor(args.bandwidth_anchor)
     if args.copy_calibration:
         import torch
         n = int(args.copy_calibration * (1 << 30))
