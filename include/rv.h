@@ -290,6 +290,29 @@ rv_status rv_check_batch(rv_ctx *ctx, rv_kernel *const *ks, size_t n, rv_result 
 rv_status rv_get_witnesses(rv_ctx *ctx, rv_kernel *k, uint64_t first_index, rv_witness *out,
                            size_t cap, size_t *n_out);
 
+/* For callers that cannot allocate device memory while they check: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same check as rv_check (same kernels, bit-identical
+ * result), but its scratch -- the records of one chunk, the per-bucket
+ * arrays, the hot-bucket lists and the per-pass result slots -- lives in a
+ * library-owned device array of RV_STATIC_SCRATCH_BYTES, one per device,
+ * held from the first rv_ctx_create on that device until the process ends;
+ * the context's workspace is not used.  The kernel's pass table for that
+ * array is built and uploaded by rv_load_kernel_desc, so this call makes no
+ * allocation of any kind: it launches the kernels on the context's stream,
+ * copies the per-pass results into a fixed host buffer of its own and
+ * waits on the stream.  Every call on one device shares that device's
+ * array, which keeps the last call's contents (each call clears what it
+ * needs): calls that overlap on one device -- from different threads, or
+ * from contexts on different streams -- race, and the caller must serialise
+ * them.  Errors: RV_ERR_TOO_LARGE when one of k's passes needs more records
+ * or buckets than the array holds, or k has more than RV_STATIC_MAX_PASSES
+ * passes (rv_last_error gives the sizes); RV_ERR_DEVICE if the array's
+ * address could not be obtained at context creation; otherwise as rv_check. */
+#define RV_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+#define RV_STATIC_MAX_PASSES 8192
+rv_status rv_check_static(rv_ctx *ctx, rv_kernel *k, rv_result *out);
+
 /* Records of one barrier interval as the expansion wrote them (sorted = 0)
  * or after the per-bucket sort (sorted = 1: location order; requires every
  * bucket to fit one on-chip slice, else RV_ERR_UNSUPPORTED).  *n_out is the

@@ -40,6 +40,7 @@ struct Lane {
     void *h_down = nullptr;     // pinned: results coming down
     size_t down_cap = 0;
     hipEvent_t done = nullptr;
+    bool untimed = false;       // never record timing events (rv_check_static creates none)
     // the batch in flight
     std::vector<rv_kernel *> jobs;
     std::vector<size_t> res0;
@@ -77,6 +78,7 @@ struct rv_ctx {
     size_t ws_bytes = 0;
     Lane main;
     std::string err;
+    hipError_t scratch_err = hipSuccess;   // lookup of the static scratch's address on `device`
     bool serving = false;           // a server owns the device work of this context (set and cleared
                                     // while no worker thread runs)
     std::atomic<int> target{DEFAULT_TARGET};   // planner: mean records per bucket for kernels loaded next
@@ -134,8 +136,9 @@ hipEvent_t get_event(rv_ctx *c) {
 }
 
 template <class F>
-void timed(rv_ctx *c, hipStream_t st, int stage, F &&f) {
-    if (c->serving || !c->timing) { f(); return; }
+void timed(rv_ctx *c, const Lane &ln, int stage, F &&f) {
+    if (c->serving || !c->timing || ln.untimed) { f(); return; }
+    hipStream_t st = ln.stream;
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) { f(); return; }
     (void)hipEventRecord(a, st);
@@ -202,11 +205,11 @@ rv_status check_launch(Lane &ln) {
 // count -> scan -> expansion for one chunk
 void run_expand(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
     hipStream_t st = ln.stream;
-    timed(c, st, RV_STAGE_FILL, [&] { launch_fill_u32(ln.counts(), buckets, 0u, st); });
-    timed(c, st, RV_STAGE_COUNT, [&] { launch_hist(subs, nsub, items, ln.counts(), ln.d_res, c->ncu, st); });
-    timed(c, st, RV_STAGE_SCAN,
+    timed(c, ln, RV_STAGE_FILL, [&] { launch_fill_u32(ln.counts(), buckets, 0u, st); });
+    timed(c, ln, RV_STAGE_COUNT, [&] { launch_hist(subs, nsub, items, ln.counts(), ln.d_res, c->ncu, st); });
+    timed(c, ln, RV_STAGE_SCAN,
           [&] { launch_scan(ln.counts(), ln.starts(), ln.cursor(), ln.bsum(), buckets, st); });
-    timed(c, st, RV_STAGE_EXPAND,
+    timed(c, ln, RV_STAGE_EXPAND,
           [&] { launch_scatter(subs, nsub, items, ln.rec(), ln.cursor(), c->ncu, st); });
 }
 
@@ -222,8 +225,8 @@ void run_group(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t 
 void run_check_chunk(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
     hipStream_t st = ln.stream;
     run_expand(c, ln, subs, nsub, items, buckets);
-    timed(c, st, RV_STAGE_SORT_SCAN, [&] { run_group(c, ln, subs, nsub, buckets); });
-    timed(c, st, RV_STAGE_FINISH, [&] {
+    timed(c, ln, RV_STAGE_SORT_SCAN, [&] { run_group(c, ln, subs, nsub, buckets); });
+    timed(c, ln, RV_STAGE_FINISH, [&] {
         launch_finish(subs, nsub, buckets, ln.conf(), ln.d_res, st);
         launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_res, st);
     });
@@ -238,41 +241,59 @@ void decode_witness(const rv_kernel &k, uint32_t interval, const uint32_t w[4], 
     decode_instance(k, interval, w[2], out.second, g, l);
 }
 
-// Per-kernel result from its passes' slots hr[0 .. k.subs.size()).
-rv_status assemble(const rv_kernel &k, const SubResult *hr, rv_result *out, std::string &msg) {
-    rv_result r;
-    memset(&r, 0, sizeof r);
+// Folds the passes' slots of one kernel, in pass order, into its result.
+struct ResultAcc {
+    rv_result r{};
     unsigned long long oob = ~0ull;
-    for (size_t i = 0; i < k.subs.size(); i++) {
-        if (hr[i].pad) {
+    bool overflow = false;
+    bool have_first = false;
+    uint32_t first_sub = 0;
+    uint32_t w[4] = {0, 0, 0, 0};
+
+    void add(const SubResult &s, uint32_t i) {
+        overflow = overflow || s.pad;
+        r.n_records += s.records;
+        r.n_conflicts += s.conflicts;
+        oob = std::min(oob, s.oob);
+        if (s.conflicts && !have_first) {
+            have_first = true;
+            first_sub = i;
+            memcpy(w, s.w, sizeof w);
+        }
+    }
+
+    rv_status finish(const rv_kernel &k, rv_result *out, std::string &msg) {
+        if (overflow) {
             msg = "internal: the hot-bucket lists of the grouping stage overflowed their capacity";
             return RV_ERR_DEVICE;
         }
-        r.n_records += hr[i].records;
-        r.n_conflicts += hr[i].conflicts;
-        oob = std::min(oob, hr[i].oob);
-    }
-    if (oob != ~0ull) {
-        uint32_t iv = (uint32_t)(oob >> 32), id = (uint32_t)oob;
-        rv_side s;
-        uint32_t g, l;
-        decode_instance(k, iv, id, s, g, l);
-        char buf[256];
-        snprintf(buf, sizeof buf,
-                 "index out of bounds: interval %u, block %u, thread %u, dynamic phase %u, access %u, loop (%d,%d,%d)",
-                 iv, s.block, s.tid, s.dyn_phase, s.access, s.loop[0], s.loop[1], s.loop[2]);
-        msg = buf;
-        return RV_ERR_OOB;
-    }
-    for (size_t i = 0; i < k.subs.size(); i++) {
-        if (hr[i].conflicts) {
-            decode_witness(k, k.subs[i].interval, hr[i].w, r.witness);
-            r.has_witness = 1;
-            break;
+        if (oob != ~0ull) {
+            uint32_t iv = (uint32_t)(oob >> 32), id = (uint32_t)oob;
+            rv_side s;
+            uint32_t g, l;
+            decode_instance(k, iv, id, s, g, l);
+            char buf[256];
+            snprintf(buf, sizeof buf,
+                     "index out of bounds: interval %u, block %u, thread %u, dynamic phase %u, access %u, loop "
+                     "(%d,%d,%d)",
+                     iv, s.block, s.tid, s.dyn_phase, s.access, s.loop[0], s.loop[1], s.loop[2]);
+            msg = buf;
+            return RV_ERR_OOB;
         }
+        if (have_first) {
+            decode_witness(k, k.subs[first_sub].interval, w, r.witness);
+            r.has_witness = 1;
+        }
+        *out = r;
+        return RV_OK;
     }
-    *out = r;
-    return RV_OK;
+};
+
+// Per-kernel result from its passes' slots hr[0 .. k.subs.size()).
+rv_status assemble(const rv_kernel &k, const SubResult *hr, rv_result *out, std::string &msg) {
+    ResultAcc acc;
+    for (size_t i = 0; i < k.subs.size(); i++) acc.add(hr[i], (uint32_t)i);
+    return acc.finish(k, out, msg);
 }
 
 // Records a job of k may need on a lane (its largest pass and bucket count).
@@ -298,7 +319,7 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
     // A single kernel planned for this workspace uses its resident pass table.
     const bool resident = n == 1 && ks[0]->plan_cap_records == ln.L.cap_records &&
                           ks[0]->plan_cap_buckets == ln.L.cap_buckets;
-    timed(c, s, RV_STAGE_FILL, [&] { launch_init_results(ln.d_res, ns, s); });
+    timed(c, ln, RV_STAGE_FILL, [&] { launch_init_results(ln.d_res, ns, s); });
     if (resident) {
         const rv_kernel *k = ks[0];
         for (auto &ch : k->chunks)
@@ -534,6 +555,9 @@ rv_status rv_ctx_create(rv_ctx **out, int device, void *hip_stream, void *worksp
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->ncu = (unsigned)ncu;
+    // the address of this device's static scratch (rv_check_static); a
+    // failure is reported by rv_check_static, which alone needs it
+    c->scratch_err = static_scratch_init(device);
     *out = c;
     return RV_OK;
 }
@@ -556,6 +580,12 @@ const char *rv_last_error(const rv_ctx *c) { return c ? c->err.c_str() : "null c
 
 namespace {
 
+// Workspace part of the static scratch (after the result slots).
+const WorkspaceLayout &static_layout() {
+    static const WorkspaceLayout L = layout_workspace(RV_STATIC_SCRATCH_BYTES - STATIC_RES_BYTES);
+    return L;
+}
+
 rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kernel **out) {
     rv_kernel *k = new (std::nothrow) rv_kernel;
     if (!k) return fail(c, RV_ERR_TOO_LARGE, "out of host memory");
@@ -571,6 +601,25 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     if (st) { delete k; return fail(c, st, m); }
     k->plan_cap_records = c->main.L.cap_records;
     k->plan_cap_buckets = c->main.L.cap_buckets;
+    // the same passes chunked for the static scratch of rv_check_static
+    try {
+        std::vector<ChunkPlan> main_chunks = std::move(k->chunks);
+        std::string sm;
+        if (k->subs.size() > (size_t)RV_STATIC_MAX_PASSES) {
+            k->static_msg = "the kernel has " + std::to_string(k->subs.size()) + " passes; the static scratch holds " +
+                            std::to_string(RV_STATIC_MAX_PASSES) + " result slots";
+        } else if (plan_chunks(*k, static_layout(), sm) == RV_OK) {
+            k->static_ok = true;
+        } else {
+            k->static_msg = "static scratch of " + std::to_string(RV_STATIC_SCRATCH_BYTES >> 20) + " MiB: " + sm;
+        }
+        k->chunks_static = std::move(k->chunks);
+        k->chunks = std::move(main_chunks);
+        if (!k->static_ok) k->chunks_static.clear();
+    } catch (const std::bad_alloc &) {
+        delete k;
+        return fail(c, RV_ERR_TOO_LARGE, "out of host memory");
+    }
     if (hipSetDevice(c->device) != hipSuccess) { delete k; return fail(c, RV_ERR_DEVICE, "hipSetDevice failed"); }
     // one device block: kernel constants, entries, guard rows, entry prefixes, passes
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -579,7 +628,8 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     const size_t o_gr = al(o_en + k->entries.size() * sizeof(DevEntry));
     const size_t o_ei = al(o_gr + k->guard_rows.size() * sizeof(int32_t));
     const size_t o_sb = al(o_ei + k->entry_items.size() * sizeof(uint32_t));
-    const size_t total = al(o_sb + k->subs.size() * sizeof(DevSub) + 1);
+    const size_t o_ss = al(o_sb + k->subs.size() * sizeof(DevSub));
+    const size_t total = al(o_ss + (k->static_ok ? k->subs.size() : 0) * sizeof(DevSub) + 1);
     hipError_t e = hipMalloc(&k->d_mem, total);
     if (e != hipSuccess) { delete k; return fail(c, RV_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e)); }
     char *base = reinterpret_cast<char *>(k->d_mem);
@@ -588,11 +638,18 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     k->d_guards = reinterpret_cast<int32_t *>(base + o_gr);
     k->d_entry_items = reinterpret_cast<uint32_t *>(base + o_ei);
     k->d_subs = reinterpret_cast<DevSub *>(base + o_sb);
+    k->d_subs_static = k->static_ok ? reinterpret_cast<DevSub *>(base + o_ss) : nullptr;
     k->h_subs.clear();
     for (auto &ch : k->chunks) {
         uint64_t items = 0, buckets = 0;
         make_devsubs(*k, ch.sub_begin, ch.sub_end, 0, k->h_subs, items, buckets);
         for (uint32_t i = ch.sub_begin; i < ch.sub_end; i++) k->h_subs[i].res = i;
+    }
+    std::vector<DevSub> h_static;
+    for (auto &ch : k->chunks_static) {
+        uint64_t items = 0, buckets = 0;
+        make_devsubs(*k, ch.sub_begin, ch.sub_end, 0, h_static, items, buckets);
+        for (uint32_t i = ch.sub_begin; i < ch.sub_end; i++) h_static[i].res = i;
     }
     std::vector<char> host(total, 0);
     memcpy(host.data() + o_kc, &k->kc, sizeof(DevKernel));
@@ -600,6 +657,7 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     if (!k->guard_rows.empty()) memcpy(host.data() + o_gr, k->guard_rows.data(), k->guard_rows.size() * 4);
     if (!k->entry_items.empty()) memcpy(host.data() + o_ei, k->entry_items.data(), k->entry_items.size() * 4);
     if (!k->h_subs.empty()) memcpy(host.data() + o_sb, k->h_subs.data(), k->h_subs.size() * sizeof(DevSub));
+    if (!h_static.empty()) memcpy(host.data() + o_ss, h_static.data(), h_static.size() * sizeof(DevSub));
     e = hipMemcpy(k->d_mem, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(k->d_mem);
@@ -707,6 +765,45 @@ rv_status rv_check_batch(rv_ctx *c, rv_kernel *const *ks, size_t n, rv_result *o
     rv_status st = lane_enqueue(c, c->main, ks, n);
     if (st) return main_fail(c, st);
     return main_fail(c, lane_collect(c->main, out, nullptr));
+}
+
+rv_status rv_check_static(rv_ctx *c, rv_kernel *k, rv_result *out) {
+    if (!c || !k || !out) return RV_ERR_INVALID;
+    if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
+    c->err.clear();
+    if (!k->static_ok) return fail(c, RV_ERR_TOO_LARGE, k->static_msg);
+    if (c->scratch_err != hipSuccess)
+        return fail(c, RV_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(c->scratch_err));
+    HIP_TRY(c, hipSetDevice(c->device));
+    char *base = reinterpret_cast<char *>(static_scratch(c->device));
+    if (!base) return fail(c, RV_ERR_DEVICE, "the static scratch has no address on this device");
+    // a lane over the static scratch: result slots first, then one chunk's workspace
+    Lane ln;
+    ln.stream = c->main.stream;
+    ln.untimed = true;
+    ln.d_res = reinterpret_cast<SubResult *>(base);
+    ln.ws = base + STATIC_RES_BYTES;
+    ln.L = static_layout();
+    const size_t ns = k->subs.size();
+    launch_init_results(ln.d_res, ns, ln.stream);
+    for (auto &ch : k->chunks_static)
+        run_check_chunk(c, ln, k->d_subs_static + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets);
+    rv_status st = check_launch(ln);
+    if (st) return fail(c, st, ln.err);
+    // results come down through a fixed host buffer, a piece at a time
+    ResultAcc acc;
+    SubResult piece[128];
+    for (size_t i = 0; i < ns; i += 128) {
+        const size_t n = std::min<size_t>(128, ns - i);
+        HIP_TRY(c, hipMemcpyAsync(piece, ln.d_res + i, n * sizeof(SubResult), hipMemcpyDeviceToHost, ln.stream));
+        HIP_TRY(c, hipStreamSynchronize(ln.stream));
+        for (size_t j = 0; j < n; j++) acc.add(piece[j], (uint32_t)(i + j));
+    }
+    if (!ns) HIP_TRY(c, hipStreamSynchronize(ln.stream));
+    std::string m;
+    st = acc.finish(*k, out, m);
+    return st ? fail(c, st, m) : RV_OK;
 }
 
 rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_witness *out, size_t cap,

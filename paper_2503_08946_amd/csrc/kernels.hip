@@ -34,6 +34,7 @@
 // same XCD (workgroups are dealt round-robin over the 8 XCDs), so the bucket
 // counters and partially written lines they share stay in one L2.
 
+#include <mutex>
 #include <type_traits>
 
 #include "rv_internal.h"
@@ -1877,6 +1878,42 @@ __global__ void k_gather(const DevSub *subs_g, uint32_t nsub, const unsigned lon
             out[g - lo] = d;
         }
     }
+}
+
+// ------------------------------------------------ static scratch (no-alloc)
+// Scratch of rv_check_static: per-pass result slots, then one chunk's
+// workspace (records, bucket arrays, hot lists).  Each device holds its own
+// copy from the moment the library's code object is loaded on it until the
+// process ends.  Host code must never pass `scratch` itself to a kernel (in
+// host code the name is a stand-in, not a device address): it uses the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[RV_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_DEVICES];
+hipError_t g_scratch_err[SCRATCH_DEVICES];
+bool g_scratch_done[SCRATCH_DEVICES];
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+    if (device < 0 || device >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_err[device];
+}
+
+void *static_scratch(int device) {
+    if (device < 0 || device >= SCRATCH_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_done[device] ? g_scratch_ptr[device] : nullptr;
 }
 
 // --------------------------------------------------------------- launchers

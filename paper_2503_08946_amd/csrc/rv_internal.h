@@ -237,6 +237,11 @@ struct rv_kernel {
     std::vector<rv::DevSub> h_subs;
     size_t plan_cap_records = 0;     // the workspace layout `chunks` was planned for
     size_t plan_cap_buckets = 0;
+    // the same passes chunked for the static scratch of rv_check_static
+    std::vector<rv::ChunkPlan> chunks_static;
+    rv::DevSub *d_subs_static = nullptr;
+    bool static_ok = false;
+    std::string static_msg;          // why static_ok is false
     rv_ctx *owner = nullptr;
 };
 
@@ -289,5 +294,13 @@ void launch_gather(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const u
                    unsigned long long base, unsigned long long lo, unsigned long long hi,
                    DevWitness *out, hipStream_t st);
 size_t scan_bsum_words(size_t n);
+
+// The device scratch of rv_check_static (kernels.hip): its address on
+// `device` is looked up once, with that device current (rv_ctx_create), and
+// kept; static_scratch returns it, or null before a successful lookup.
+hipError_t static_scratch_init(int device);
+void *static_scratch(int device);
+// Static scratch layout: RV_STATIC_MAX_PASSES result slots, then a workspace.
+constexpr size_t STATIC_RES_BYTES = ((size_t)RV_STATIC_MAX_PASSES * sizeof(SubResult) + 255) & ~(size_t)255;
 
 }  // namespace rv

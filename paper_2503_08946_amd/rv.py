@@ -150,6 +150,7 @@ def lib():
             "rv_kernel_get_info": [V, V, P(rv_kernel_info)],
             "rv_check": [V, V, P(rv_result)],
             "rv_check_batch": [V, P(V), S, P(rv_result)],
+            "rv_check_static": [V, V, P(rv_result)],
             "rv_get_witnesses": [V, V, u64, P(rv_witness), S, P(S)],
             "rv_debug_records": [V, V, u32, ctypes.c_int, P(rv_record), S, P(S)],
             "rv_set_timing": [V, ctypes.c_int],
@@ -176,7 +177,8 @@ def lib():
 
 
 EXPORTED = ("rv_validate_desc", "rv_plan_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_error", "rv_load_kernel_desc",
-            "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_get_witnesses",
+            "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_check_static",
+            "rv_get_witnesses",
             "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest", "rv_ctx_get_tuning",
             "rv_ctx_set_tuning", "rv_autotune", "rv_server_create",
             "rv_server_destroy", "rv_server_submit", "rv_server_poll", "rv_server_drain", "rv_server_get_stats")
@@ -415,6 +417,13 @@ class Context:
     def check(self, k: Kernel) -> Result:
         out = rv_result()
         self._call(lib().rv_check, self.handle, k.handle, ctypes.byref(out))
+        return _result(out)
+
+    def check_static(self, k: Kernel) -> Result:
+        """rv_check_static: the check with the library's static device
+        scratch instead of the context's workspace (no allocation)."""
+        out = rv_result()
+        self._call(lib().rv_check_static, self.handle, k.handle, ctypes.byref(out))
         return _result(out)
 
     def check_batch(self, ks: Sequence[Kernel]) -> List[Result]:
