@@ -16,6 +16,11 @@ Workloads (synthetic, seeded descriptions from ``workloads``):
   batch      4096 random affine 2-D kernels (seed 4, records log-uniform in
              [1e2, 1e6], 432,085,651 records) checked by one rv_check_batch
              per step; also times one rv_check per kernel for comparison
+  gespmm     the shared-memory staging pattern of Ge-SpMM's Algorithm 2
+             (the paper's case study) across sizes (M rows, N columns, T
+             chunks, K candidate B rows): the race-free kernel is timed at
+             each size and its two barrier-dropped mutants are checked
+             against their closed forms
   serve      a server over a 64 GiB budget fed 10,000 random affine jobs
              (seed 5, records log-uniform in [1e3, 1e7]) at Poisson arrival
              times, rate 0.7 x the measured closed-loop capacity, after 500
@@ -249,6 +254,84 @@ def bench_batch(args, rv, torch):
     print(json.dumps(out), flush=True)
 
 
+def gespmm_expected(M, N, T, K):
+    """Hand-derived counts of the Ge-SpMM staging kernel (B read over the
+    candidate rows only): records, and conflicts with both barriers (the
+    paper's verdict: race-free), without the middle barrier and without the
+    trailing one; the first witness of each mutant sits at sm_k[0] of block 0."""
+    threads, blocks = M * N, M * (N // 32)
+    return {"records": threads * T * (4 + 32 * (4 + K)),
+            "both": 0, "no_middle": 64 * T * blocks, "no_trailing": 64 * (T - 1) * blocks}
+
+
+def bench_gespmm(args, rv, torch):
+    from workloads import kernels as K
+    ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
+    ctx.group = args.group
+    ctx.target = args.target
+    sweep, total_records, total_s, stage_acc = [], 0, 0.0, None
+    for (M, N, T, Kb) in K.GESPMM_SWEEP:
+        exp = gespmm_expected(M, N, T, Kb)
+        # the two mutants: counted once, against their closed forms
+        mut = {}
+        for tag, mid, trail in (("no_middle", False, True), ("no_trailing", True, False)):
+            km = ctx.load(K.gespmm_crc(M, N, T, Kb, middle_barrier=mid, trailing_barrier=trail, kb_on_all=False))
+            r = ctx.check(km)
+            km.free()
+            w = r.witness
+            ok = (r.n_records == exp["records"] and r.n_conflicts == exp[tag] and w is not None
+                  and (w.space, w.block, w.array, w.address) == (0, 0, 4, 0)
+                  and (w.first.tid, w.first.is_write, w.second.tid, w.second.is_write) == (0, 1, 31, 0))
+            if not ok:
+                raise SystemExit(f"gespmm {M}x{N} T={T} K={Kb} {tag}: {r} differs from the closed form {exp}")
+            mut[tag] = r.n_conflicts
+        k = ctx.load(K.gespmm_crc(M, N, T, Kb, kb_on_all=False))
+        for i in range(args.warmup):
+            r = ctx.check(k)
+        ctx.timing(reset=True)
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            r = ctx.check(k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.set_timing(False)
+        stages = ctx.timing(reset=True)
+        k.free()
+        if (r.n_records, r.n_conflicts) != (exp["records"], 0):
+            raise SystemExit(f"gespmm {M}x{N} T={T} K={Kb}: {r} differs from the closed form {exp}")
+        stage_acc = stages if stage_acc is None else {
+            n: (stage_acc[n][0] + v[0], stage_acc[n][1] + v[1]) for n, v in stages.items()}
+        total_records += r.n_records * args.steps
+        total_s += dt
+        ms = dt / args.steps * 1e3
+        sweep.append({"M": M, "N": N, "T": T, "K": Kb, "records": r.n_records, "ms": round(ms, 3),
+                      "records_per_s": r.n_records / (ms * 1e-3), "conflicts": r.n_conflicts,
+                      "verdict": "race-free" if r.n_conflicts == 0 else "races",
+                      "mutant_conflicts": mut})
+        log(f"[bench] gespmm M={M} N={N} T={T} K={Kb}: {r.n_records} records, {ms:.2f} ms, "
+            f"{r.n_records / (ms * 1e-3):.3g} records/s, conflicts 0 (mutants {mut})")
+    per_step = {n: v[0] / args.steps for n, v in stage_acc.items()}
+    out = {
+        "metric": "access records race-checked/sec + % HBM peak; p50/p99 verify latency",
+        "value": total_records / total_s, "unit": "records/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total_s / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "Ge-SpMM Algorithm 2 shared-memory staging (coalesced row caching), superset "
+                               "domain, B read over K candidate rows; one step = one check of each size in turn",
+                   "records": total_records // args.steps, "sizes": len(sweep)},
+        "sweep": sweep,
+        "stage_ms_per_step": {n: round(v, 4) for n, v in per_step.items()},
+        "roofline": roofline_from(stage_acc, total_records, GROUP_KERNEL[ctx.group]),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        M, N, T, Kb = K.GESPMM_SWEEP[0]
+        out["cpu_baseline"] = cpu_baseline(K.gespmm_crc(M, N, T, Kb, kb_on_all=False), args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args, rv, torch):
     import numpy as np
     from workloads import random_affine as RA
@@ -406,6 +489,8 @@ def main():
         return bench_batch(args, rv, torch)
     if args.workload == "serve":
         return bench_serve(args, rv, torch)
+    if args.workload == "gespmm":
+        return bench_gespmm(args, rv, torch)
     descs, wl_text = make_workload(args.workload)
     log(f"[bench] workload {args.workload}: {wl_text}")
     ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))

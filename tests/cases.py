@@ -235,3 +235,14 @@ def large_grid(offset, dim, write_offset=None):
     p = b.phase(acc, False)
     b.segment([p])
     return b.build()
+
+
+def gespmm_closed_form(M, N, T, K):
+    """Hand-derived figures of ``gespmm_crc(M, N, T, K, kb_on_all=False)``
+    (the derivation is in golden/closed_forms.json, entry gespmm-crc-b-only):
+    records, and conflicts with both barriers, without the middle one and
+    without the trailing one."""
+    threads = M * N
+    blocks = M * (N // 32)
+    return {"records": threads * T * (4 + 32 * (4 + K)),
+            "conflicts": {"both": 0, "no_middle": 64 * T * blocks, "no_trailing": 64 * (T - 1) * blocks}}

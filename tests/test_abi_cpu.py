@@ -124,3 +124,15 @@ def test_plan_matches_validate_errors():
     info = rv.plan(K.tiled_matmul(grid=16, k_iters=64, drop_dynamic=64))
     assert info.n_instances == 1_141_112_832 and info.n_intervals == 128
     assert info.n_chunks == 0 and info.n_fast_entries == info.n_proven_entries == info.n_entries
+
+
+@pytest.mark.parametrize("size", list(K.GESPMM_SWEEP), ids=lambda s: "M%d-N%d-T%d-K%d" % s)
+def test_plan_gespmm_sweep_sizes(size):
+    # every size the Ge-SpMM benchmark sweeps plans in all three variants,
+    # with the hand-derived record count (no guards: instances = records)
+    from cases import gespmm_closed_form
+    M, N, T, Kb = size
+    cf = gespmm_closed_form(M, N, T, Kb)
+    for mid, trail in ((True, True), (False, True), (True, False)):
+        info = rv.plan(K.gespmm_crc(M, N, T, Kb, middle_barrier=mid, trailing_barrier=trail, kb_on_all=False))
+        assert info.n_instances == cf["records"]

@@ -104,6 +104,19 @@ def test_gespmm_crc(mid, trail, expect):
         assert _loc(w) == wp["loc"] and _side(w.first) == wp["first"] and _side(w.second) == wp["second"]
 
 
+@pytest.mark.parametrize("mid,trail,expect", [tuple(v) for v in PINS["gespmm-crc-b-only"]["variants"]])
+def test_gespmm_crc_b_only(mid, trail, expect):
+    pin = PINS["gespmm-crc-b-only"]
+    desc = K.gespmm_crc(M=4, N=64, T=3, K=2, middle_barrier=mid, trailing_barrier=trail, kb_on_all=False)
+    r = oracle.check(desc)
+    assert r.n_records == pin["n_records"] == 4 * 64 * 3 * (4 + 32 * (4 + 2))
+    assert r.n_conflicts == expect and r.n_pairs == 31 * expect
+    if not mid and trail:
+        w = r.witnesses[0]
+        wp = pin["witness_middle_dropped"]
+        assert _loc(w) == wp["loc"] and _side(w.first) == wp["first"] and _side(w.second) == wp["second"]
+
+
 # ----------------------------------------------------------- brute force
 def _brute_compare(desc):
     n, confl = brute_check(desc)

@@ -180,7 +180,8 @@ def polynomial_product(n: int = 64) -> KernelDesc:
 
 
 def gespmm_crc(M: int = 4, N: int = 64, T: int = 3, K: int = 2,
-               middle_barrier: bool = True, trailing_barrier: bool = True) -> KernelDesc:
+               middle_barrier: bool = True, trailing_barrier: bool = True,
+               kb_on_all: bool = True) -> KernelDesc:
     """The shared-memory staging pattern of Ge-SpMM's Algorithm 2 written from
     the access relations of Section 2.1.2, as a SIMT kernel.
 
@@ -194,9 +195,16 @@ def gespmm_crc(M: int = 4, N: int = 64, T: int = 3, K: int = 2,
     T: for kk in [0,32), kb in [0,K):  R sm_k[kk], R sm_val[kk], R B[kb][j],
        R C[i][j], W C[i][j]       (kb is the existential row index of B)
        [barrier]
+
+    With ``kb_on_all = False`` only the read of B ranges over ``kb`` (the
+    relation of Section 2.1.2 quantifies k in the B read alone); the other
+    T accesses loop over ``kk`` only.  The races are the same either way:
+    only the number of repeated reads differs.
     """
     assert N % 32 == 0
-    b = Builder((32, 1), (M, N // 32), f"gespmm-crc-M{M}-N{N}-T{T}")
+    tag = f"gespmm-crc-M{M}-N{N}-T{T}" + ("" if kb_on_all else f"-K{K}")
+    tag += ("" if middle_barrier else "-nomid") + ("" if trailing_barrier else "-notrail")
+    b = Builder((32, 1), (M, N // 32), tag)
     colInd = b.array(GLOBAL, (32 * T,), "A_colInd")
     val = b.array(GLOBAL, (32 * T,), "A_val")
     Bm = b.array(GLOBAL, (K, N), "B")
@@ -210,17 +218,25 @@ def gespmm_crc(M: int = 4, N: int = 64, T: int = 3, K: int = 2,
         rw(sm_v, True, aff(tx=1), name="W sm_val[tid]"),
     ]
     loops = ((0, 32), (0, K))
+    lk = loops if kb_on_all else ((0, 32),)
     t_acc = [
-        rw(sm_k, False, aff(l0=1), loops=loops, name="R sm_k[kk]"),
-        rw(sm_v, False, aff(l0=1), loops=loops, name="R sm_val[kk]"),
+        rw(sm_k, False, aff(l0=1), loops=lk, name="R sm_k[kk]"),
+        rw(sm_v, False, aff(l0=1), loops=lk, name="R sm_val[kk]"),
         rw(Bm, False, aff(l1=1), aff(by=32, tx=1), loops=loops, name="R B[kb][j]"),
-        rw(Cm, False, aff(bx=1), aff(by=32, tx=1), loops=loops, name="R C[i][j]"),
-        rw(Cm, True, aff(bx=1), aff(by=32, tx=1), loops=loops, name="W C[i][j]"),
+        rw(Cm, False, aff(bx=1), aff(by=32, tx=1), loops=lk, name="R C[i][j]"),
+        rw(Cm, True, aff(bx=1), aff(by=32, tx=1), loops=lk, name="W C[i][j]"),
     ]
     pf = b.phase(f_acc, barrier_after=middle_barrier)
     pt = b.phase(t_acc, barrier_after=trailing_barrier)
     b.segment([pf, pt], repeat=T)
     return b.build()
+
+
+# Sizes of the Ge-SpMM staging benchmark: (M rows, N columns, T chunks of 32
+# nonzeros per row, K candidate rows of B).  Every row holds the superset of
+# T chunks (Section 2.1.1), so a size is a record count, not a sparsity
+# pattern; the largest barrier interval stays below 2^32 instances.
+GESPMM_SWEEP = ((1024, 64, 4, 8), (4096, 128, 4, 16), (16384, 256, 2, 8), (65536, 64, 8, 4))
 
 
 # ------------------------------------------------------ textbook patterns
