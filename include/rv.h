@@ -104,9 +104,17 @@ typedef struct {
 
 typedef struct { rv_affine g; } rv_guard;   /* holds iff g >= 0 */
 
-/* A run of accesses ("code section"); barrier_after != 0 ends it with a
- * block-wide barrier.  Barriers are block-uniform. */
-typedef struct { int32_t access_begin, access_count, barrier_after; } rv_phase;
+/* A run of accesses ("code section") that may end with a barrier
+ * (Section 2, component (4)): RV_BARRIER_BLOCK orders every thread of the
+ * block (__syncthreads); RV_BARRIER_WARP orders the threads of one warp
+ * (__syncwarp over the whole warp: the warp-level synchronisation of
+ * coarse-grained warp merging, Section 1.1.4).  guard_begin / guard_count
+ * (a range in rv_kernel_desc.guards; affine in tx, ty, bx, by, k only) name
+ * the threads that reach the barrier: they feed the divergence check
+ * (rv_check_barriers); the race check treats every barrier as reached by
+ * all threads of its scope. */
+enum { RV_BARRIER_NONE = 0, RV_BARRIER_BLOCK = 1, RV_BARRIER_WARP = 2 };
+typedef struct { int32_t access_begin, access_count, barrier_after, guard_begin, guard_count; } rv_phase;
 
 /* A run of phases executed repeat times; RV_V_K = k_base + repetition.  The
  * order of segments, repetitions and phases is the schedule. */
@@ -119,6 +127,7 @@ typedef struct {
     const rv_guard *guards;     int32_t n_guards;
     const rv_phase *phases;     int32_t n_phases;
     const rv_segment *segments; int32_t n_segments;
+    int32_t warp_size;          /* threads per warp: consecutive linear thread ids of a block (0: 32) */
 } rv_kernel_desc;
 
 /* ---------------------------------------------------------------- results */

@@ -66,6 +66,16 @@ class OrcRecord(ctypes.Structure):
         [("loop", ctypes.c_int64 * 3), ("is_write", ctypes.c_int64)]
 
 
+class OrcDeps(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "status", "n_records", "n_raw", "n_waw", "n_war", "n_dep_locations")] + [("oob", ctypes.c_int64 * 5)]
+
+
+class OrcDiv(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "status", "n_instances", "n_divergent", "dphase", "block", "warp", "arrive_tid", "skip_tid")]
+
+
 _lib = None
 
 
@@ -84,6 +94,13 @@ def _load():
         lib.orc_records.restype = ctypes.c_int
         lib.orc_intervals.argtypes = [P(ctypes.c_int64), ctypes.c_int64, P(ctypes.c_int64)]
         lib.orc_intervals.restype = ctypes.c_int
+        lib.orc_check_strict.argtypes = [P(ctypes.c_int64), ctypes.c_int64, P(OrcResult), P(OrcWitness),
+                                         ctypes.c_int64]
+        lib.orc_check_strict.restype = ctypes.c_int
+        lib.orc_ordered.argtypes = [P(ctypes.c_int64), ctypes.c_int64, P(OrcDeps)]
+        lib.orc_ordered.restype = ctypes.c_int
+        lib.orc_divergence.argtypes = [P(ctypes.c_int64), ctypes.c_int64, P(OrcDiv)]
+        lib.orc_divergence.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -91,7 +108,8 @@ def _load():
 def serialize(desc) -> np.ndarray:
     """Description -> the oracle's int64 word layout (see rv_oracle.c)."""
     w = [MAGIC, desc.block[0], desc.block[1], desc.grid[0], desc.grid[1],
-         len(desc.arrays), len(desc.accesses), 0, len(desc.phases), len(desc.segments)]
+         len(desc.arrays), len(desc.accesses), 0, len(desc.phases), len(desc.segments),
+         getattr(desc, "warp_size", 32)]
     guards = []
     for a in desc.arrays:
         dims = list(a.dims) + [1] * (3 - len(a.dims))
@@ -107,10 +125,14 @@ def serialize(desc) -> np.ndarray:
             w += list(ac.idx[d]) if d < len(ac.idx) else [0] * 11
         w += [len(guards), len(ac.guards)]
         guards += list(ac.guards)
+    ph_words = []
+    for p in desc.phases:
+        bg = tuple(getattr(p, "barrier_guards", ()))
+        ph_words += [p.access_begin, p.access_count, int(p.barrier_after), len(guards), len(bg)]
+        guards += list(bg)
     for g in guards:
         w += list(g)
-    for p in desc.phases:
-        w += [p.access_begin, p.access_count, int(p.barrier_after)]
+    w += ph_words
     for s in desc.segments:
         w += [s.phase_begin, s.phase_count, s.repeat, s.k_base]
     w[7] = len(guards)
@@ -152,15 +174,21 @@ class Result:
     witnesses: List[Witness]
 
 
-def check(desc, max_witnesses: int = 1 << 16, ilo: int = 0, ihi: Optional[int] = None) -> Result:
-    """Run the oracle on intervals [ilo, ihi) (default: all)."""
+def check(desc, max_witnesses: int = 1 << 16, ilo: int = 0, ihi: Optional[int] = None,
+          strict: bool = False) -> Result:
+    """Run the oracle on intervals [ilo, ihi) (default: all).  ``strict``:
+    blocks are never ordered (global records of different blocks conflict
+    across intervals); the whole kernel is checked and ilo/ihi are ignored."""
     lib = _load()
     words = serialize(desc)
     res = OrcResult()
     buf = (OrcWitness * max(1, max_witnesses))()
     hi = (1 << 62) if ihi is None else ihi
-    lib.orc_check(words.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(words), ilo, hi,
-                  ctypes.byref(res), buf, max_witnesses)
+    wp = words.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    if strict:
+        lib.orc_check_strict(wp, len(words), ctypes.byref(res), buf, max_witnesses)
+    else:
+        lib.orc_check(wp, len(words), ilo, hi, ctypes.byref(res), buf, max_witnesses)
     ws = []
     for i in range(res.n_witness):
         b = buf[i]
@@ -198,3 +226,44 @@ def n_intervals(desc) -> int:
     if st:
         raise ValueError(f"oracle status {st}")
     return n.value
+
+
+@dataclass
+class Deps:
+    status: int
+    n_records: int
+    n_raw: int
+    n_waw: int
+    n_war: int
+    n_dep_locations: int
+
+
+def ordered(desc) -> Deps:
+    """RaW / WaW / WaR counts of the kernel run on its sequential schedule
+    (dynamic phase, global thread, loop index); see rv_oracle.c step 8."""
+    lib = _load()
+    words = serialize(desc)
+    out = OrcDeps()
+    lib.orc_ordered(words.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(words), ctypes.byref(out))
+    return Deps(out.status, out.n_records, out.n_raw, out.n_waw, out.n_war, out.n_dep_locations)
+
+
+@dataclass
+class Divergence:
+    status: int
+    n_instances: int
+    n_divergent: int
+    dphase: int
+    block: int
+    warp: int
+    arrive_tid: int
+    skip_tid: int
+
+
+def divergence(desc) -> Divergence:
+    """Barrier instances reached by part of their scope (rv_oracle.c step 9)."""
+    lib = _load()
+    words = serialize(desc)
+    out = OrcDiv()
+    lib.orc_divergence(words.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(words), ctypes.byref(out))
+    return Divergence(*(getattr(out, n) for n, _ in OrcDiv._fields_))

@@ -79,10 +79,27 @@ rv_status validate(const rv_kernel_desc *d, std::string &msg) {
             msg = fmt("access %lld: bad guard range", i); return RV_ERR_INVALID;
         }
     }
+    if (d->warp_size < 0) { msg = "warp_size must be >= 0 (0: 32)"; return RV_ERR_INVALID; }
     for (int i = 0; i < d->n_phases; i++) {
         const rv_phase &p = d->phases[i];
         if (p.access_begin < 0 || p.access_count < 0 || (int64_t)p.access_begin + p.access_count > d->n_accesses) {
             msg = fmt("phase %lld: bad access range", i); return RV_ERR_INVALID;
+        }
+        if (p.barrier_after < RV_BARRIER_NONE || p.barrier_after > RV_BARRIER_WARP) {
+            msg = fmt("phase %lld: bad barrier kind", i); return RV_ERR_INVALID;
+        }
+        if (p.guard_begin < 0 || p.guard_count < 0 || (int64_t)p.guard_begin + p.guard_count > d->n_guards ||
+            (p.guard_count && p.barrier_after == RV_BARRIER_NONE)) {
+            msg = fmt("phase %lld: bad barrier guard range", i); return RV_ERR_INVALID;
+        }
+        for (int g = p.guard_begin; g < p.guard_begin + p.guard_count; g++)
+            for (int v = RV_V_L0; v < RV_NV; v++)
+                if (d->guards[g].g.coef[v]) {
+                    msg = fmt("phase %lld: a barrier guard may use tx, ty, bx, by and k only", i);
+                    return RV_ERR_INVALID;
+                }
+        if (p.barrier_after == RV_BARRIER_WARP) {
+            msg = fmt("phase %lld: warp barriers are not supported yet", i); return RV_ERR_UNSUPPORTED;
         }
     }
     for (int i = 0; i < d->n_segments; i++) {
@@ -142,7 +159,7 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 k.dyn_phase.push_back(ph);
                 k.dyn_k.push_back(s.k_base + r);
                 k.dyn_interval.push_back(barriers);
-                if (k.phases[ph].barrier_after) barriers++;
+                if (k.phases[ph].barrier_after == RV_BARRIER_BLOCK) barriers++;
             }
     k.n_intervals = k.dyn_phase.empty() ? 0 : k.dyn_interval.back() + 1;
 

@@ -63,7 +63,8 @@ class rv_guard(ctypes.Structure):
 
 
 class rv_phase(ctypes.Structure):
-    _fields_ = [("access_begin", i32), ("access_count", i32), ("barrier_after", i32)]
+    _fields_ = [("access_begin", i32), ("access_count", i32), ("barrier_after", i32),
+                ("guard_begin", i32), ("guard_count", i32)]
 
 
 class rv_segment(ctypes.Structure):
@@ -76,7 +77,8 @@ class rv_kernel_desc(ctypes.Structure):
                 ("accesses", ctypes.POINTER(rv_access)), ("n_accesses", i32),
                 ("guards", ctypes.POINTER(rv_guard)), ("n_guards", i32),
                 ("phases", ctypes.POINTER(rv_phase)), ("n_phases", i32),
-                ("segments", ctypes.POINTER(rv_segment)), ("n_segments", i32)]
+                ("segments", ctypes.POINTER(rv_segment)), ("n_segments", i32),
+                ("warp_size", i32)]
 
 
 class rv_side(ctypes.Structure):
@@ -220,14 +222,18 @@ class Marshalled:
             c.guard_begin = len(guards_list)
             c.guard_count = len(ac.guards)
             guards_list.extend(ac.guards)
-        guards = (rv_guard * max(1, len(guards_list)))()
-        for i, g in enumerate(guards_list):
-            _affine(g, guards[i].g)
         phases = (rv_phase * max(1, len(desc.phases)))()
         for i, p in enumerate(desc.phases):
             phases[i].access_begin = int(p.access_begin)
             phases[i].access_count = int(p.access_count)
-            phases[i].barrier_after = int(bool(p.barrier_after))
+            phases[i].barrier_after = int(p.barrier_after)
+            bg = tuple(getattr(p, "barrier_guards", ()))
+            phases[i].guard_begin = len(guards_list)
+            phases[i].guard_count = len(bg)
+            guards_list.extend(bg)
+        guards = (rv_guard * max(1, len(guards_list)))()
+        for i, g in enumerate(guards_list):
+            _affine(g, guards[i].g)
         segs = (rv_segment * max(1, len(desc.segments)))()
         for i, s in enumerate(desc.segments):
             segs[i].phase_begin = int(s.phase_begin)
@@ -242,6 +248,7 @@ class Marshalled:
         d.guards, d.n_guards = guards, len(guards_list)
         d.phases, d.n_phases = phases, len(desc.phases)
         d.segments, d.n_segments = segs, len(desc.segments)
+        d.warp_size = int(getattr(desc, "warp_size", 32))
         self._keep = (arrays, accesses, guards, phases, segs)
         self.desc = d
 

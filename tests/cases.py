@@ -61,6 +61,24 @@ def rand_small(rng, i):
         b.segment(pids[1:], repeat=int(rng.integers(1, 3)))
     return b.build()
 
+def rand_scoped(rng, i):
+    """``rand_small`` kernels with barrier scopes: each phase ends with no
+    barrier, a block barrier or a warp barrier, barriers may carry guards
+    (affine in tx, ty, bx, by, k) and warps hold 1-4 threads (or 32), so
+    small blocks span several warps."""
+    import dataclasses
+    d = rand_small(rng, i)
+    phases = []
+    for ph in d.phases:
+        kind = int(rng.choice([0, 1, 2, 2]))
+        guards = ()
+        if kind and rng.random() < 0.4:
+            guards = (aff(int(rng.integers(-1, 4)), tx=int(rng.integers(-2, 3)), ty=int(rng.integers(-1, 2)),
+                          bx=int(rng.integers(-1, 2)), k=int(rng.integers(-1, 2))),)
+        phases.append(dataclasses.replace(ph, barrier_after=kind, barrier_guards=guards))
+    return d.replace(phases=phases, warp_size=int(rng.choice([1, 2, 3, 4, 32])), name=f"rand-scoped-{i}")
+
+
 def rand_medium(rng, i, oob_rate=0.01):
     """Random kernels of a few thousand to a few hundred thousand records,
     spanning several expansion tiles and location buckets: 2-D launches up

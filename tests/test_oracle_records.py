@@ -30,7 +30,7 @@ def _brute_records(desc):
     """Per interval: the simulated records as rows of oracle.RECORD_COLUMNS."""
     out = {}
     for r in simulate(desc):
-        interval, space, blk, array, address, (thread, dyn, acc, li), _thr, is_write, loops = r
+        interval, space, blk, array, address, (thread, dyn, acc, li), _thr, is_write, loops, _fine = r
         out.setdefault(interval, []).append(
             (interval, space, blk, array, address, thread, dyn, acc, li) + tuple(loops) + (is_write,))
     return out

@@ -13,8 +13,15 @@ and writes; Section 2.1, the Domain / Read / Write / Schedule sets):
                    affine forms that must be ``>= 0`` (a conjunction).  Two
                    auxiliary variables may hold ``floor(e / d)`` or the
                    Euclidean ``e mod d`` of an affine ``e``.
-* ``phases``    -- runs of accesses; ``barrier_after`` marks a block-wide
-                   barrier at the end of the phase.
+* ``phases``    -- runs of accesses; ``barrier_after`` ends the phase with a
+                   barrier: ``BARRIER_BLOCK`` (all threads of the block,
+                   ``__syncthreads``) or ``BARRIER_WARP`` (the threads of one
+                   warp, ``__syncwarp``; warps are ``warp_size`` consecutive
+                   linear thread ids of a block).  ``barrier_guards`` (affine
+                   forms over tx, ty, bx, by, k that must be ``>= 0``) say which
+                   threads reach the barrier; the race check treats every
+                   barrier as reached by all threads, the divergence check
+                   reports barriers that only part of their scope reaches.
 * ``segments``  -- runs of phases repeated ``repeat`` times; the variable
                    ``k`` holds ``k_base + r`` in repetition ``r``.
 
@@ -36,6 +43,7 @@ V_TX, V_TY, V_BX, V_BY, V_K, V_L0, V_L1, V_L2, V_AUX0, V_AUX1 = range(NV)
 
 SHARED, GLOBAL = 0, 1
 AUX_NONE, AUX_FLOORDIV, AUX_EMOD = 0, 1, 2
+BARRIER_NONE, BARRIER_BLOCK, BARRIER_WARP = 0, 1, 2
 
 
 def aff(c0: int = 0, **terms: int) -> Tuple[int, ...]:
@@ -84,7 +92,8 @@ class Access:
 class Phase:
     access_begin: int
     access_count: int
-    barrier_after: bool
+    barrier_after: int                           # BARRIER_NONE / BARRIER_BLOCK / BARRIER_WARP (True = block)
+    barrier_guards: Tuple[Tuple[int, ...], ...] = ()   # who reaches the barrier: each affine >= 0
 
 
 @dataclass(frozen=True)
@@ -104,6 +113,7 @@ class KernelDesc:
     phases: List[Phase]
     segments: List[Segment]
     name: str = ""
+    warp_size: int = 32                          # threads per warp (CUDA: 32)
 
     # ------------------------------------------------------------ sizes
     @property
@@ -131,10 +141,11 @@ class Builder:
     """Convenience builder: phases are appended in order and a segment covers
     a contiguous run of phases."""
 
-    def __init__(self, block, grid, name=""):
+    def __init__(self, block, grid, name="", warp_size=32):
         self.block = tuple(block)
         self.grid = tuple(grid)
         self.name = name
+        self.warp_size = int(warp_size)
         self.arrays: List[Array] = []
         self.accesses: List[Access] = []
         self.phases: List[Phase] = []
@@ -145,17 +156,18 @@ class Builder:
         self.arrays.append(Array(space, tuple(int(d) for d in dims), name))
         return len(self.arrays) - 1
 
-    def phase(self, accesses: Sequence[Access], barrier_after: bool) -> int:
+    def phase(self, accesses: Sequence[Access], barrier_after, barrier_guards=()) -> int:
+        """``barrier_after``: False / True (block barrier) or a BARRIER_* kind."""
         begin = len(self.accesses)
         self.accesses.extend(accesses)
-        self.phases.append(Phase(begin, len(accesses), bool(barrier_after)))
+        self.phases.append(Phase(begin, len(accesses), int(barrier_after), tuple(barrier_guards)))
         return len(self.phases) - 1
 
-    def phase_like(self, phase_id: int, barrier_after: bool) -> int:
+    def phase_like(self, phase_id: int, barrier_after) -> int:
         """A new phase over the same accesses as ``phase_id`` (used to peel
         one iteration of a repeated segment with a different barrier flag)."""
         src = self.phases[phase_id]
-        self.phases.append(Phase(src.access_begin, src.access_count, bool(barrier_after)))
+        self.phases.append(Phase(src.access_begin, src.access_count, int(barrier_after), src.barrier_guards))
         return len(self.phases) - 1
 
     def segment(self, phase_ids: Sequence[int], repeat=1, k_base=0):
@@ -166,7 +178,7 @@ class Builder:
 
     def build(self) -> KernelDesc:
         return KernelDesc(self.block, self.grid, list(self.arrays), list(self.accesses),
-                          list(self.phases), list(self.segments), self.name)
+                          list(self.phases), list(self.segments), self.name, self.warp_size)
 
 
 def rw(array: int, is_write: bool, *idx, loops=(), aux=(Aux(), Aux()), guards=(), name=""):

@@ -19,14 +19,24 @@ only lay out data; none of them computes records, locations or conflicts.
                                (Section 2.1.2), as a looped SIMT kernel.
 * ``stride1_*`` / ``half_index_*`` -- the two textbook patterns: stride-1
                                writes and ``a[tid / 2]`` writes.
+* ``polynomial_product_full`` -- the same example with its zeroing statement
+                               ``S: C[k] = 0`` as a phase of its own.
+* ``warp_reduction``        -- per-warp tree reduction ordered by warp barriers
+                               (coarse-grained warp merging), optionally with
+                               one warp barrier dropped.
+* ``warp_exchange``         -- a warp barrier (or a block barrier) between
+                               writes and reads that cross warps.
+* ``cross_block_global``    -- global elements written by block 0 and read by
+                               every block after a barrier.
+* ``guarded_barrier``       -- barriers reached by part of a block or warp.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
-from .desc import (AUX_EMOD, AUX_FLOORDIV, GLOBAL, SHARED, Aux, Builder, KernelDesc,
-                   Phase, Segment, aff, aff_from, rw)
+from .desc import (AUX_EMOD, AUX_FLOORDIV, BARRIER_BLOCK, BARRIER_WARP, GLOBAL, SHARED, Aux, Builder,
+                   KernelDesc, Phase, Segment, aff, aff_from, rw)
 
 
 # --------------------------------------------------------------------- tiny
@@ -176,6 +186,108 @@ def polynomial_product(n: int = 64) -> KernelDesc:
         rw(C, True, aff(tx=1, l0=1), loops=loop, name="W C[i+j]"),
     ], barrier_after=False)
     b.segment([p])
+    return b.build()
+
+
+def polynomial_product_full(n: int = 64) -> KernelDesc:
+    """Section 2.1's example with both statements: S (``C[k] = 0`` for k in
+    [0, 2n-1)) is phase 0, run by thread 0 (its loop is ``l0``); T is
+    ``polynomial_product``'s phase.  No barrier: the phases are the code
+    sections of the sequential schedule (S before T)."""
+    b = Builder((n, 1), (1, 1), f"polynomial-product-full-{n}")
+    A = b.array(GLOBAL, (n,), "A")
+    B = b.array(GLOBAL, (n,), "B")
+    C = b.array(GLOBAL, (2 * n - 1,), "C")
+    s = b.phase([rw(C, True, aff(l0=1), loops=((0, 2 * n - 1),), guards=(aff(tx=-1),), name="W C[k]")],
+                barrier_after=False)
+    loop = ((0, n),)
+    t = b.phase([
+        rw(C, False, aff(tx=1, l0=1), loops=loop, name="R C[i+j]"),
+        rw(A, False, aff(tx=1), loops=loop, name="R A[i]"),
+        rw(B, False, aff(l0=1), loops=loop, name="R B[j]"),
+        rw(C, True, aff(tx=1, l0=1), loops=loop, name="W C[i+j]"),
+    ], barrier_after=False)
+    b.segment([s, t])
+    return b.build()
+
+
+def warp_reduction(dropped: int = -1, block: int = 64, grid: int = 2, warp: int = 32) -> KernelDesc:
+    """Coarse-grained warp merging: each warp reduces its own slice of a
+    shared array with warp barriers only.  Phase k (h = warp/2 >> k): lanes
+    ``lane < h`` (lane = tid mod warp) read s[tid] and s[tid + h] and write
+    s[tid]; a warp barrier follows every phase except ``dropped``."""
+    levels = warp.bit_length() - 1
+    b = Builder((block, 1), (grid, 1), f"warp-reduction-w{warp}" + ("" if dropped < 0 else f"-drop{dropped}"),
+                warp_size=warp)
+    s = b.array(SHARED, (block,), "s")
+    lane = (Aux(AUX_EMOD, warp, aff(tx=1)), Aux())
+    pids = []
+    for k in range(levels):
+        h = (warp // 2) >> k
+        g = aff(h - 1, aux0=-1)                               # lane < h
+        pids.append(b.phase([
+            rw(s, False, aff(tx=1), aux=lane, guards=(g,), name="R s[tid]"),
+            rw(s, False, aff(h, tx=1), aux=lane, guards=(g,), name="R s[tid+h]"),
+            rw(s, True, aff(tx=1), aux=lane, guards=(g,), name="W s[tid]"),
+        ], barrier_after=0 if k == dropped else BARRIER_WARP))
+    b.segment(pids)
+    return b.build()
+
+
+def warp_exchange(kind: int = BARRIER_WARP, block: int = 64, grid: int = 2, warp: int = 32) -> KernelDesc:
+    """s[tid] written, then a barrier of ``kind``, then s[block-1-tid] read:
+    every element is read by a thread of the other half of the block."""
+    b = Builder((block, 1), (grid, 1), f"warp-exchange-{'warp' if kind == BARRIER_WARP else 'block'}-w{warp}",
+                warp_size=warp)
+    s = b.array(SHARED, (block,), "s")
+    p0 = b.phase([rw(s, True, aff(tx=1), name="W s[tid]")], barrier_after=kind)
+    p1 = b.phase([rw(s, False, aff(block - 1, tx=-1), name="R s[block-1-tid]")], barrier_after=False)
+    b.segment([p0, p1])
+    return b.build()
+
+
+def cross_block_global(block: int = 32, grid: int = 4) -> KernelDesc:
+    """Block 0 writes g[tid]; block barrier; every block reads g[tid]."""
+    b = Builder((block, 1), (grid, 1), "cross-block-global")
+    g = b.array(GLOBAL, (block,), "g")
+    p0 = b.phase([rw(g, True, aff(tx=1), guards=(aff(bx=-1),), name="W g[tid] (block 0)")], barrier_after=True)
+    p1 = b.phase([rw(g, False, aff(tx=1), name="R g[tid]")], barrier_after=False)
+    b.segment([p0, p1])
+    return b.build()
+
+
+def guarded_barrier(case: str) -> KernelDesc:
+    """Barriers that carry guards.  ``block-half``: blockDim 32, gridDim 3, a
+    block barrier reached by tid <= 15.  ``warp-tail``: blockDim 64 (two warps
+    of 32), gridDim 2, a warp barrier reached by tid <= 47.  ``block-uniform``:
+    gridDim 4, a block barrier reached by the blocks bx <= 1 (all their
+    threads).  ``k-uniform``: a barrier in a segment repeated 3 times,
+    reached while k <= 1."""
+    if case == "block-half":
+        b = Builder((32, 1), (3, 1), "guarded-barrier-block-half")
+        s = b.array(SHARED, (32,))
+        p0 = b.phase([rw(s, True, aff(tx=1))], barrier_after=BARRIER_BLOCK, barrier_guards=(aff(15, tx=-1),))
+        p1 = b.phase([rw(s, False, aff(31, tx=-1))], barrier_after=False)
+        b.segment([p0, p1])
+    elif case == "warp-tail":
+        b = Builder((64, 1), (2, 1), "guarded-barrier-warp-tail")
+        s = b.array(SHARED, (64,))
+        p0 = b.phase([rw(s, True, aff(tx=1))], barrier_after=BARRIER_WARP, barrier_guards=(aff(47, tx=-1),))
+        p1 = b.phase([rw(s, False, aff(tx=1))], barrier_after=False)
+        b.segment([p0, p1])
+    elif case == "block-uniform":
+        b = Builder((32, 1), (4, 1), "guarded-barrier-block-uniform")
+        s = b.array(SHARED, (32,))
+        p0 = b.phase([rw(s, True, aff(tx=1))], barrier_after=BARRIER_BLOCK, barrier_guards=(aff(1, bx=-1),))
+        p1 = b.phase([rw(s, False, aff(tx=1))], barrier_after=False)
+        b.segment([p0, p1])
+    elif case == "k-uniform":
+        b = Builder((16, 1), (2, 1), "guarded-barrier-k-uniform")
+        s = b.array(SHARED, (16,))
+        p0 = b.phase([rw(s, True, aff(tx=1))], barrier_after=BARRIER_BLOCK, barrier_guards=(aff(1, k=-1),))
+        b.segment([p0], repeat=3)
+    else:
+        raise ValueError(case)
     return b.build()
 
 
