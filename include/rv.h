@@ -263,6 +263,36 @@ const char *rv_last_error(const rv_ctx *ctx);
  * leave int32), RV_ERR_TOO_LARGE (an interval of >= 2^32 instances, or one
  * the context's workspace cannot hold), RV_ERR_DEVICE. */
 rv_status rv_load_kernel_desc(rv_ctx *ctx, const rv_kernel_desc *desc, rv_kernel **out);
+
+/* Which race a loaded kernel is checked for.
+ *  RV_SEM_INTERVAL (rv_load_kernel_desc): two records of one location
+ *    conflict when they come from different threads, one writes, and
+ *    nothing orders them: they are in the same barrier interval, and not in
+ *    the same warp on either side of a warp barrier.  Records of global
+ *    arrays from different blocks are compared within one interval index.
+ *  RV_SEM_STRICT: no barrier orders two blocks (Abstract; Section 1: a race
+ *    is one thread overwriting data another still uses), so records of a
+ *    global array from different blocks conflict across intervals; within
+ *    one block the intervals still order them.  Shared arrays are checked
+ *    per interval as above.  Witnesses of global locations follow every
+ *    shared one, in (array, address) order; their interval is the first
+ *    side's.  Kernels with warp barriers are RV_ERR_UNSUPPORTED here.
+ * The canonical witness of a conflicting location is that of rv_witness
+ * taken inside the smallest sub-interval (fine interval between warp
+ * barriers; interval, in strict mode for global arrays) holding a
+ * conflict; when only records of different units (warps; blocks) conflict,
+ * `second` is the smallest-id record if its unit differs from first's, else
+ * the largest-id record. */
+enum { RV_SEM_INTERVAL = 0, RV_SEM_STRICT = 1 };
+typedef struct {
+    int32_t semantics;       /* RV_SEM_* */
+    int32_t reserved[3];     /* 0 */
+} rv_load_options;
+/* rv_load_kernel_desc with options (NULL: the defaults).  Errors as
+ * rv_load_kernel_desc, and RV_ERR_UNSUPPORTED for a combination this build
+ * does not check, RV_ERR_INVALID for unknown options. */
+rv_status rv_load_kernel_desc_ex(rv_ctx *ctx, const rv_kernel_desc *desc, const rv_load_options *opt,
+                                 rv_kernel **out);
 rv_status rv_free_kernel(rv_ctx *ctx, rv_kernel *k);
 rv_status rv_kernel_get_info(rv_ctx *ctx, const rv_kernel *k, rv_kernel_info *out);
 
@@ -321,6 +351,29 @@ rv_status rv_get_witnesses(rv_ctx *ctx, rv_kernel *k, uint64_t first_index, rv_w
 #define RV_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 #define RV_STATIC_MAX_PASSES 8192
 rv_status rv_check_static(rv_ctx *ctx, rv_kernel *k, rv_result *out);
+
+/* Barrier divergence (Section 2, component (4): barriers; Section 1.1.4:
+ * warp-level synchronisation).  A barrier whose rv_phase carries guards is
+ * reached by the threads for which every guard is >= 0.  One instance of a
+ * block barrier is (dynamic phase, block); of a warp barrier, (dynamic
+ * phase, block, warp).  An instance is divergent when some but not all of
+ * its threads reach it (undefined behaviour in CUDA).  The race check
+ * itself treats every barrier as reached by all threads of its scope. */
+typedef struct {
+    uint64_t n_instances;    /* barrier instances of the kernel (guarded or not) */
+    uint64_t n_divergent;    /* divergent instances */
+    int32_t has_divergence;  /* the fields below describe the first divergent instance in
+                                (dynamic phase, block, warp) order */
+    uint32_t dyn_phase;      /* the phase the barrier ends */
+    uint32_t block;
+    int32_t warp;            /* -1 for a block barrier */
+    uint32_t arrive_tid;     /* its smallest thread (linear id in the block) that reaches the barrier */
+    uint32_t skip_tid;       /* its smallest thread that does not */
+} rv_barrier_result;
+/* Evaluate every guarded barrier of a loaded kernel on the GPU (one
+ * workgroup per barrier and block) and report divergence into *out (host).
+ * Blocks of more than 4096 threads: RV_ERR_UNSUPPORTED.  Errors as rv_check. */
+rv_status rv_check_barriers(rv_ctx *ctx, rv_kernel *k, rv_barrier_result *out);
 
 /* Records of one barrier interval as the expansion wrote them (sorted = 0)
  * or after the per-bucket sort (sorted = 1: location order; requires every

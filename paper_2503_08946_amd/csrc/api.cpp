@@ -35,6 +35,8 @@ struct Lane {
     size_t subs_cap = 0;
     DevWitness *d_win = nullptr;    // witness windows (rv_get_witnesses), grown on demand
     size_t win_cap = 0;
+    BarrierResult *d_bres = nullptr;   // per guarded barrier (rv_check_barriers), grown on demand
+    size_t bres_cap = 0;
     void *h_up = nullptr;       // pinned: pass tables going up
     size_t up_cap = 0;
     void *h_down = nullptr;     // pinned: results coming down
@@ -188,10 +190,12 @@ void lane_release(Lane &ln) {
     if (ln.d_res) (void)hipFree(ln.d_res);
     if (ln.d_subs) (void)hipFree(ln.d_subs);
     if (ln.d_win) (void)hipFree(ln.d_win);
+    if (ln.d_bres) (void)hipFree(ln.d_bres);
     if (ln.h_up) (void)hipHostFree(ln.h_up);
     if (ln.h_down) (void)hipHostFree(ln.h_down);
     if (ln.done) (void)hipEventDestroy(ln.done);
-    ln.d_res = nullptr; ln.d_subs = nullptr; ln.d_win = nullptr; ln.h_up = nullptr; ln.h_down = nullptr;
+    ln.d_res = nullptr; ln.d_subs = nullptr; ln.d_win = nullptr; ln.d_bres = nullptr; ln.h_up = nullptr;
+    ln.h_down = nullptr; ln.bres_cap = 0;
     ln.done = nullptr;
     ln.res_cap = ln.subs_cap = ln.win_cap = ln.up_cap = ln.down_cap = 0;
 }
@@ -214,31 +218,37 @@ void run_expand(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t
 }
 
 // Group by location and judge: LDS-table fold or LDS sort + segmented scan.
-void run_group(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t buckets) {
-    if (c->group == RV_GROUP_SORT_SCAN)
+// Passes with sub-keys are judged by the fold kernels, whose judge handles
+// a location's sub-intervals together.
+void run_group(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t buckets, bool subkeys) {
+    if (c->group == RV_GROUP_SORT_SCAN && !subkeys)
         launch_bucket(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), 0, c->ncu, ln.stream);
     else
         launch_fold(subs, nsub, buckets, ln.rec(), ln.starts(), ln.counts(), ln.conf(), ln.hot(), ln.d_res, c->ncu,
                     ln.stream);
 }
 
-void run_check_chunk(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets) {
+void run_check_chunk(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets,
+                     bool subkeys) {
     hipStream_t st = ln.stream;
     run_expand(c, ln, subs, nsub, items, buckets);
-    timed(c, ln, RV_STAGE_SORT_SCAN, [&] { run_group(c, ln, subs, nsub, buckets); });
+    timed(c, ln, RV_STAGE_SORT_SCAN, [&] { run_group(c, ln, subs, nsub, buckets, subkeys); });
     timed(c, ln, RV_STAGE_FINISH, [&] {
         launch_finish(subs, nsub, buckets, ln.conf(), ln.d_res, st);
         launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_res, st);
     });
 }
 
+// `interval` is the planned space of the pass (a barrier interval, or the
+// global space of strict semantics); the witness names the first side's
+// barrier interval.
 void decode_witness(const rv_kernel &k, uint32_t interval, const uint32_t w[4], rv_witness &out) {
     memset(&out, 0, sizeof out);
-    out.interval = interval;
     decode_location(k, interval, w[0], out.space, out.array, out.block, out.address);
     uint32_t g, l;
     decode_instance(k, interval, w[1], out.first, g, l);
     decode_instance(k, interval, w[2], out.second, g, l);
+    out.interval = k.dyn_interval[out.first.dyn_phase];
 }
 
 // Folds the passes' slots of one kernel, in pass order, into its result.
@@ -276,7 +286,8 @@ struct ResultAcc {
             snprintf(buf, sizeof buf,
                      "index out of bounds: interval %u, block %u, thread %u, dynamic phase %u, access %u, loop "
                      "(%d,%d,%d)",
-                     iv, s.block, s.tid, s.dyn_phase, s.access, s.loop[0], s.loop[1], s.loop[2]);
+                     k.dyn_interval[s.dyn_phase], s.block, s.tid, s.dyn_phase, s.access, s.loop[0], s.loop[1],
+                     s.loop[2]);
             msg = buf;
             return RV_ERR_OOB;
         }
@@ -323,14 +334,15 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
     if (resident) {
         const rv_kernel *k = ks[0];
         for (auto &ch : k->chunks)
-            run_check_chunk(c, ln, k->d_subs + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets);
+            run_check_chunk(c, ln, k->d_subs + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets,
+                            k->has_subkeys);
     } else {
         // passes in (kernel, pass) order, greedy chunks by capacity
-        struct Chunk { size_t sub_begin, sub_end; uint64_t items, buckets; };
+        struct Chunk { size_t sub_begin, sub_end; uint64_t items, buckets; bool subkeys; };
         std::vector<Chunk> chunks;
         std::vector<DevSub> table;
         table.reserve(ns);
-        Chunk cur{0, 0, 0, 0};
+        Chunk cur{0, 0, 0, 0, false};
         uint64_t rec_bound = 0;
         for (size_t j = 0; j < n; j++) {
             const rv_kernel &k = *ks[j];
@@ -341,9 +353,10 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
                     (rec_bound + I.P > ln.L.cap_records || cur.buckets + nb > ln.L.cap_buckets ||
                      cur.items + I.items >= (1ull << 31))) {
                     chunks.push_back(cur);
-                    cur = Chunk{table.size(), table.size(), 0, 0};
+                    cur = Chunk{table.size(), table.size(), 0, 0, false};
                     rec_bound = 0;
                 }
+                cur.subkeys = cur.subkeys || k.has_subkeys;
                 DevSub D = k.h_subs[i];     // the pass as loaded; begins and slot re-based here
                 D.item_begin = (uint32_t)cur.items;
                 D.bucket_begin = (uint32_t)cur.buckets;
@@ -366,7 +379,7 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
         }
         for (auto &ch : chunks)
             run_check_chunk(c, ln, ln.d_subs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items,
-                            ch.buckets);
+                            ch.buckets, ch.subkeys);
     }
     if ((st = check_launch(ln))) return st;
     if (ns) HIP_TRY_L(ln, hipMemcpyAsync(ln.h_down, ln.d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, s));
@@ -586,13 +599,14 @@ const WorkspaceLayout &static_layout() {
     return L;
 }
 
-rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kernel **out) {
+rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kernel **out,
+                      int semantics = RV_SEM_INTERVAL) {
     rv_kernel *k = new (std::nothrow) rv_kernel;
     if (!k) return fail(c, RV_ERR_TOO_LARGE, "out of host memory");
     std::string m;
     rv_status st;
     try {
-        st = plan_kernel(desc, target, *k, m);
+        st = plan_kernel(desc, target, *k, m, semantics);
         if (!st) st = plan_chunks(*k, c->main.L, m);
     } catch (const std::bad_alloc &) {
         st = RV_ERR_TOO_LARGE;
@@ -629,7 +643,8 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     const size_t o_ei = al(o_gr + k->guard_rows.size() * sizeof(int32_t));
     const size_t o_sb = al(o_ei + k->entry_items.size() * sizeof(uint32_t));
     const size_t o_ss = al(o_sb + k->subs.size() * sizeof(DevSub));
-    const size_t total = al(o_ss + (k->static_ok ? k->subs.size() : 0) * sizeof(DevSub) + 1);
+    const size_t o_br = al(o_ss + (k->static_ok ? k->subs.size() : 0) * sizeof(DevSub));
+    const size_t total = al(o_br + k->barriers.size() * sizeof(DevBarrier) + 1);
     hipError_t e = hipMalloc(&k->d_mem, total);
     if (e != hipSuccess) { delete k; return fail(c, RV_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e)); }
     char *base = reinterpret_cast<char *>(k->d_mem);
@@ -639,6 +654,7 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     k->d_entry_items = reinterpret_cast<uint32_t *>(base + o_ei);
     k->d_subs = reinterpret_cast<DevSub *>(base + o_sb);
     k->d_subs_static = k->static_ok ? reinterpret_cast<DevSub *>(base + o_ss) : nullptr;
+    k->d_barriers = reinterpret_cast<DevBarrier *>(base + o_br);
     k->h_subs.clear();
     for (auto &ch : k->chunks) {
         uint64_t items = 0, buckets = 0;
@@ -658,6 +674,8 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     if (!k->entry_items.empty()) memcpy(host.data() + o_ei, k->entry_items.data(), k->entry_items.size() * 4);
     if (!k->h_subs.empty()) memcpy(host.data() + o_sb, k->h_subs.data(), k->h_subs.size() * sizeof(DevSub));
     if (!h_static.empty()) memcpy(host.data() + o_ss, h_static.data(), h_static.size() * sizeof(DevSub));
+    if (!k->barriers.empty())
+        memcpy(host.data() + o_br, k->barriers.data(), k->barriers.size() * sizeof(DevBarrier));
     e = hipMemcpy(k->d_mem, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(k->d_mem);
@@ -699,6 +717,16 @@ rv_status rv_load_kernel_desc(rv_ctx *c, const rv_kernel_desc *desc, rv_kernel *
     if (!c || !out) return RV_ERR_INVALID;
     c->err.clear();
     return load_kernel(c, desc, c->target, out);
+}
+
+rv_status rv_load_kernel_desc_ex(rv_ctx *c, const rv_kernel_desc *desc, const rv_load_options *opt,
+                                 rv_kernel **out) {
+    if (!c || !out) return RV_ERR_INVALID;
+    c->err.clear();
+    rv_load_options o{};
+    if (opt) o = *opt;
+    if (o.reserved[0] || o.reserved[1] || o.reserved[2]) return fail(c, RV_ERR_INVALID, "reserved options must be 0");
+    return load_kernel(c, desc, c->target, out, o.semantics);
 }
 
 rv_status rv_free_kernel(rv_ctx *c, rv_kernel *k) {
@@ -788,7 +816,8 @@ rv_status rv_check_static(rv_ctx *c, rv_kernel *k, rv_result *out) {
     const size_t ns = k->subs.size();
     launch_init_results(ln.d_res, ns, ln.stream);
     for (auto &ch : k->chunks_static)
-        run_check_chunk(c, ln, k->d_subs_static + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets);
+        run_check_chunk(c, ln, k->d_subs_static + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets,
+                        k->has_subkeys);
     rv_status st = check_launch(ln);
     if (st) return fail(c, st, ln.err);
     // results come down through a fixed host buffer, a piece at a time
@@ -804,6 +833,45 @@ rv_status rv_check_static(rv_ctx *c, rv_kernel *k, rv_result *out) {
     std::string m;
     st = acc.finish(*k, out, m);
     return st ? fail(c, st, m) : RV_OK;
+}
+
+rv_status rv_check_barriers(rv_ctx *c, rv_kernel *k, rv_barrier_result *out) {
+    if (!c || !k || !out) return RV_ERR_INVALID;
+    if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
+    c->err.clear();
+    rv_barrier_result r;
+    memset(&r, 0, sizeof r);
+    r.n_instances = k->barrier_instances;
+    const uint32_t n = (uint32_t)k->barriers.size();
+    if (n) {
+        if (k->kc.tpb > BARRIER_MAX_TPB)
+            return fail(c, RV_ERR_UNSUPPORTED, "the divergence check handles blocks of at most 4096 threads");
+        HIP_TRY(c, hipSetDevice(c->device));
+        Lane &ln = c->main;
+        rv_status st = grow_device(ln, ln.d_bres, ln.bres_cap, n);
+        if (st) return main_fail(c, st);
+        launch_barriers(k->d_barriers, n, k->d_kc, k->d_guards, k->kc.nblocks, ln.d_bres, c->ncu, ln.stream);
+        if ((st = check_launch(ln))) return main_fail(c, st);
+        std::vector<BarrierResult> h(n);
+        HIP_TRY(c, hipMemcpyAsync(h.data(), ln.d_bres, n * sizeof(BarrierResult), hipMemcpyDeviceToHost, ln.stream));
+        HIP_TRY(c, hipStreamSynchronize(ln.stream));
+        for (uint32_t g = 0; g < n; g++) {       // guarded barriers are in dynamic-phase order
+            r.n_divergent += h[g].divergent;
+            if (h[g].divergent && !r.has_divergence) {
+                const DevBarrier &B = k->barriers[g];
+                r.has_divergence = 1;
+                r.dyn_phase = B.dphase;
+                r.block = (uint32_t)(h[g].first / B.nscope);
+                r.warp = k->phases[k->dyn_phase[B.dphase]].barrier_after == RV_BARRIER_BLOCK
+                             ? -1 : (int32_t)(h[g].first % B.nscope);
+                r.arrive_tid = h[g].arrive;
+                r.skip_tid = h[g].skip;
+            }
+        }
+    }
+    *out = r;
+    return RV_OK;
 }
 
 rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_witness *out, size_t cap,
@@ -836,7 +904,7 @@ rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_wit
         const DevSub *subs = k->d_subs + ch.sub_begin;
         const uint32_t nsub = ch.sub_end - ch.sub_begin;
         run_expand(c, ln, subs, nsub, ch.items, ch.buckets);
-        run_group(c, ln, subs, nsub, ch.buckets);
+        run_group(c, ln, subs, nsub, ch.buckets, k->has_subkeys);
         launch_finish(subs, nsub, ch.buckets, ln.conf(), ln.d_res, s);
         // exclusive scan of per-bucket conflict counts -> list positions (cursor area)
         launch_scan(ln.conf(), ln.cursor(), nullptr, ln.bsum(), ch.buckets, s);
@@ -876,7 +944,7 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
     if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
     c->err.clear();
     *n_out = 0;
-    if (interval >= k->n_intervals) return fail(c, RV_ERR_INVALID, "no such interval");
+    if (interval >= k->intervals.size()) return fail(c, RV_ERR_INVALID, "no such interval");
     HIP_TRY(c, hipSetDevice(c->device));
     Lane &ln = c->main;
     uint32_t sb = 0;
@@ -919,10 +987,10 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
         const uint32_t hiw = (uint32_t)(recs[i] >> 32), id = (uint32_t)recs[i];
         rv_record &o = out[i];
         memset(&o, 0, sizeof o);
-        o.interval = interval;
         decode_location(*k, interval, hiw >> 1, o.space, o.array, o.block, o.address);
         rv_side sd;
         decode_instance(*k, interval, id, sd, o.gthread, o.lidx);
+        o.interval = k->dyn_interval[sd.dyn_phase];
         o.dyn_phase = sd.dyn_phase;
         o.access = sd.access;
         o.loop[0] = sd.loop[0]; o.loop[1] = sd.loop[1]; o.loop[2] = sd.loop[2];

@@ -34,6 +34,7 @@
 // same XCD (workgroups are dealt round-robin over the 8 XCDs), so the bucket
 // counters and partially written lines they share stay in one L2.
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -312,7 +313,7 @@ __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, 
                         E.row[r][C_A0] * a0 + E.row[r][C_A1] * a1;
             inb = (uint32_t)ix[0] < E.dim[0] && (uint32_t)ix[1] < E.dim[1] && (uint32_t)ix[2] < E.dim[2];
             const uint32_t flat = ((uint32_t)ix[0] * E.dim[1] + (uint32_t)ix[1]) * E.dim[2] + (uint32_t)ix[2];
-            loc = locbase + flat;
+            loc = locbase + (flat << E.wshift);
             id = idbase + li;
         }
         f(s, ok, inb, loc, id);
@@ -1556,14 +1557,84 @@ __device__ __forceinline__ uint32_t sub_of_bucket(CSub *subs, uint32_t nsub, uin
     return lo_s;
 }
 
+// Unordered unit of an instance id: its thread's warp, or its block (upb = 1,
+// unit size = threads per block).
+__device__ __forceinline__ uint32_t unit_of(uint32_t id, Magic mgM, Magic mg_tpb, uint32_t tpb, Magic mg_unit,
+                                            uint32_t upb) {
+    const uint32_t th = udiv(id, mgM);
+    const uint32_t blk = udiv(th, mg_tpb);
+    return blk * upb + udiv(th - blk * tpb, mg_unit);
+}
+
+// Conflict across units of a location's combined summary (no sub-interval
+// holds a conflict of its own): ids are thread-major and units are
+// monotone in the thread, so the units of the smallest and largest ids
+// differ iff the location spans two units; with a write, one of those two
+// records lies in a unit other than the first write's.
+__device__ __forceinline__ bool judge_units(const Seg &s, Magic mgM, Magic mg_tpb, uint32_t tpb, Magic mg_unit,
+                                            uint32_t upb, uint32_t &second, uint32_t &srw) {
+    if (s.mxw1 == 0u) return false;
+    const uint32_t u_mn = unit_of(s.mn, mgM, mg_tpb, tpb, mg_unit, upb);
+    const uint32_t u_mx = unit_of(s.mx, mgM, mg_tpb, tpb, mg_unit, upb);
+    if (u_mn == u_mx) return false;
+    const uint32_t u_w = unit_of(s.mnw, mgM, mg_tpb, tpb, mg_unit, upb);
+    if (u_mn != u_w) { second = s.mn; srw = (s.mn == s.mnw) ? 1u : 0u; }
+    else { second = s.mx; srw = (s.mx + 1 == s.mxw1) ? 1u : 0u; }
+    return true;
+}
+
+// judge_tables for a pass with sub-keys: a location is 2^wshift consecutive
+// table entries, one per sub-interval (fine interval between warp barriers,
+// or barrier interval).  Thread t judges location t: the smallest
+// sub-interval with a conflict gives the witness; if there is none, the
+// location's combined summary is judged across units.
+template <bool RESET>
+__device__ __noinline__ uint32_t judge_tables_sub(uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
+                                                  uint32_t width, uint32_t lo, CSub &S, uint32_t *wout,
+                                                  uint32_t *red) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t w = S.wshift, G = 1u << w, nloc = width >> w;     // nloc <= TBL / 2 = BKT_WG
+    const Magic mgM = ldm(S.mgM), mg_unit = ldm(S.mg_unit);
+    CKer &K = *cptr(S.kc);
+    const Magic mg_tpb = ldm(K.mg_tpb);
+    bool c = false;
+    Seg e{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+    uint32_t second = 0, srw = 0, key = 0;
+    if (t < nloc) {
+        Seg comb{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+        for (uint32_t j = 0; j < G; j++) {
+            const uint32_t k = t * G + j;
+            const Seg x{0u, t_mn[k], t_mx[k], t_mnw[k], t_mxw1[k]};
+            if (x.mn == 0xFFFFFFFFu) continue;
+            if (RESET) { t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0; }
+            uint32_t sc, sr;
+            if (!c && judge(x, mgM, sc, sr)) { c = true; e = x; second = sc; srw = sr; key = lo + k; }
+            comb.mn = min(comb.mn, x.mn);
+            comb.mx = max(comb.mx, x.mx);
+            comb.mnw = min(comb.mnw, x.mnw);
+            comb.mxw1 = max(comb.mxw1, x.mxw1);
+        }
+        if (!c && comb.mn != 0xFFFFFFFFu &&
+            judge_units(comb, mgM, mg_tpb, K.tpb, mg_unit, S.upb, second, srw)) {
+            c = true; e = comb; key = lo + t * G;
+        }
+    }
+    uint32_t total;
+    const uint32_t pos = block_excl_add<BKT_WG>(c ? 1u : 0u, red, &total);   // also orders the reads
+    if (c) put_witness(wout, pos, key, e, second, srw);                     // before the next clear
+    return total;
+}
+
 // Judge every location of a folded bucket and write its witnesses in
 // location order at the start of the bucket's region; returns the count.
 // With RESET, each entry read is set back to the empty summary, so the
 // tables are ready for the next bucket once the judge's barriers are passed.
 template <bool RESET = false>
 __device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
-                                                 uint32_t width, uint32_t lo, Magic mgM, uint32_t *wout,
+                                                 uint32_t width, uint32_t lo, CSub &S, uint32_t *wout,
                                                  uint32_t *red) {
+    if (S.wshift) return judge_tables_sub<RESET>(t_mn, t_mx, t_mnw, t_mxw1, width, lo, S, wout, red);
+    const Magic mgM = ldm(S.mgM);
     constexpr int TP = TBL / BKT_WG;
     const uint32_t t = threadIdx.x;
     bool c[TP];
@@ -1673,7 +1744,7 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
             // reset entry by entry by the previous bucket's judge
             run_fold(cur, lo, t_mn, t_mx, t_mnw, t_mxw1);
             __syncthreads();
-            const uint32_t total = judge_tables<true>(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
+            const uint32_t total = judge_tables<true>(t_mn, t_mx, t_mnw, t_mxw1, width, lo, S,
                                                       reinterpret_cast<uint32_t *>(rec + start), red);
             if (t == 0) conf[b] = total;
         };
@@ -1720,7 +1791,7 @@ __global__ void __launch_bounds__(BKT_WG) k_mid(const DevSub *subs_g, uint32_t n
         __syncthreads();
         fold_records<BKT_WG>(rec + start, 0, cnt, lo, t, t_mn, t_mx, t_mnw, t_mxw1);
         __syncthreads();
-        const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
+        const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, S,
                                             reinterpret_cast<uint32_t *>(rec + start), red);
         if (t == 0) conf[b] = total;
     }
@@ -1811,7 +1882,7 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
                     t_mxw1[k] = __hip_atomic_load(&g[3 * TBL + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 __syncthreads();
-                const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, ldm(S.mgM),
+                const uint32_t total = judge_tables(t_mn, t_mx, t_mnw, t_mxw1, width, lo, S,
                                                     reinterpret_cast<uint32_t *>(rec + start), red);
                 if (t == 0) conf[bk] = total;
             }
@@ -1877,6 +1948,84 @@ __global__ void k_gather(const DevSub *subs_g, uint32_t nsub, const unsigned lon
             d.sub = sub; d.pad[0] = d.pad[1] = d.pad[2] = 0;
             out[g - lo] = d;
         }
+    }
+}
+
+// ------------------------------------------------------ barrier divergence
+// One workgroup per (guarded barrier, block) item, dealt out cyclically: the
+// threads of the block evaluate the barrier's guards into an LDS byte map,
+// then each scope (the block, or one warp) is scanned for a thread that
+// reaches the barrier and one that does not.  A scope with both is a
+// divergent instance: counted, and the smallest (block, scope) kept.
+__global__ void __launch_bounds__(256) k_barriers(const DevBarrier *__restrict__ bars, uint32_t nbar,
+                                                  const DevKernel *__restrict__ kc_g,
+                                                  const int32_t *__restrict__ guards, uint32_t nblocks,
+                                                  BarrierResult *__restrict__ res) {
+    __shared__ uint8_t reach[BARRIER_MAX_TPB];
+    const DevKernel K = *kc_g;
+    const uint32_t t = threadIdx.x;
+    const uint64_t items = (uint64_t)nbar * nblocks;
+    for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const uint32_t g = (uint32_t)(it / nblocks), blk = (uint32_t)(it % nblocks);
+        const DevBarrier B = bars[g];
+        const int32_t bx = (int32_t)(blk % K.gdx), by = (int32_t)(blk / K.gdx);
+        for (uint32_t tid = t; tid < K.tpb; tid += blockDim.x) {
+            const int32_t tx = (int32_t)(tid % K.bdx), ty = (int32_t)(tid / K.bdx);
+            bool ok = true;
+            for (uint32_t q = 0; q < B.guard_count; q++) {
+                const int32_t *gr = guards + (size_t)(B.guard_begin + q) * NC;
+                ok = ok && gr[C_TX] * tx + gr[C_TY] * ty + gr[C_BX] * bx + gr[C_BY] * by + gr[C_C0] >= 0;
+            }
+            reach[tid] = ok ? 1 : 0;
+        }
+        __syncthreads();
+        for (uint32_t sc = t; sc < B.nscope; sc += blockDim.x) {
+            const uint32_t t0 = sc * B.scope, t1 = min(K.tpb, t0 + B.scope);
+            bool any = false, all = true;
+            for (uint32_t x = t0; x < t1; x++) { any = any || reach[x]; all = all && reach[x]; }
+            if (any && !all) {
+                atomicAdd(&res[g].divergent, 1ull);
+                atomicMin(&res[g].first, (unsigned long long)blk * B.nscope + sc);
+            }
+        }
+        __syncthreads();     // the map is rewritten for the next item
+    }
+}
+
+// The first divergent instance of each guarded barrier: its smallest thread
+// that reaches the barrier and smallest that does not (one workgroup per
+// barrier, after k_barriers).
+__global__ void __launch_bounds__(256) k_barriers_first(const DevBarrier *__restrict__ bars,
+                                                        const DevKernel *__restrict__ kc_g,
+                                                        const int32_t *__restrict__ guards,
+                                                        BarrierResult *__restrict__ res) {
+    __shared__ uint32_t red[2 * (256 / 64)];
+    const DevKernel K = *kc_g;
+    const uint32_t g = blockIdx.x, t = threadIdx.x;
+    const unsigned long long first = res[g].first;
+    if (first == ~0ull) return;
+    const DevBarrier B = bars[g];
+    const uint32_t blk = (uint32_t)(first / B.nscope), sc = (uint32_t)(first % B.nscope);
+    const int32_t bx = (int32_t)(blk % K.gdx), by = (int32_t)(blk / K.gdx);
+    const uint32_t t0 = sc * B.scope, t1 = min(K.tpb, t0 + B.scope);
+    uint32_t arrive = 0xFFFFFFFFu, skip = 0xFFFFFFFFu;
+    for (uint32_t tid = t0 + t; tid < t1; tid += blockDim.x) {
+        const int32_t tx = (int32_t)(tid % K.bdx), ty = (int32_t)(tid / K.bdx);
+        bool ok = true;
+        for (uint32_t q = 0; q < B.guard_count; q++) {
+            const int32_t *gr = guards + (size_t)(B.guard_begin + q) * NC;
+            ok = ok && gr[C_TX] * tx + gr[C_TY] * ty + gr[C_BX] * bx + gr[C_BY] * by + gr[C_C0] >= 0;
+        }
+        if (ok) arrive = min(arrive, tid); else skip = min(skip, tid);
+    }
+    arrive = wave_min(arrive);
+    skip = wave_min(skip);
+    if (lane() == 0) { red[t >> 6] = arrive; red[4 + (t >> 6)] = skip; }
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < 4; w++) { arrive = min(arrive, red[w]); skip = min(skip, red[4 + w]); }
+        res[g].arrive = arrive;
+        res[g].skip = skip;
     }
 }
 
@@ -2004,6 +2153,21 @@ void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned 
     hipLaunchKernelGGL(k_mid, dim3(ncu * occ_mid), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
     hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot,
                        res);
+}
+
+__global__ void k_init_barrier_results(BarrierResult *r, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { r[i].divergent = 0; r[i].first = ~0ull; r[i].arrive = r[i].skip = 0xFFFFFFFFu; }
+}
+
+void launch_barriers(const DevBarrier *bars, uint32_t n, const DevKernel *kc, const int32_t *guards,
+                     uint32_t nblocks, BarrierResult *res, unsigned ncu, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_init_barrier_results, dim3((n + 255) / 256), dim3(256), 0, st, res, n);
+    const uint64_t items = (uint64_t)n * nblocks;
+    const unsigned grid = (unsigned)std::min<uint64_t>(items, (uint64_t)ncu * 8);
+    hipLaunchKernelGGL(k_barriers, dim3(grid), dim3(256), 0, st, bars, n, kc, guards, nblocks, res);
+    hipLaunchKernelGGL(k_barriers_first, dim3(n), dim3(256), 0, st, bars, kc, guards, res);
 }
 
 void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf, SubResult *res,

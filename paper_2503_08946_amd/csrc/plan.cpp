@@ -98,9 +98,6 @@ rv_status validate(const rv_kernel_desc *d, std::string &msg) {
                     msg = fmt("phase %lld: a barrier guard may use tx, ty, bx, by and k only", i);
                     return RV_ERR_INVALID;
                 }
-        if (p.barrier_after == RV_BARRIER_WARP) {
-            msg = fmt("phase %lld: warp barriers are not supported yet", i); return RV_ERR_UNSUPPORTED;
-        }
     }
     for (int i = 0; i < d->n_segments; i++) {
         const rv_segment &s = d->segments[i];
@@ -125,9 +122,19 @@ static long double row_bound(const int32_t *row, const long double *vmax) {
     return b;
 }
 
-rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::string &msg) {
+static uint32_t ceil_log2(uint64_t n) {
+    uint32_t w = 0;
+    while ((1ull << w) < n) w++;
+    return w;
+}
+
+rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::string &msg, int semantics) {
     rv_status st = validate(d, msg);
     if (st) return st;
+    if (semantics != RV_SEM_INTERVAL && semantics != RV_SEM_STRICT) {
+        msg = "unknown semantics"; return RV_ERR_INVALID;
+    }
+    k.semantics = semantics;
     k.launch = d->launch;
     k.arrays.assign(d->arrays, d->arrays + d->n_arrays);
     k.accesses.assign(d->accesses, d->accesses + d->n_accesses);
@@ -151,7 +158,8 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
     for (auto &s : k.segments) ndyn += (uint64_t)s.repeat * s.phase_count;
     if (ndyn >= (1ull << 31)) { msg = "too many dynamic phases"; return RV_ERR_TOO_LARGE; }
     k.dyn_phase.clear(); k.dyn_k.clear(); k.dyn_interval.clear();
-    uint32_t barriers = 0;
+    std::vector<uint32_t> dyn_fine;   // barriers of either kind before each dynamic phase
+    uint32_t barriers = 0, fine = 0;
     for (auto &s : k.segments)
         for (int r = 0; r < s.repeat; r++)
             for (int j = 0; j < s.phase_count; j++) {
@@ -159,28 +167,114 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 k.dyn_phase.push_back(ph);
                 k.dyn_k.push_back(s.k_base + r);
                 k.dyn_interval.push_back(barriers);
+                dyn_fine.push_back(fine);
                 if (k.phases[ph].barrier_after == RV_BARRIER_BLOCK) barriers++;
+                if (k.phases[ph].barrier_after != RV_BARRIER_NONE) fine++;
+                if (k.phases[ph].barrier_after == RV_BARRIER_WARP && semantics == RV_SEM_STRICT) {
+                    msg = "strict semantics with warp barriers are not supported";
+                    return RV_ERR_UNSUPPORTED;
+                }
             }
     k.n_intervals = k.dyn_phase.empty() ? 0 : k.dyn_interval.back() + 1;
+    const uint32_t warp = d->warp_size > 0 ? (uint32_t)d->warp_size : 32u;
 
-    // ---- per interval: entries, layout, ranges, buckets
-    k.entries.clear(); k.hentries.clear(); k.guard_rows.clear(); k.entry_items.clear();
-    k.intervals.assign(k.n_intervals, IntervalPlan());
+    // ---- barriers: their instances, and the guarded ones for the divergence
+    // check (guard rows over tx, ty, bx, by with k folded into the constant)
+    k.guard_rows.clear();
+    k.barriers.clear();
+    k.barrier_instances = 0;
+    for (size_t dd = 0; dd < k.dyn_phase.size(); dd++) {
+        const rv_phase &ph = k.phases[k.dyn_phase[dd]];
+        if (ph.barrier_after == RV_BARRIER_NONE) continue;
+        const uint32_t scope = ph.barrier_after == RV_BARRIER_BLOCK ? (uint32_t)tpb
+                                                                     : std::min<uint32_t>(warp, (uint32_t)tpb);
+        const uint32_t nscope = (uint32_t)((tpb + scope - 1) / scope);
+        k.barrier_instances += nblocks * nscope;
+        if (!ph.guard_count) continue;
+        DevBarrier B{};
+        B.dphase = (uint32_t)dd;
+        B.guard_begin = (uint32_t)(k.guard_rows.size() / NC);
+        B.guard_count = (uint32_t)ph.guard_count;
+        B.scope = scope;
+        B.nscope = nscope;
+        for (int g = ph.guard_begin; g < ph.guard_begin + ph.guard_count; g++) {
+            const rv_affine &f = k.guards[g].g;
+            int32_t row[NC] = {0};
+            const int64_t c0 = (int64_t)f.c0 + (int64_t)f.coef[RV_V_K] * k.dyn_k[dd];
+            row[C_TX] = f.coef[RV_V_TX]; row[C_TY] = f.coef[RV_V_TY];
+            row[C_BX] = f.coef[RV_V_BX]; row[C_BY] = f.coef[RV_V_BY];
+            long double b = std::fabs((long double)c0) + std::fabs((long double)row[C_TX]) * (long double)(bdx - 1) +
+                            std::fabs((long double)row[C_TY]) * (long double)(bdy - 1) +
+                            std::fabs((long double)row[C_BX]) * (long double)(gdx - 1) +
+                            std::fabs((long double)row[C_BY]) * (long double)(gdy - 1);
+            if (b > 2147483647.0L) {
+                msg = fmt("dynamic phase %lld: a barrier guard may leave int32", (long long)dd);
+                return RV_ERR_RANGE;
+            }
+            row[C_C0] = (int32_t)c0;
+            k.guard_rows.insert(k.guard_rows.end(), row, row + NC);
+        }
+        k.barriers.push_back(B);
+    }
+
+    // ---- the planned location spaces ("virtual intervals").  Interval
+    // semantics: one per barrier interval; the fine interval of each dynamic
+    // phase inside it (warp barriers) becomes a sub-key below the location,
+    // and warps are the unordered units.  Strict semantics: the barrier
+    // intervals keep the shared arrays only, and one more space holds the
+    // global arrays of the whole kernel with the interval as the sub-key and
+    // blocks as the units (blocks are never ordered).
+    struct Virt { uint32_t d0, d1, space_mask; bool strict_global; };
+    std::vector<Virt> virt;
+    {
+        uint32_t d0 = 0;
+        for (uint32_t iv = 0; iv < k.n_intervals; iv++) {
+            uint32_t d1 = d0;
+            while (d1 < k.dyn_phase.size() && k.dyn_interval[d1] == iv) d1++;
+            virt.push_back(Virt{d0, d1, semantics == RV_SEM_STRICT ? 1u : 3u, false});
+            d0 = d1;
+        }
+        if (semantics == RV_SEM_STRICT) virt.push_back(Virt{0, (uint32_t)k.dyn_phase.size(), 2u, true});
+    }
+
+    // ---- per planned space: entries, layout, ranges, buckets
+    k.entries.clear(); k.hentries.clear(); k.entry_items.clear();
+    k.intervals.assign(virt.size(), IntervalPlan());
     k.subs.clear();
     k.n_instances = 0; k.max_interval_instances = 0; k.n_buckets = 0;
-    uint32_t d0 = 0;
-    for (uint32_t iv = 0; iv < k.n_intervals; iv++) {
+    k.has_subkeys = false;
+    for (uint32_t iv = 0; iv < virt.size(); iv++) {
         IntervalPlan &I = k.intervals[iv];
-        uint32_t d1 = d0;
-        while (d1 < k.dyn_phase.size() && k.dyn_interval[d1] == iv) d1++;
+        const uint32_t d0 = virt[iv].d0, d1 = virt[iv].d1, smask = virt[iv].space_mask;
+        auto in_space = [&](int a) { return (smask >> k.arrays[k.accesses[a].array].space) & 1u; };
         I.dphase_begin = d0; I.dphase_end = d1;
         I.entry_begin = (uint32_t)k.entries.size();
         I.arr_off.assign(k.arrays.size(), -1);
+        // sub-key of each dynamic phase and its width, and the unordered units
+        uint32_t nsubk = 1, sub0 = 0;
+        if (virt[iv].strict_global) {
+            nsubk = std::max<uint32_t>(k.n_intervals, 1);
+            I.unit = (uint32_t)tpb; I.upb = 1;
+        } else if (d1 > d0) {
+            sub0 = dyn_fine[d0];
+            nsubk = dyn_fine[d1 - 1] - sub0 + 1;
+            I.unit = std::min<uint32_t>(warp, (uint32_t)tpb); I.upb = (uint32_t)((tpb + warp - 1) / warp);
+        }
+        I.w = ceil_log2(nsubk);
+        if (I.w > (uint32_t)SMAX) {
+            msg = fmt("interval %lld: %lld barrier-separated parts exceed the sub-key (at most 512)", iv, nsubk);
+            return RV_ERR_UNSUPPORTED;
+        }
+        if (I.w) k.has_subkeys = true;
+        auto subkey = [&](uint32_t dd) {
+            return virt[iv].strict_global ? k.dyn_interval[dd] : dyn_fine[dd] - sub0;
+        };
         // touched arrays
         std::vector<char> touched(k.arrays.size(), 0);
         for (uint32_t dd = d0; dd < d1; dd++) {
             const rv_phase &ph = k.phases[k.dyn_phase[dd]];
-            for (int a = ph.access_begin; a < ph.access_begin + ph.access_count; a++) touched[k.accesses[a].array] = 1;
+            for (int a = ph.access_begin; a < ph.access_begin + ph.access_count; a++)
+                if (in_space(a)) touched[k.accesses[a].array] = 1;
         }
         uint64_t S = 0, G = 0;
         for (size_t a = 0; a < k.arrays.size(); a++)
@@ -188,9 +282,9 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
         for (size_t a = 0; a < k.arrays.size(); a++)
             if (touched[a] && k.arrays[a].space == RV_GLOBAL) { I.arr_off[a] = (int64_t)G; G += arr_size(k.arrays[a]); }
         I.S = S;
-        I.K = nblocks * S + G;
+        I.K = (nblocks * S + G) << I.w;
         if (I.K >= (1ull << 31)) {
-            msg = fmt("interval %lld: %lld locations do not fit a 31-bit key", iv, (long long)I.K);
+            msg = fmt("interval %lld: %lld location keys do not fit 31 bits", iv, (long long)I.K);
             return RV_ERR_KEY_BITS;
         }
         // entries
@@ -199,6 +293,7 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
             const rv_phase &ph = k.phases[k.dyn_phase[dd]];
             const int32_t kval = k.dyn_k[dd];
             for (int a = ph.access_begin; a < ph.access_begin + ph.access_count; a++) {
+                if (!in_space(a)) continue;
                 const rv_access &ac = k.accesses[a];
                 const rv_array &ar = k.arrays[ac.array];
                 DevEntry E{};
@@ -301,6 +396,15 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                     stride *= (uint32_t)ar.dim[j];
                 }
                 E.fr[C_C0] += E.loc_base;
+                // sub-key below the location: key = location << w | sub
+                const uint32_t sk = subkey(dd);
+                E.wshift = I.w;
+                if (I.w) {
+                    for (int v = 0; v < NC; v++) E.fr[v] <<= I.w;
+                    E.fr[C_C0] += sk;
+                    E.loc_mul <<= I.w;
+                    E.loc_base = (E.loc_base << I.w) + sk;
+                }
                 // work items: lch loop points x gt threads per lane
                 if (E.box > 0) {
                     E.lch = std::min<uint32_t>(E.box, RPL);
@@ -374,7 +478,7 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
         if (I.P > 0 && I.K > 0) {
             long double ratio = (long double)k.target * (long double)I.K / (long double)I.P;
             int s = ratio >= 1 ? (int)std::floor(std::log2((double)ratio)) : 0;
-            s = std::max(0, std::min(SMAX, s));
+            s = std::max((int)I.w, std::min(SMAX, s));     // a bucket holds whole locations
             I.s = (uint32_t)s;
             uint64_t span = (uint64_t)NBMAX << s;   // locations per pass
             I.nsub = (uint32_t)((I.K + span - 1) / span);
@@ -390,7 +494,6 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 k.subs.push_back(sp);
             }
         }
-        d0 = d1;
     }
     return RV_OK;
 }
@@ -485,6 +588,9 @@ void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0, s
         D.mgM = make_magic((uint32_t)I.M);
         D.interval = sp.interval;
         D.res = res0 + (i - sb);
+        D.wshift = I.w;
+        D.upb = I.upb ? I.upb : 1u;
+        D.mg_unit = make_magic(I.unit ? I.unit : 1u);
         items += I.items;
         buckets += sp.nb;
         out.push_back(D);
@@ -522,6 +628,7 @@ void decode_instance(const rv_kernel &k, uint32_t interval, uint32_t id, rv_side
 void decode_location(const rv_kernel &k, uint32_t interval, uint32_t loc, int32_t &space, int32_t &array,
                      uint32_t &block, int64_t &address) {
     const IntervalPlan &I = k.intervals[interval];
+    loc >>= I.w;                      // the sub-key below the location
     uint64_t shared_end = (uint64_t)k.kc.nblocks * I.S;
     uint64_t rem;
     if (loc < shared_end) {

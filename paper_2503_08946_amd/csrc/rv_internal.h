@@ -110,7 +110,10 @@ struct DevEntry {
     // mapping, a lane's gt consecutive threads differ in tx alone): every
     // index and the location are affine in the slot.
     uint32_t tlin;
-    uint32_t pad0;
+    // Sub-key: the location key is (location << wshift) | sub-interval; the
+    // general path shifts its flattened index (loc_mul, loc_base and fr
+    // already carry the shift and the sub-interval).
+    uint32_t wshift;
 };
 
 struct DevKernel {
@@ -135,6 +138,14 @@ struct DevSub {
     Magic mgM;
     uint32_t interval;
     uint32_t res;                  // result slot
+    // Sub-keys (warp barriers; strict semantics' global space): a location
+    // spans 2^wshift consecutive keys, one per sub-interval.  Records of one
+    // sub-interval are judged as usual; across sub-intervals only records of
+    // different units conflict: unit(thread) = block * upb + tid / unit size
+    // (warps, or blocks with upb = 1 and unit size = threads per block).
+    uint32_t wshift;
+    uint32_t upb;
+    Magic mg_unit;
 };
 
 // Per-pass result slot (device).
@@ -147,6 +158,27 @@ struct SubResult {
     uint32_t w[4];                 // location, first id, second id, second is_write
 };
 static_assert(sizeof(SubResult) == 48, "SubResult layout");
+
+// A barrier that carries guards (the threads that reach it), at one dynamic
+// phase: its scopes are the block (scope = threads per block, nscope = 1)
+// or the block's warps (scope = warp size, nscope = warps per block).
+struct DevBarrier {
+    uint32_t dphase;
+    uint32_t guard_begin, guard_count;   // rows (NC int32 each) in the kernel's guard table, k folded in
+    uint32_t scope, nscope;
+    uint32_t pad[3];
+};
+
+// Per guarded barrier: its divergent scope instances and the first of them
+// in (block, scope) order with that instance's smallest reaching thread and
+// smallest thread that does not reach it.
+struct BarrierResult {
+    unsigned long long divergent;
+    unsigned long long first;            // block * nscope + scope; ~0 when none
+    uint32_t arrive, skip;
+    uint32_t pad[2];
+};
+static_assert(sizeof(BarrierResult) == 32, "BarrierResult layout");
 
 // Device witness of the collect mode: the SubResult-style words plus the pass.
 struct DevWitness {
@@ -172,6 +204,8 @@ struct IntervalPlan {
     uint32_t items = 0;
     uint32_t items_begin = 0;      // offset into KernelPlan::entry_items
     uint32_t dphase_begin = 0, dphase_end = 0;
+    uint32_t w = 0;                // sub-key bits below the location
+    uint32_t unit = 0, upb = 0;    // unordered units across sub-intervals: threads per unit, units per block
 };
 
 struct SubPlan {
@@ -213,7 +247,9 @@ struct rv_kernel {
     std::vector<uint32_t> dyn_phase;
     std::vector<int32_t> dyn_k;
     std::vector<uint32_t> dyn_interval;
-    uint32_t n_intervals = 0;
+    uint32_t n_intervals = 0;      // barrier intervals (strict semantics plan one more space after them)
+    int semantics = RV_SEM_INTERVAL;
+    bool has_subkeys = false;      // some pass has sub-keys (judged by the fold kernels)
     // plan
     rv::DevKernel kc{};
     std::vector<rv::DevEntry> entries;
@@ -227,8 +263,12 @@ struct rv_kernel {
     uint64_t max_interval_instances = 0;
     uint64_t n_buckets = 0;
     int target = rv::DEFAULT_TARGET;
+    // guarded barriers (divergence check) and the number of barrier instances
+    std::vector<rv::DevBarrier> barriers;
+    uint64_t barrier_instances = 0;
     // device copies
     void *d_mem = nullptr;
+    rv::DevBarrier *d_barriers = nullptr;
     rv::DevKernel *d_kc = nullptr;
     rv::DevEntry *d_entries = nullptr;
     int32_t *d_guards = nullptr;
@@ -249,7 +289,8 @@ namespace rv {
 
 // plan.cpp
 rv_status validate(const rv_kernel_desc *d, std::string &msg);
-rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::string &msg);
+rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::string &msg,
+                      int semantics = RV_SEM_INTERVAL);
 WorkspaceLayout layout_workspace(size_t bytes);
 rv_status plan_chunks(rv_kernel &k, const WorkspaceLayout &L, std::string &msg);
 // Append DevSub entries for passes [sb, se) of k.  Item and bucket begins
@@ -294,6 +335,11 @@ void launch_gather(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const u
                    unsigned long long base, unsigned long long lo, unsigned long long hi,
                    DevWitness *out, hipStream_t st);
 size_t scan_bsum_words(size_t n);
+// Divergence of the guarded barriers bars[0..n): res[0..n) receives the
+// divergent scope instances of each (its first instance included).
+void launch_barriers(const DevBarrier *bars, uint32_t n, const DevKernel *kc, const int32_t *guards,
+                     uint32_t nblocks, BarrierResult *res, unsigned ncu, hipStream_t st);
+constexpr uint32_t BARRIER_MAX_TPB = 4096;   // threads per block the divergence check handles
 
 // The device scratch of rv_check_static (kernels.hip): its address on
 // `device` is looked up once, with that device current (rv_ctx_create), and

@@ -113,6 +113,18 @@ class rv_record(ctypes.Structure):
                 ("loop", i32 * 3), ("is_write", i32)]
 
 
+class rv_barrier_result(ctypes.Structure):
+    _fields_ = [("n_instances", u64), ("n_divergent", u64), ("has_divergence", i32), ("dyn_phase", u32),
+                ("block", u32), ("warp", i32), ("arrive_tid", u32), ("skip_tid", u32)]
+
+
+class rv_load_options(ctypes.Structure):
+    _fields_ = [("semantics", i32), ("reserved", i32 * 3)]
+
+
+SEMANTICS = {"interval": 0, "strict": 1}
+
+
 class rv_tuning(ctypes.Structure):
     _fields_ = [("target", i32), ("group", i32), ("n_candidates", i32), ("reserved", i32),
                 ("candidates", i32 * 8), ("cand_group", i32 * 8), ("ms", ctypes.c_double * 8)]
@@ -148,11 +160,13 @@ def lib():
             "rv_ctx_create": [P(V), ctypes.c_int, V, V, S],
             "rv_ctx_destroy": [V],
             "rv_load_kernel_desc": [V, P(rv_kernel_desc), P(V)],
+            "rv_load_kernel_desc_ex": [V, P(rv_kernel_desc), P(rv_load_options), P(V)],
             "rv_free_kernel": [V, V],
             "rv_kernel_get_info": [V, V, P(rv_kernel_info)],
             "rv_check": [V, V, P(rv_result)],
             "rv_check_batch": [V, P(V), S, P(rv_result)],
             "rv_check_static": [V, V, P(rv_result)],
+            "rv_check_barriers": [V, V, P(rv_barrier_result)],
             "rv_get_witnesses": [V, V, u64, P(rv_witness), S, P(S)],
             "rv_debug_records": [V, V, u32, ctypes.c_int, P(rv_record), S, P(S)],
             "rv_set_timing": [V, ctypes.c_int],
@@ -179,7 +193,9 @@ def lib():
 
 
 EXPORTED = ("rv_validate_desc", "rv_plan_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_error", "rv_load_kernel_desc",
+            "rv_load_kernel_desc_ex",
             "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_check_static",
+            "rv_check_barriers",
             "rv_get_witnesses",
             "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest", "rv_ctx_get_tuning",
             "rv_ctx_set_tuning", "rv_autotune", "rv_server_create",
@@ -415,10 +431,18 @@ class Context:
             pass
 
     # ---------------------------------------------------------------- API
-    def load(self, desc) -> Kernel:
+    def load(self, desc, semantics: str = "interval") -> Kernel:
+        """Load a description; ``semantics`` "interval" (the default) or
+        "strict" (blocks are never ordered: rv_load_kernel_desc_ex)."""
         m = Marshalled(desc)
         h = ctypes.c_void_p()
-        self._call(lib().rv_load_kernel_desc, self.handle, ctypes.byref(m.desc), ctypes.byref(h))
+        if semantics == "interval":
+            self._call(lib().rv_load_kernel_desc, self.handle, ctypes.byref(m.desc), ctypes.byref(h))
+        else:
+            o = rv_load_options()
+            o.semantics = SEMANTICS[semantics]
+            self._call(lib().rv_load_kernel_desc_ex, self.handle, ctypes.byref(m.desc), ctypes.byref(o),
+                       ctypes.byref(h))
         return Kernel(self, h, desc)
 
     def check(self, k: Kernel) -> Result:
@@ -432,6 +456,15 @@ class Context:
         out = rv_result()
         self._call(lib().rv_check_static, self.handle, k.handle, ctypes.byref(out))
         return _result(out)
+
+    def check_barriers(self, k: Kernel) -> dict:
+        """rv_check_barriers: divergent barrier instances of a kernel."""
+        out = rv_barrier_result()
+        self._call(lib().rv_check_barriers, self.handle, k.handle, ctypes.byref(out))
+        d = {name: getattr(out, name) for name, _ in rv_barrier_result._fields_}
+        d["first"] = ((out.dyn_phase, out.block, out.warp, out.arrive_tid, out.skip_tid)
+                      if out.has_divergence else None)
+        return d
 
     def check_batch(self, ks: Sequence[Kernel]) -> List[Result]:
         b = Batch(self, ks)

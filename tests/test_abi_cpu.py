@@ -136,3 +136,21 @@ def test_plan_gespmm_sweep_sizes(size):
     for mid, trail in ((True, True), (False, True), (True, False)):
         info = rv.plan(K.gespmm_crc(M, N, T, Kb, middle_barrier=mid, trailing_barrier=trail, kb_on_all=False))
         assert info.n_instances == cf["records"]
+
+
+def test_plan_warp_barriers_and_strict():
+    from workloads.desc import BARRIER_WARP
+    # warp barriers: one barrier interval, 5 fine intervals -> 3 sub-key bits
+    info = rv.plan(K.warp_reduction(-1))
+    assert info.n_intervals == 1 and info.n_instances == 128 * 5 * 3      # before the guards
+    assert rv.validate(K.cross_block_global())[0] == 0
+    # warp barriers are refused in strict mode only at load (a context is
+    # needed), validation accepts them
+    assert rv.validate(K.warp_exchange(BARRIER_WARP))[0] == 0
+    # a barrier guard may not use loop variables
+    d = K.guarded_barrier("block-half")
+    bad = d.replace(phases=[d.phases[0].__class__(0, 1, 1, (aff(l0=1),)), d.phases[1]])
+    assert rv.validate(bad)[0] == -1
+    # a barrier kind outside 0..2
+    bad = d.replace(phases=[d.phases[0].__class__(0, 1, 3), d.phases[1]])
+    assert rv.validate(bad)[0] == -1
