@@ -166,8 +166,12 @@ typedef struct {
 /* Per-stage GPU time, accumulated while timing is enabled (HIP events on the
  * context's stream around each launch). */
 enum { RV_STAGE_FILL = 0, RV_STAGE_COUNT, RV_STAGE_SCAN, RV_STAGE_EXPAND, RV_STAGE_SORT_SCAN,
-       RV_STAGE_FINISH, RV_NSTAGE };
-typedef struct { double ms[RV_NSTAGE]; uint64_t launches[RV_NSTAGE]; } rv_timing;
+       RV_STAGE_FINISH, RV_STAGE_SMALL /* batched passes checked on chip */, RV_NSTAGE };
+typedef struct {
+    double ms[RV_NSTAGE];
+    uint64_t launches[RV_NSTAGE];
+    uint64_t small_records;   /* records of the batched passes checked on chip (RV_STAGE_SMALL) */
+} rv_timing;
 
 /* Static facts about a loaded kernel. */
 typedef struct {
@@ -283,7 +287,15 @@ rv_status rv_load_kernel_desc(rv_ctx *ctx, const rv_kernel_desc *desc, rv_kernel
  * conflict; when only records of different units (warps; blocks) conflict,
  * `second` is the smallest-id record if its unit differs from first's, else
  * the largest-id record. */
-enum { RV_SEM_INTERVAL = 0, RV_SEM_STRICT = 1 };
+/*  RV_SEM_ORDERED: the check of Section 2.1 step 6 on a sequential schedule
+ *    (the appendix listings' Before = Schedule << Schedule): dynamic phases
+ *    run one after another, inside one the threads in global-thread order,
+ *    each walking its loop points in row-major order; the accesses of one
+ *    phase at one (thread, loop index) form one statement instance.
+ *    Barriers play no part.  Such a kernel is checked with
+ *    rv_check_counts only (RaW, WaW, WaR; rv_check: RV_ERR_STATE).  The
+ *    instance ids of all phases share 32 bits (RV_ERR_TOO_LARGE beyond). */
+enum { RV_SEM_INTERVAL = 0, RV_SEM_STRICT = 1, RV_SEM_ORDERED = 2 };
 typedef struct {
     int32_t semantics;       /* RV_SEM_* */
     int32_t reserved[3];     /* 0 */
@@ -352,6 +364,28 @@ rv_status rv_get_witnesses(rv_ctx *ctx, rv_kernel *k, uint64_t first_index, rv_w
 #define RV_STATIC_MAX_PASSES 8192
 rv_status rv_check_static(rv_ctx *ctx, rv_kernel *k, rv_result *out);
 
+/* Exact pair and dependence counts.  For a kernel loaded with interval
+ * semantics and no warp barriers: n_pairs = the unordered pairs of
+ * different threads that touch one location in one barrier interval, at
+ * least one of them writing it, summed over (interval, location) -- the
+ * distinct-thread pairs behind n_conflicts.  For a kernel loaded with
+ * RV_SEM_ORDERED: the dependence relations of Section 2.1 step 6 (RaW =
+ * (Write . Read^-1) * Before, WaW, WaR, with Before = earlier on the
+ * sequential schedule) counted as (earlier instance, element, later
+ * instance) triples, and the elements holding at least one of them.  Each
+ * bucket's records are ordered on the GPU by (location, thread) or
+ * (location, time) -- an LDS sort, or a radix sort in global memory for
+ * buckets above 4096 records -- and scanned.  Errors: RV_ERR_UNSUPPORTED for
+ * strict semantics or a kernel with warp barriers; otherwise as rv_check
+ * (out of bounds: the message names an out-of-bounds instance). */
+typedef struct {
+    uint64_t n_records;
+    uint64_t n_conflicts;        /* interval semantics: as rv_check; ordered: 0 */
+    uint64_t n_pairs;            /* interval semantics */
+    uint64_t n_raw, n_waw, n_war, n_dep_locations;   /* ordered semantics */
+} rv_counts;
+rv_status rv_check_counts(rv_ctx *ctx, rv_kernel *k, rv_counts *out);
+
 /* Barrier divergence (Section 2, component (4): barriers; Section 1.1.4:
  * warp-level synchronisation).  A barrier whose rv_phase carries guards is
  * reached by the threads for which every guard is >= 0.  One instance of a
@@ -389,7 +423,7 @@ rv_status rv_set_timing(rv_ctx *ctx, int enable);
 rv_status rv_get_timing(rv_ctx *ctx, rv_timing *out, int reset);
 
 /* ---------------------------------------------------------------- tuning
- * Two free parameters, neither of which changes any result:
+ * Three free parameters, none of which changes any result:
  *  - `target`, the planner's mean number of records per location bucket: it
  *    sets each interval's bucket width 2^s (s = floor(log2(target x
  *    locations / instances)), clamped to [0, 9]), trading the number of
@@ -400,7 +434,13 @@ rv_status rv_get_timing(rv_ctx *ctx, rv_timing *out, int reset);
  *    conflict and its witness follow (Section 2.1 step 6 reduced to one
  *    location); FOLD reaches it with LDS atomics on per-location slots,
  *    SORT_SCAN by sorting the bucket in LDS and scanning runs of equal
- *    location.  It applies to the next checks. */
+ *    location.  It applies to the next checks.
+ *  - `small_cap`, the batched checks' small-pass threshold: in
+ *    rv_check_batch (and a server's batches) a pass of at most small_cap
+ *    instances (at most 2048; 0 turns the path off) is checked entirely on
+ *    chip by one workgroup -- its records folded into an LDS hash table of
+ *    per-location summaries, then judged -- instead of going through the
+ *    record buffer in HBM and the bucket kernels.  Passes whose interval has warp barriers never take it. */
 enum {
     RV_GROUP_FOLD = 0,       /* fold records into per-location LDS tables with atomics (default) */
     RV_GROUP_SORT_SCAN = 1   /* LDS counting sort of each bucket + DPP segmented scan */
@@ -409,15 +449,17 @@ typedef struct {
     int32_t target;          /* mean records per bucket, in [64, 4096]; default 2048 */
     int32_t group;           /* RV_GROUP_*: how a bucket's records are grouped by location */
     int32_t n_candidates;    /* rv_autotune: candidates measured */
-    int32_t reserved;
+    int32_t small_cap;       /* batched small-pass threshold in [0, 2048]; default 2048 */
     int32_t candidates[8];   /* rv_autotune: target of each candidate */
     int32_t cand_group[8];   /* rv_autotune: grouping of each candidate */
+    int32_t cand_small[8];   /* rv_autotune: small-pass threshold of each candidate */
     double ms[8];            /* rv_autotune: median wall time of one batched check per candidate */
 } rv_tuning;
 rv_status rv_ctx_get_tuning(rv_ctx *ctx, rv_tuning *out);
-rv_status rv_ctx_set_tuning(rv_ctx *ctx, const rv_tuning *t);   /* reads target and group */
+rv_status rv_ctx_set_tuning(rv_ctx *ctx, const rv_tuning *t);   /* reads target, group and small_cap */
 /* Measure a batched check of descs[0..n) (host memory, as rv_load_kernel_desc
- * takes them) under each candidate (target, group), `trials` timed runs after one
+ * takes them) under each candidate (target in {1024, 2048}, group, small_cap
+ * in {0, 2048}), `trials` timed runs after one
  * warm-up each (host wall time from launch to results on the host, median),
  * keep the fastest in the context and report all of them in *out.  A
  * description that fails to load or check fails the call with its code. */

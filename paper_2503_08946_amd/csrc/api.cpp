@@ -37,12 +37,26 @@ struct Lane {
     size_t win_cap = 0;
     BarrierResult *d_bres = nullptr;   // per guarded barrier (rv_check_barriers), grown on demand
     size_t bres_cap = 0;
+    PassCounts *d_cnt = nullptr;       // per pass (rv_check_counts), grown on demand
+    size_t cnt_cap = 0;
+    unsigned long long *d_tmp = nullptr;   // a second record area (rv_check_counts' large buckets)
+    size_t tmp_cap = 0;
     void *h_up = nullptr;       // pinned: pass tables going up
     size_t up_cap = 0;
     void *h_down = nullptr;     // pinned: results coming down
     size_t down_cap = 0;
     hipEvent_t done = nullptr;
     bool untimed = false;       // never record timing events (rv_check_static creates none)
+    std::vector<uint32_t> small_slots;   // result slots of the batch's passes checked on chip
+    uint64_t small_records = 0;          // their records, summed when the batch is collected
+    // the last batch's pass table, still in d_subs: reused when the next batch
+    // has the same kernels (load serials) and small-pass threshold
+    struct TabChunk { size_t sub_begin, sub_end; uint64_t items, buckets; bool subkeys; };
+    std::vector<uint64_t> tab_key;
+    std::vector<TabChunk> tab_chunks;
+    size_t tab_nreg = 0, tab_nsmall = 0;
+    std::vector<uint32_t> tab_small_slots;
+    bool tab_valid = false;
     // the batch in flight
     std::vector<rv_kernel *> jobs;
     std::vector<size_t> res0;
@@ -85,6 +99,7 @@ struct rv_ctx {
                                     // while no worker thread runs)
     std::atomic<int> target{DEFAULT_TARGET};   // planner: mean records per bucket for kernels loaded next
     std::atomic<int> group{RV_GROUP_FOLD};     // per-bucket grouping kernel (read by a server's worker)
+    std::atomic<int> small_cap{(int)SMALL_CAP};   // batched passes of at most this many instances run on chip
     // timing
     bool timing = false;
     struct Ev { int stage; hipEvent_t a, b; };
@@ -94,6 +109,8 @@ struct rv_ctx {
 };
 
 namespace {
+
+const char *const ORDERED_ONLY = "the kernel was loaded for ordered dependences: use rv_check_counts";
 
 rv_status fail(rv_ctx *c, rv_status st, const std::string &m) {
     if (c) c->err = m;
@@ -166,6 +183,7 @@ rv_status drain_timing(rv_ctx *c) {
 template <class T>
 rv_status grow_device(Lane &ln, T *&p, size_t &cap, size_t n) {
     if (n <= cap) return RV_OK;
+    if ((void *)p == (void *)ln.d_subs) ln.tab_valid = false;
     HIP_TRY_L(ln, hipStreamSynchronize(ln.stream));
     if (p) HIP_TRY_L(ln, hipFree(p));
     p = nullptr;
@@ -191,11 +209,14 @@ void lane_release(Lane &ln) {
     if (ln.d_subs) (void)hipFree(ln.d_subs);
     if (ln.d_win) (void)hipFree(ln.d_win);
     if (ln.d_bres) (void)hipFree(ln.d_bres);
+    if (ln.d_cnt) (void)hipFree(ln.d_cnt);
+    if (ln.d_tmp) (void)hipFree(ln.d_tmp);
     if (ln.h_up) (void)hipHostFree(ln.h_up);
     if (ln.h_down) (void)hipHostFree(ln.h_down);
     if (ln.done) (void)hipEventDestroy(ln.done);
     ln.d_res = nullptr; ln.d_subs = nullptr; ln.d_win = nullptr; ln.d_bres = nullptr; ln.h_up = nullptr;
     ln.h_down = nullptr; ln.bres_cap = 0;
+    ln.d_cnt = nullptr; ln.cnt_cap = 0; ln.d_tmp = nullptr; ln.tmp_cap = 0;
     ln.done = nullptr;
     ln.res_cap = ln.subs_cap = ln.win_cap = ln.up_cap = ln.down_cap = 0;
 }
@@ -318,6 +339,7 @@ bool fits(const rv_kernel &k, const WorkspaceLayout &L) {
 // into pinned memory and `ln.done` is recorded after them.
 rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
     ln.jobs.assign(ks, ks + n);
+    ln.small_slots.clear();
     ln.res0.assign(n + 1, 0);
     for (size_t j = 0; j < n; j++) ln.res0[j + 1] = ln.res0[j] + ks[j]->subs.size();
     const size_t ns = ln.res0[n];
@@ -337,17 +359,45 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
             run_check_chunk(c, ln, k->d_subs + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets,
                             k->has_subkeys);
     } else {
+        // the same kernels as the last batch on this lane: its table is on the device
+        std::vector<uint64_t> key(n + 1);
+        for (size_t j = 0; j < n; j++) key[j] = ks[j]->serial;
+        key[n] = (uint64_t)std::max(0, (int)c->small_cap);
+        if (ln.tab_valid && key == ln.tab_key) {
+            ln.small_slots = ln.tab_small_slots;
+            if (ln.tab_nsmall)
+                timed(c, ln, RV_STAGE_SMALL, [&] {
+                    launch_small(ln.d_subs + ln.tab_nreg, (uint32_t)ln.tab_nsmall, ln.d_res, c->ncu, s);
+                });
+            for (auto &ch : ln.tab_chunks)
+                run_check_chunk(c, ln, ln.d_subs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items,
+                                ch.buckets, ch.subkeys);
+            goto launched;
+        }
+        ln.tab_valid = false;
+        {
         // passes in (kernel, pass) order, greedy chunks by capacity
-        struct Chunk { size_t sub_begin, sub_end; uint64_t items, buckets; bool subkeys; };
+        using Chunk = Lane::TabChunk;
         std::vector<Chunk> chunks;
         std::vector<DevSub> table;
         table.reserve(ns);
         Chunk cur{0, 0, 0, 0, false};
         uint64_t rec_bound = 0;
+        std::vector<DevSub> small;     // passes checked on chip (k_small)
+        std::vector<uint32_t> small_items;
+        const uint64_t small_cap = (uint64_t)std::max(0, (int)c->small_cap);
         for (size_t j = 0; j < n; j++) {
             const rv_kernel &k = *ks[j];
             for (uint32_t i = 0; i < k.subs.size(); i++) {
                 const IntervalPlan &I = k.intervals[k.subs[i].interval];
+                if (I.P <= small_cap && I.w == 0) {
+                    DevSub D = k.h_subs[i];
+                    D.res = (uint32_t)(ln.res0[j] + i);
+                    small.push_back(D);
+                    small_items.push_back(I.items);
+                    ln.small_slots.push_back(D.res);
+                    continue;
+                }
                 const uint32_t nb = k.subs[i].nb;
                 if (cur.sub_end > cur.sub_begin &&
                     (rec_bound + I.P > ln.L.cap_records || cur.buckets + nb > ln.L.cap_buckets ||
@@ -369,6 +419,16 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
             }
         }
         if (cur.sub_end > cur.sub_begin) chunks.push_back(cur);
+        const size_t nreg = table.size();
+        // largest first (by work items): the persistent workgroups take the
+        // list round-robin, so the long passes do not straggle
+        {
+            std::vector<uint32_t> order(small.size());
+            for (uint32_t i = 0; i < order.size(); i++) order[i] = i;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](uint32_t x, uint32_t y) { return small_items[x] > small_items[y]; });
+            for (uint32_t i : order) table.push_back(small[i]);
+        }
         st = grow_device(ln, ln.d_subs, ln.subs_cap, std::max<size_t>(table.size(), 1));
         if (st) return st;
         st = grow_pinned(ln, ln.h_up, ln.up_cap, std::max<size_t>(table.size(), 1) * sizeof(DevSub));
@@ -377,10 +437,21 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
             memcpy(ln.h_up, table.data(), table.size() * sizeof(DevSub));
             HIP_TRY_L(ln, hipMemcpyAsync(ln.d_subs, ln.h_up, table.size() * sizeof(DevSub), hipMemcpyHostToDevice, s));
         }
+        if (!small.empty())
+            timed(c, ln, RV_STAGE_SMALL,
+                  [&] { launch_small(ln.d_subs + nreg, (uint32_t)small.size(), ln.d_res, c->ncu, s); });
         for (auto &ch : chunks)
             run_check_chunk(c, ln, ln.d_subs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items,
                             ch.buckets, ch.subkeys);
+        ln.tab_key = std::move(key);
+        ln.tab_chunks = std::move(chunks);
+        ln.tab_nreg = nreg;
+        ln.tab_nsmall = small.size();
+        ln.tab_small_slots = ln.small_slots;
+        ln.tab_valid = true;
+        }
     }
+launched:
     if ((st = check_launch(ln))) return st;
     if (ns) HIP_TRY_L(ln, hipMemcpyAsync(ln.h_down, ln.d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, s));
     if (!ln.done) HIP_TRY_L(ln, hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
@@ -396,15 +467,30 @@ rv_status lane_collect(Lane &ln, rv_result *out, rv_status *status, std::string 
     HIP_TRY_L(ln, hipEventSynchronize(ln.done));
     ln.busy = false;
     const SubResult *hr = reinterpret_cast<const SubResult *>(ln.h_down);
+    ln.small_records = 0;
+    for (uint32_t slot : ln.small_slots) ln.small_records += hr[slot].records;
+    const size_t n = ln.jobs.size();
+    std::vector<rv_status> sts(n);
+    std::vector<std::string> ms(n);
+    auto work = [&](size_t j0, size_t j1) {
+        for (size_t j = j0; j < j1; j++) sts[j] = assemble(*ln.jobs[j], hr + ln.res0[j], &out[j], ms[j]);
+    };
+    // a large batch decodes its witnesses on several host threads
+    const size_t nth = n >= 1024 ? std::min<size_t>(8, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    if (nth > 1) {
+        std::vector<std::thread> th;
+        for (size_t q = 0; q < nth; q++) th.emplace_back(work, n * q / nth, n * (q + 1) / nth);
+        for (auto &x : th) x.join();
+    } else {
+        work(0, n);
+    }
     rv_status first = RV_OK;
-    for (size_t j = 0; j < ln.jobs.size(); j++) {
-        std::string m;
-        rv_status st = assemble(*ln.jobs[j], hr + ln.res0[j], &out[j], m);
-        if (status) status[j] = st;
-        if (msgs) msgs[j] = m;
-        if (st && first == RV_OK) {
-            first = st;
-            ln.err = ln.jobs.size() > 1 ? "kernel " + std::to_string(j) + ": " + m : m;
+    for (size_t j = 0; j < n; j++) {
+        if (status) status[j] = sts[j];
+        if (msgs) msgs[j] = ms[j];
+        if (sts[j] && first == RV_OK) {
+            first = sts[j];
+            ln.err = n > 1 ? "kernel " + std::to_string(j) + ": " + ms[j] : ms[j];
         }
     }
     return first;
@@ -682,6 +768,8 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
         delete k;
         return fail(c, RV_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
     }
+    static std::atomic<uint64_t> serials{0};
+    k->serial = ++serials;
     k->owner = c;
     *out = k;
     return RV_OK;
@@ -769,6 +857,7 @@ rv_status rv_plan_desc(const rv_kernel_desc *desc, int32_t target, rv_kernel_inf
 rv_status rv_check(rv_ctx *c, rv_kernel *k, rv_result *out) {
     if (!c || !k || !out) return RV_ERR_INVALID;
     if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+    if (k->semantics == RV_SEM_ORDERED) return fail(c, RV_ERR_STATE, ORDERED_ONLY);
     if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
     c->err.clear();
     HIP_TRY(c, hipSetDevice(c->device));
@@ -789,15 +878,19 @@ rv_status rv_check_batch(rv_ctx *c, rv_kernel *const *ks, size_t n, rv_result *o
     for (size_t j = 0; j < n; j++) {
         if (!ks[j]) return fail(c, RV_ERR_INVALID, "null kernel in batch");
         if (ks[j]->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+        if (ks[j]->semantics == RV_SEM_ORDERED) return fail(c, RV_ERR_STATE, ORDERED_ONLY);
     }
     rv_status st = lane_enqueue(c, c->main, ks, n);
     if (st) return main_fail(c, st);
-    return main_fail(c, lane_collect(c->main, out, nullptr));
+    st = lane_collect(c->main, out, nullptr);
+    if (c->timing) c->acc.small_records += c->main.small_records;
+    return main_fail(c, st);
 }
 
 rv_status rv_check_static(rv_ctx *c, rv_kernel *k, rv_result *out) {
     if (!c || !k || !out) return RV_ERR_INVALID;
     if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+    if (k->semantics == RV_SEM_ORDERED) return fail(c, RV_ERR_STATE, ORDERED_ONLY);
     if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
     c->err.clear();
     if (!k->static_ok) return fail(c, RV_ERR_TOO_LARGE, k->static_msg);
@@ -833,6 +926,92 @@ rv_status rv_check_static(rv_ctx *c, rv_kernel *k, rv_result *out) {
     std::string m;
     st = acc.finish(*k, out, m);
     return st ? fail(c, st, m) : RV_OK;
+}
+
+rv_status rv_check_counts(rv_ctx *c, rv_kernel *k, rv_counts *out) {
+    if (!c || !k || !out) return RV_ERR_INVALID;
+    if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
+    if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
+    c->err.clear();
+    const bool ordered = k->semantics == RV_SEM_ORDERED;
+    if (!ordered && (k->semantics != RV_SEM_INTERVAL || k->has_subkeys))
+        return fail(c, RV_ERR_UNSUPPORTED, "pair counts are defined for interval semantics without warp barriers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    Lane &ln = c->main;
+    const size_t ns = k->subs.size();
+    uint64_t bound = 1;
+    for (auto &ch : k->chunks) bound = std::max<uint64_t>(bound, ch.records_bound);
+    rv_status st = grow_device(ln, ln.d_res, ln.res_cap, std::max<size_t>(ns, 1));
+    if (!st) st = grow_device(ln, ln.d_cnt, ln.cnt_cap, std::max<size_t>(ns, 1));
+    if (!st) st = grow_device(ln, ln.d_tmp, ln.tmp_cap, (size_t)bound);
+    if (st) return main_fail(c, st);
+    hipStream_t s = ln.stream;
+    launch_init_results(ln.d_res, ns, s);
+    launch_init_counts(ln.d_cnt, ns, s);
+    for (auto &ch : k->chunks) {
+        const DevSub *subs = k->d_subs + ch.sub_begin;
+        const uint32_t nsub = ch.sub_end - ch.sub_begin;
+        run_expand(c, ln, subs, nsub, ch.items, ch.buckets);
+        // counts read the buckets before the judge writes witnesses into them
+        timed(c, ln, RV_STAGE_SORT_SCAN, [&] {
+            launch_counts(subs, nsub, ch.buckets, ln.rec(), ln.d_tmp, ln.starts(), ln.counts(), ordered ? 1 : 0,
+                          ln.d_cnt, c->ncu, s);
+            if (!ordered) run_group(c, ln, subs, nsub, ch.buckets, false);
+        });
+        if (!ordered)
+            timed(c, ln, RV_STAGE_FINISH, [&] {
+                launch_finish(subs, nsub, ch.buckets, ln.conf(), ln.d_res, s);
+                launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_res, s);
+            });
+    }
+    if ((st = check_launch(ln))) return main_fail(c, st);
+    std::vector<SubResult> hr(std::max<size_t>(ns, 1));
+    std::vector<PassCounts> hc(std::max<size_t>(ns, 1));
+    if (ns) {
+        HIP_TRY(c, hipMemcpyAsync(hr.data(), ln.d_res, ns * sizeof(SubResult), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(hc.data(), ln.d_cnt, ns * sizeof(PassCounts), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    rv_counts r;
+    memset(&r, 0, sizeof r);
+    if (ordered) {
+        unsigned long long oob = ~0ull;
+        for (size_t i = 0; i < ns; i++) {
+            if (hr[i].pad) return fail(c, RV_ERR_DEVICE, "internal: a capacity of the grouping stage was exceeded");
+            r.n_records += hr[i].records;
+            oob = std::min(oob, hr[i].oob);
+        }
+        if (oob != ~0ull) {
+            // phase-major ids: the dynamic phase is the entry whose id base covers it
+            const uint32_t id = (uint32_t)oob;
+            const IntervalPlan &I = k->intervals[0];
+            uint32_t e = I.entry_begin;
+            for (uint32_t x = I.entry_begin; x < I.entry_begin + I.entry_count; x++)
+                if (k->entries[x].off <= id) e = x;
+            const DevEntry &E = k->entries[e];
+            const uint32_t g = (id - E.off) / std::max<uint32_t>(E.tmul, 1), li = (id - E.off) % std::max<uint32_t>(E.tmul, 1);
+            char buf[192];
+            snprintf(buf, sizeof buf, "index out of bounds: dynamic phase %u, block %u, thread %u, loop index %u",
+                     k->hentries[e].dphase, g / k->kc.tpb, g % k->kc.tpb, li);
+            return fail(c, RV_ERR_OOB, buf);
+        }
+    } else {
+        rv_result rr;
+        std::string m;
+        st = assemble(*k, hr.data(), &rr, m);
+        if (st) return fail(c, st, m);
+        r.n_records = rr.n_records;
+        r.n_conflicts = rr.n_conflicts;
+    }
+    for (size_t i = 0; i < ns; i++) {
+        r.n_pairs += hc[i].pairs;
+        r.n_raw += hc[i].raw;
+        r.n_waw += hc[i].waw;
+        r.n_war += hc[i].war;
+        r.n_dep_locations += hc[i].deploc;
+    }
+    *out = r;
+    return RV_OK;
 }
 
 rv_status rv_check_barriers(rv_ctx *c, rv_kernel *k, rv_barrier_result *out) {
@@ -879,6 +1058,7 @@ rv_status rv_get_witnesses(rv_ctx *c, rv_kernel *k, uint64_t first_index, rv_wit
     if (!c || !k || !n_out || (cap && !out)) return RV_ERR_INVALID;
     if (k->owner != c) return fail(c, RV_ERR_STATE, "kernel was loaded on another context");
     if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
+    if (k->semantics == RV_SEM_ORDERED) return fail(c, RV_ERR_STATE, ORDERED_ONLY);
     c->err.clear();
     *n_out = 0;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -963,6 +1143,7 @@ rv_status rv_debug_records(rv_ctx *c, rv_kernel *k, uint32_t interval, int sorte
     st = grow_device(ln, ln.d_subs, ln.subs_cap, table.size());
     if (st) return main_fail(c, st);
     hipStream_t s = ln.stream;
+    ln.tab_valid = false;    // the batch table in d_subs is overwritten
     HIP_TRY(c, hipMemcpy(ln.d_subs, table.data(), table.size() * sizeof(DevSub), hipMemcpyHostToDevice));
     launch_init_results(ln.d_res, se - sb, s);
     run_expand(c, ln, ln.d_subs, se - sb, items, buckets);
@@ -1058,7 +1239,7 @@ rv_status rv_server_create(rv_ctx *c, void *workspace, size_t budget_bytes, uint
 
 rv_status rv_server_submit(rv_server *s, rv_kernel *k, uint64_t *job_id) {
     if (!s || !k || !job_id) return RV_ERR_INVALID;
-    if (k->owner != s->c) return RV_ERR_STATE;
+    if (k->owner != s->c || k->semantics == RV_SEM_ORDERED) return RV_ERR_STATE;
     if (!fits(*k, s->lanes[0].L)) return RV_ERR_BUDGET;
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return RV_ERR_STATE;
@@ -1122,6 +1303,7 @@ rv_status rv_ctx_get_tuning(rv_ctx *c, rv_tuning *out) {
     memset(out, 0, sizeof *out);
     out->target = c->target;
     out->group = c->group;
+    out->small_cap = c->small_cap;
     return RV_OK;
 }
 
@@ -1129,8 +1311,11 @@ rv_status rv_ctx_set_tuning(rv_ctx *c, const rv_tuning *t) {
     if (!c || !t) return RV_ERR_INVALID;
     if (t->target < 64 || t->target > CAP) return fail(c, RV_ERR_INVALID, "target must be in [64, 4096]");
     if (t->group != RV_GROUP_FOLD && t->group != RV_GROUP_SORT_SCAN) return fail(c, RV_ERR_INVALID, "unknown grouping");
+    if (t->small_cap < 0 || t->small_cap > (int)SMALL_CAP)
+        return fail(c, RV_ERR_INVALID, "small_cap must be in [0, 2048]");
     c->target = t->target;
     c->group = t->group;
+    c->small_cap = t->small_cap;
     return RV_OK;
 }
 
@@ -1139,16 +1324,18 @@ rv_status rv_autotune(rv_ctx *c, const rv_kernel_desc *descs, size_t n, int32_t 
     if (c->serving) return fail(c, RV_ERR_STATE, "the context is serving");
     c->err.clear();
     HIP_TRY(c, hipSetDevice(c->device));
-    static const int cand[] = {512, 1024, 2048, 3072};
+    static const int cand[] = {1024, 2048};
     static const int groups[] = {RV_GROUP_FOLD, RV_GROUP_SORT_SCAN};
+    static const int smalls[] = {0, (int)SMALL_CAP};
     const int nc = (int)(sizeof cand / sizeof cand[0]), ng = (int)(sizeof groups / sizeof groups[0]);
+    const int nsm = (int)(sizeof smalls / sizeof smalls[0]);
     rv_tuning t;
     memset(&t, 0, sizeof t);
-    t.n_candidates = nc * ng;
+    t.n_candidates = nc * ng * nsm;
     rv_status st = RV_OK;
     std::vector<rv_result> res(std::max<size_t>(n, 1));
     int best = -1;
-    const int saved_group = c->group;
+    const int saved_group = c->group, saved_small = c->small_cap;
     for (int ci = 0; ci < nc && !st; ci++) {
         std::vector<rv_kernel *> ks;
         for (size_t j = 0; j < n && !st; j++) {
@@ -1156,11 +1343,14 @@ rv_status rv_autotune(rv_ctx *c, const rv_kernel_desc *descs, size_t n, int32_t 
             st = load_kernel(c, &descs[j], cand[ci], &k);
             if (!st) ks.push_back(k);
         }
-        for (int gi = 0; gi < ng && !st; gi++) {
-            const int q = ci * ng + gi;
+        for (int q0 = 0; q0 < ng * nsm && !st; q0++) {
+            const int gi = q0 / nsm, si = q0 % nsm;
+            const int q = ci * ng * nsm + q0;
             t.candidates[q] = cand[ci];
             t.cand_group[q] = groups[gi];
+            t.cand_small[q] = smalls[si];
             c->group = groups[gi];
+            c->small_cap = smalls[si];
             // host wall time of the whole batched check (launches, device
             // work, result readback): the quantity being traded off
             std::vector<double> ms;
@@ -1179,13 +1369,16 @@ rv_status rv_autotune(rv_ctx *c, const rv_kernel_desc *descs, size_t n, int32_t 
         for (auto k : ks) free_kernel(k);
     }
     c->group = saved_group;
+    c->small_cap = saved_small;
     if (st) return st;
     if (best >= 0) {
         c->target = t.candidates[best];
         c->group = t.cand_group[best];
+        c->small_cap = t.cand_small[best];
     }
     t.target = c->target;
     t.group = c->group;
+    t.small_cap = c->small_cap;
     *out = t;
     return RV_OK;
 }

@@ -282,7 +282,7 @@ __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, 
                 base[r] = E.row[r][C_TX] * tx + E.row[r][C_TY] * ty + E.row[r][C_BX] * bx +
                           E.row[r][C_BY] * by + E.row[r][C_C0];
             }
-            idbase = gg * S.M + E.off + lstart;
+            idbase = gg * E.tmul + E.off + lstart;
             locbase = blk * E.loc_mul + E.loc_base;
         }
         bool ok = false, inb = false;
@@ -370,7 +370,7 @@ __device__ __forceinline__ void expand_fast(CSub &S, CEnt &E, CKer &K, uint32_t 
     const uint32_t d0 = E.dim[0], d1 = E.dim[1], d2 = E.dim[2];
     const uint32_t ftx = E.fr[C_TX], fty = E.fr[C_TY], fbx = E.fr[C_BX], fby = E.fr[C_BY], fc0 = E.fr[C_C0];
     const uint32_t loc_mul = E.loc_mul, eoff = E.off;
-    const uint32_t tpb = K.tpb, bdx = K.bdx, gdx = K.gdx, nthreads = K.nthreads, M = S.M;
+    const uint32_t tpb = K.tpb, bdx = K.bdx, gdx = K.gdx, nthreads = K.nthreads, M = E.tmul;
     const Magic mg_tpb = ldm(K.mg_tpb), mg_gdx = ldm(K.mg_gdx), mg_bdx = ldm(K.mg_bdx);
     uint32_t c1 = st.c1, c2 = st.c2;
     uint32_t t0 = ts0, t1 = ts1, t2 = ts2, tl = tls;
@@ -530,7 +530,7 @@ __device__ __forceinline__ bool lin_probe(CSub &S, CEnt &E, CKer &K, uint32_t it
     L.lcnt = lcnt;
     L.hi = (loc << 1) | E.rw;
     L.dhi = dl << 1;
-    L.id = gg * S.M + E.off + st.lstart;
+    L.id = gg * E.tmul + E.off + st.lstart;
     L.live = live;
     if (!live) {
         L.n = 0;
@@ -622,8 +622,8 @@ __device__ __forceinline__ bool tlin_probe(CSub &S, CEnt &E, CKer &K, uint32_t i
     L.lcnt = lcnt;
     L.hi = (loc << 1) | E.rw;
     L.dhi = dl << 1;
-    L.id = gg * S.M + E.off;
-    L.did = S.M;
+    L.id = gg * E.tmul + E.off;
+    L.did = E.tmul;
     L.bin = b0 - mn;
     L.mn = mn;
     L.R = mx - mn + 1u;
@@ -1636,14 +1636,17 @@ __device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx,
     if (S.wshift) return judge_tables_sub<RESET>(t_mn, t_mx, t_mnw, t_mxw1, width, lo, S, wout, red);
     const Magic mgM = ldm(S.mgM);
     constexpr int TP = TBL / BKT_WG;
+    static_assert(TP == 2, "the judge packs the two halves' counts into one scan");
     const uint32_t t = threadIdx.x;
     bool c[TP];
     Seg e[TP];
     uint32_t second[TP], srw[TP];
-    uint32_t nc = 0;
+    // thread t judges locations t and t + 256 (consecutive threads read
+    // consecutive words: no bank conflicts); witnesses keep location order
+    // by placing the first half's before the second half's
 #pragma unroll
     for (int i = 0; i < TP; i++) {
-        const uint32_t k = t * TP + i;
+        const uint32_t k = t + i * BKT_WG;
         c[i] = false; second[i] = 0; srw[i] = 0;
         e[i] = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
         if (k < width) {
@@ -1653,16 +1656,13 @@ __device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx,
                 if (RESET) { t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0; }
             }
         }
-        nc += c[i] ? 1u : 0u;
     }
     uint32_t total;
-    uint32_t pos = block_excl_add<BKT_WG>(nc, red, &total);   // its barriers also order the table reads
-    if (total) {                                               // before anyone clears the tables again
-#pragma unroll
-        for (int i = 0; i < TP; i++)
-            if (c[i]) put_witness(wout, pos++, lo + t * TP + i, e[i], second[i], srw[i]);
-    }
-    return total;
+    const uint32_t pre = block_excl_add<BKT_WG>((c[0] ? 1u : 0u) | (c[1] ? 0x10000u : 0u), red, &total);
+    const uint32_t tot0 = total & 0xFFFFu;   // its barriers also order the table reads before anyone
+    if (c[0]) put_witness(wout, pre & 0xFFFFu, lo + t, e[0], second[0], srw[0]);     // clears them again
+    if (c[1]) put_witness(wout, tot0 + (pre >> 16), lo + t + BKT_WG, e[1], second[1], srw[1]);
+    return tot0 + (total >> 16);
 }
 
 // The fold deals groups of up to FOLD_GROUP consecutive buckets out
@@ -1694,7 +1694,7 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
     uint32_t sidx = sub_of_bucket(subs, nsub, r * gsz);   // groups only increase: walk forward
 #pragma unroll
     for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
-        const uint32_t k = t * (TBL / BKT_WG) + k2;
+        const uint32_t k = t + k2 * BKT_WG;
         t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
     }
     for (uint32_t base = r * gsz; base < nbuckets; base += G * gsz) {
@@ -1951,6 +1951,422 @@ __global__ void k_gather(const DevSub *subs_g, uint32_t nsub, const unsigned lon
     }
 }
 
+// ------------------------------------------------- small passes, on chip
+// A pass of at most SMALL_CAP instances is checked by one workgroup without
+// its records touching HBM.  The workgroup expands every work item of the
+// pass and folds each record into a per-location summary held in an LDS
+// hash table (open addressing on the location key, linear probing, at most
+// half full since a pass has at most SMALL_CAP locations); each lane first
+// merges its consecutive records of one location in registers.  The judge
+// then scans the table: the pass's conflict count, and the witness of its
+// smallest conflicting location.  Passes are dealt to the persistent
+// workgroups cyclically.
+constexpr uint32_t SMALL_HASH = 2 * SMALL_CAP;
+
+__device__ __forceinline__ uint32_t small_slot(uint32_t *keys, uint32_t loc, uint32_t &over) {
+    uint32_t h = (loc * 0x9E3779B1u) >> (32 - 12);        // SMALL_HASH = 4096 slots
+    for (uint32_t n = 0; n < SMALL_HASH; n++) {
+        const uint32_t k = atomicCAS(&keys[h], 0xFFFFFFFFu, loc);
+        if (k == 0xFFFFFFFFu || k == loc) return h;
+        h = (h + 1) & (SMALL_HASH - 1);
+    }
+    over = 1;
+    return 0xFFFFFFFFu;
+}
+static_assert(SMALL_HASH == 4096, "small_slot hashes to 12 bits");
+
+__global__ void __launch_bounds__(BKT_WG) k_small(const DevSub *subs_g, uint32_t nsub,
+                                                  SubResult *__restrict__ res) {
+    __shared__ uint32_t keys[SMALL_HASH], t_mn[SMALL_HASH], t_mx[SMALL_HASH], t_mnw[SMALL_HASH],
+        t_mxw1[SMALL_HASH];
+    __shared__ uint32_t red[BKT_WG / 64];
+    __shared__ uint32_t s_over, s_first;
+    __shared__ unsigned long long s_oob;
+    CSub *subs = cptr(subs_g);
+    const uint32_t t = threadIdx.x;
+    for (uint32_t j = blockIdx.x; j < nsub; j += gridDim.x) {
+        CSub &S = subs[j];
+        CKer &K = *cptr(S.kc);
+        for (uint32_t i = t; i < SMALL_HASH; i += BKT_WG) {
+            keys[i] = 0xFFFFFFFFu;
+            t_mn[i] = 0xFFFFFFFFu; t_mx[i] = 0; t_mnw[i] = 0xFFFFFFFFu; t_mxw1[i] = 0;
+        }
+        if (t == 0) { s_over = 0; s_first = 0xFFFFFFFFu; s_oob = ~0ull; }
+        __syncthreads();
+        // --- expansion, folded into the table
+        const uint32_t klo = S.klo, span = S.khi - S.klo;
+        uint32_t nrec = 0;
+        CEnt *ents = cptr(S.entries);
+        CU32 *eit = cptr(S.entry_items);
+        for (uint32_t e = 0; e < S.n_entries; e++) {
+            CEnt &E = ents[e];
+            const uint32_t ni = eit[e + 1] - eit[e];
+            const uint32_t rwbit = E.rw;
+            const uint32_t v = (E.flat ? 3u : 0u) + (E.fast == 2 ? 0u : E.fast ? 1u : 2u);
+            auto run = [&](auto variant) {
+                for (uint32_t li = 0; li < ni; li++) {
+                    Seg cur{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                    uint32_t pk = 0xFFFFFFFFu;
+                    auto flush = [&]() {
+                        if (pk == 0xFFFFFFFFu) return;
+                        const uint32_t h = small_slot(keys, pk, s_over);
+                        if (h != 0xFFFFFFFFu) fold(t_mn, t_mx, t_mnw, t_mxw1, h, cur);
+                    };
+                    expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {
+                        if (ok && !inb) atomicMin(&s_oob, ((unsigned long long)S.interval << 32) | id);
+                        if (!(ok && inb && loc - klo < span)) return;
+                        nrec++;
+                        if (loc != pk) {
+                            flush();
+                            cur = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                            pk = loc;
+                        }
+                        seg_add(cur, id, rwbit);
+                    });
+                    flush();
+                }
+            };
+            switch (v) {
+                case 0: run(Variant<0>{}); break;
+                case 1: run(Variant<1>{}); break;
+                case 2: run(Variant<2>{}); break;
+                case 3: run(Variant<3>{}); break;
+                case 4: run(Variant<4>{}); break;
+                default: run(Variant<5>{}); break;
+            }
+        }
+        uint32_t total_rec;
+        block_excl_add<BKT_WG>(nrec, red, &total_rec);      // its barriers also end the folding
+        // --- judge: count, and the smallest conflicting location
+        const Magic mgM = ldm(S.mgM);
+        uint32_t nc = 0;
+        for (uint32_t i = t; i < SMALL_HASH; i += BKT_WG) {
+            if (keys[i] == 0xFFFFFFFFu) continue;
+            const Seg x{0u, t_mn[i], t_mx[i], t_mnw[i], t_mxw1[i]};
+            uint32_t sc, sr;
+            if (judge(x, mgM, sc, sr)) { nc++; atomicMin(&s_first, keys[i]); }
+        }
+        uint32_t total;
+        block_excl_add<BKT_WG>(nc, red, &total);
+        if (total) {
+            const uint32_t fl = s_first;
+            for (uint32_t i = t; i < SMALL_HASH; i += BKT_WG) {
+                if (keys[i] != fl) continue;
+                const Seg x{0u, t_mn[i], t_mx[i], t_mnw[i], t_mxw1[i]};
+                uint32_t sc = 0, sr = 0;
+                judge(x, mgM, sc, sr);
+                SubResult &R = res[S.res];
+                R.w[0] = fl; R.w[1] = x.mnw; R.w[2] = sc; R.w[3] = sr;
+            }
+        }
+        if (t == 0) {
+            SubResult &R = res[S.res];
+            R.records += total_rec;
+            R.conflicts += total;
+            if (s_oob != ~0ull) R.oob = min(R.oob, s_oob);
+            if (s_over) R.pad = 1u;
+        }
+        __syncthreads();     // the table is reset for the next pass
+    }
+}
+
+// ----------------------------------------- exact counts per location
+// Counts that need a location's records in order: distinct-thread pairs
+// (interval semantics) and RaW / WaW / WaR (ordered semantics).  Each
+// bucket's records are ordered by a count key -- in LDS for buckets of at
+// most CNT_TILE records, by a workgroup radix sort in global memory for
+// larger ones -- and scanned tile by tile with carries:
+//  PAIRS   key = (location, thread, not rw): the first record of each
+//          (location, thread) run says whether that thread writes there;
+//          with n threads and w writers a location holds C(n,2) - C(n-w,2)
+//          unordered pairs of different threads with at least one write.
+//  ORDERED key = (location, time, rw), time = the phase-major instance id:
+//          records of one statement instance are adjacent (reads first);
+//          an instance reads the location iff its first record is a read
+//          ("R head") and writes it iff its last record is a write ("W
+//          tail").  Before an instance g of a location: eW = W tails, eR =
+//          R heads of earlier instances of that location; g adds
+//          RaW += hasR(g) eW, WaW += hasW(g) eW, WaR += hasW(g) eR.
+constexpr uint32_t CNT_TILE = 4096;
+enum { CNT_PAIRS = 0, CNT_ORDERED = 1 };
+
+__device__ __forceinline__ unsigned long long count_key(unsigned long long r, uint32_t lo, Magic mgM, int mode) {
+    const uint32_t hi = (uint32_t)(r >> 32), id = (uint32_t)r;
+    const uint32_t locl = (hi >> 1) - lo, rw = hi & 1u;
+    if (mode == CNT_PAIRS) return ((((unsigned long long)locl << 32) | udiv(id, mgM)) << 1) | (rw ^ 1u);
+    return ((unsigned long long)locl << 33) | ((unsigned long long)id << 1) | rw;
+}
+
+// Inclusive max over a wave, and the exclusive max over a workgroup of NT
+// threads (identity 0).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    v = max(v, dpp<ROW_SHR1, 0xf>(0u, v));
+    v = max(v, dpp<ROW_SHR2, 0xf>(0u, v));
+    v = max(v, dpp<ROW_SHR4, 0xf>(0u, v));
+    v = max(v, dpp<ROW_SHR8, 0xf>(0u, v));
+    v = max(v, dpp<ROW_BCAST15, 0xa>(0u, v));
+    v = max(v, dpp<ROW_BCAST31, 0xc>(0u, v));
+    return v;
+}
+
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t *red, uint32_t *total) {
+    const uint32_t wid = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_max(v);
+    const uint32_t prev_lane = __shfl_up(inc, 1);
+    if (lane() == 63) red[wid] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) {
+        const uint32_t x = red[w];
+        if (w < (int)wid) before = max(before, x);
+        tot = max(tot, x);
+    }
+    __syncthreads();
+    *total = tot;
+    return max(before, lane() ? prev_lane : 0u);
+}
+
+// State carried from one tile of a bucket's ordered records to the next.
+struct CountCarry {
+    unsigned long long prev;   // last key of the previous tile (~0: none)
+    uint32_t w_before, r_before;   // W tails / R heads before the tile (ordered)
+    uint32_t open_has_r;       // ordered: the group the tile starts inside has a read
+};
+
+struct CountTables {
+    uint32_t *a, *b, *c;       // per location: pairs n / w; ordered lstart W / lstart R / dependence flag
+};
+
+// Scan one tile of m ordered records; get(i) returns the key of record i of
+// the tile, next_key the key after the tile (~0 when the bucket ends).
+template <class Get>
+__device__ __forceinline__ void count_tile(Get &&get, uint32_t m, unsigned long long next_key, int mode,
+                                           CountCarry &cc, CountTables T, uint32_t *red,
+                                           unsigned long long &raw, unsigned long long &waw,
+                                           unsigned long long &war) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t c = (m + BKT_WG - 1) / BKT_WG;
+    const uint32_t b0 = min(m, t * c), b1 = min(m, b0 + c);
+    auto prev_of = [&](uint32_t i) { return i ? get(i - 1) : cc.prev; };
+    auto next_of = [&](uint32_t i) { return i + 1 < m ? get(i + 1) : next_key; };
+    if (mode == CNT_PAIRS) {
+        for (uint32_t i = b0; i < b1; i++) {
+            const unsigned long long k = get(i), p = prev_of(i);
+            if ((k >> 1) != (p >> 1) || p == ~0ull) {
+                const uint32_t l = (uint32_t)(k >> 33);
+                atomicAdd(&T.a[l], 1u);
+                if (!(k & 1ull)) atomicAdd(&T.b[l], 1u);
+            }
+        }
+        __syncthreads();
+        if (t == 0) cc.prev = m ? get(m - 1) : cc.prev;
+        __syncthreads();
+        return;
+    }
+    // ordered: W tails and R heads of the chunk, and its last group head
+    uint32_t cw = 0, cr = 0, last_gh = 0;
+    for (uint32_t i = b0; i < b1; i++) {
+        const unsigned long long k = get(i), p = prev_of(i), n = next_of(i);
+        const bool gh = (k >> 1) != (p >> 1) || p == ~0ull;
+        const bool gt = (k >> 1) != (n >> 1) || n == ~0ull;
+        if (gt && (k & 1ull)) cw++;
+        if (gh && !(k & 1ull)) cr++;
+        if (gh) last_gh = ((i + 1) << 1) | ((k & 1ull) ? 0u : 1u);    // (index + 1, has a read)
+    }
+    uint32_t tot;
+    const uint32_t pre = block_excl_add<BKT_WG>(cw | (cr << 16), red, &tot);
+    uint32_t gmax;
+    const uint32_t gh_before = block_excl_max<BKT_WG>(last_gh, red, &gmax);
+    // running prefixes; location heads record theirs
+    uint32_t pw = cc.w_before + (pre & 0xFFFFu), pr = cc.r_before + (pre >> 16);
+    for (uint32_t i = b0; i < b1; i++) {
+        const unsigned long long k = get(i), p = prev_of(i), n = next_of(i);
+        const bool gh = (k >> 1) != (p >> 1) || p == ~0ull;
+        const bool gt = (k >> 1) != (n >> 1) || n == ~0ull;
+        if ((k >> 33) != (p >> 33) || p == ~0ull) {
+            const uint32_t l = (uint32_t)(k >> 33);
+            T.a[l] = pw;
+            T.b[l] = pr;
+        }
+        if (gt && (k & 1ull)) pw++;
+        if (gh && !(k & 1ull)) pr++;
+    }
+    __syncthreads();
+    // contributions at the group tails
+    pw = cc.w_before + (pre & 0xFFFFu);
+    pr = cc.r_before + (pre >> 16);
+    // the group open at the chunk start: its head is the latest one before the
+    // chunk in this tile, else it began in an earlier tile
+    bool open_r = gh_before ? (gh_before & 1u) != 0u : cc.open_has_r != 0u;
+    uint32_t open_idx = gh_before ? (gh_before >> 1) - 1u : 0xFFFFFFFFu;     // tile index of the head
+    for (uint32_t i = b0; i < b1; i++) {
+        const unsigned long long k = get(i), p = prev_of(i), n = next_of(i);
+        const bool gh = (k >> 1) != (p >> 1) || p == ~0ull;
+        const bool gt = (k >> 1) != (n >> 1) || n == ~0ull;
+        if (gh) { open_r = !(k & 1ull); open_idx = i; }
+        if (gt) {
+            const uint32_t l = (uint32_t)(k >> 33);
+            const bool has_w = (k & 1ull) != 0;
+            const bool has_r = open_r;
+            // prefixes exclusive of this record; the group's own R head precedes
+            // it unless the group is this one record
+            const uint32_t ew = pw - T.a[l];
+            const uint32_t er = pr - T.b[l] - ((has_r && !(gh && open_idx == i)) ? 1u : 0u);
+            const unsigned long long d_raw = has_r ? ew : 0u, d_waw = has_w ? ew : 0u, d_war = has_w ? er : 0u;
+            raw += d_raw; waw += d_waw; war += d_war;
+            if (d_raw | d_waw | d_war) T.c[l] = 1u;
+        }
+        if (gt && (k & 1ull)) pw++;
+        if (gh && !(k & 1ull)) pr++;
+    }
+    __syncthreads();
+    if (t == 0) {
+        cc.w_before += tot & 0xFFFFu;
+        cc.r_before += tot >> 16;
+        if (gmax) cc.open_has_r = gmax & 1u;
+        if (m) cc.prev = get(m - 1);
+    }
+    __syncthreads();
+}
+
+// Stable LSD radix sort of the n records at a by their count key (8-bit
+// digits over the key's nbits, digits that every record shares skipped),
+// ping-ponging with b; one workgroup.  Returns the buffer holding the result.
+__device__ unsigned long long *wg_radix_sort(unsigned long long *a, unsigned long long *b, uint32_t n, uint32_t nbits,
+                                             uint32_t lo, Magic mgM, int mode, uint32_t *hist, uint32_t *base,
+                                             uint32_t *wcnt, uint32_t *red) {
+    const uint32_t t = threadIdx.x, w = t >> 6;
+    for (uint32_t shift = 0; shift < nbits; shift += 8) {
+        hist[t] = 0;
+        __syncthreads();
+        for (uint32_t i = t; i < n; i += BKT_WG)
+            atomicAdd(&hist[(uint32_t)(count_key(a[i], lo, mgM, mode) >> shift) & 255u], 1u);
+        __syncthreads();
+        uint32_t tot;
+        const uint32_t h = hist[t];
+        base[t] = block_excl_add<BKT_WG>(h, red, &tot);
+        const uint64_t uniform = __ballot(h == n);
+        red[w] = uniform ? 1u : 0u;            // block_excl_add is done with red
+        __syncthreads();
+        const bool skip = red[0] | red[1] | red[2] | red[3];
+        __syncthreads();
+        if (skip) continue;
+        for (uint32_t r0 = 0; r0 < n; r0 += BKT_WG) {
+            const uint32_t i = r0 + t;
+            const bool valid = i < n;
+            const unsigned long long r = valid ? a[i] : 0ull;
+            const uint32_t d = valid ? ((uint32_t)(count_key(r, lo, mgM, mode) >> shift) & 255u) : 0u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; bit++) {
+                const uint64_t m1 = __ballot(valid && ((d >> bit) & 1u));
+                peers &= ((d >> bit) & 1u) ? m1 : ~m1;
+            }
+            for (uint32_t q = t; q < 4 * 256; q += BKT_WG) wcnt[q] = 0;
+            __syncthreads();
+            const uint32_t below = (uint32_t)__popcll(peers & ((1ull << lane()) - 1ull));
+            if (valid && below == 0) wcnt[w * 256 + d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t pos = base[d] + below;
+                for (uint32_t x = 0; x < w; x++) pos += wcnt[x * 256 + d];
+                b[pos] = r;
+            }
+            __syncthreads();
+            base[t] += wcnt[t] + wcnt[256 + t] + wcnt[512 + t] + wcnt[768 + t];
+            __syncthreads();
+        }
+        unsigned long long *x = a; a = b; b = x;
+    }
+    return a;
+}
+
+__global__ void __launch_bounds__(BKT_WG) k_counts(const DevSub *subs_g, uint32_t nsub, uint32_t nbuckets,
+                                                   unsigned long long *__restrict__ rec,
+                                                   unsigned long long *__restrict__ tmp,
+                                                   const uint32_t *__restrict__ starts,
+                                                   const uint32_t *__restrict__ counts, int mode,
+                                                   PassCounts *__restrict__ out) {
+    __shared__ unsigned long long keys[CNT_TILE];
+    __shared__ uint32_t ta[TBL], tb[TBL], tc[TBL];
+    __shared__ uint32_t hist[256], base[256], wcnt[4 * 256];
+    __shared__ uint32_t red[BKT_WG / 64];
+    __shared__ CountCarry cc;
+    CSub *subs = cptr(subs_g);
+    const uint32_t t = threadIdx.x;
+    for (uint32_t bk = blockIdx.x; bk < nbuckets; bk += gridDim.x) {
+        const uint32_t cnt = counts[bk];
+        if (!cnt) continue;
+        CSub &S = subs[sub_of_bucket(subs, nsub, bk)];
+        const uint32_t lo = S.klo + ((bk - S.bucket_begin) << S.s);
+        const uint32_t width = min(1u << S.s, S.khi - lo);
+        const Magic mgM = ldm(S.mgM);
+        const uint32_t start = starts[bk];
+        for (uint32_t i = t; i < TBL; i += BKT_WG) { ta[i] = 0; tb[i] = 0; tc[i] = 0; }
+        if (t == 0) { cc.prev = ~0ull; cc.w_before = 0; cc.r_before = 0; cc.open_has_r = 0; }
+        __syncthreads();
+        unsigned long long raw = 0, waw = 0, war = 0;
+        CountTables T{ta, tb, tc};
+        if (cnt <= CNT_TILE) {
+            uint32_t np = 2;
+            while (np < cnt) np <<= 1;
+            for (uint32_t i = t; i < np; i += BKT_WG)
+                keys[i] = i < cnt ? count_key(rec[start + i], lo, mgM, mode) : ~0ull;
+            __syncthreads();
+            for (uint32_t kk = 2; kk <= np; kk <<= 1) {
+                for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (uint32_t i = t; i < np; i += BKT_WG) {
+                        const uint32_t x = i ^ jj;
+                        if (x > i) {
+                            const unsigned long long a = keys[i], b = keys[x];
+                            if ((a > b) == ((i & kk) == 0)) { keys[i] = b; keys[x] = a; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            count_tile([&](uint32_t i) { return keys[i]; }, cnt, ~0ull, mode, cc, T, red, raw, waw, war);
+        } else {
+            const uint32_t nbits = 33u + S.s;      // location bits above 33 bits of (thread or time, rw)
+            const unsigned long long *srt = wg_radix_sort(rec + start, tmp + start, cnt, nbits, lo, mgM, mode,
+                                                          hist, base, wcnt, red);
+            for (uint32_t t0 = 0; t0 < cnt; t0 += CNT_TILE) {
+                const uint32_t m = min(CNT_TILE, cnt - t0);
+                const unsigned long long nk = t0 + m < cnt ? count_key(srt[t0 + m], lo, mgM, mode) : ~0ull;
+                count_tile([&](uint32_t i) { return count_key(srt[t0 + i], lo, mgM, mode); }, m, nk, mode, cc, T,
+                           red, raw, waw, war);
+            }
+        }
+        // per-location totals and the bucket's sums into its pass
+        unsigned long long pairs = 0, deploc = 0;
+        for (uint32_t l = t; l < width; l += BKT_WG) {
+            if (mode == CNT_PAIRS) {
+                const unsigned long long n = ta[l], w = tb[l];
+                pairs += n * (n - 1) / 2 - (n - w) * (n - w - 1) / 2;
+            } else {
+                deploc += tc[l];
+            }
+        }
+        // wave sums, added into the pass's counters by each wave's lane 0
+        unsigned long long v0 = pairs, v1 = raw, v2 = waw, v3 = war, v4 = deploc;
+        for (int off = 32; off > 0; off >>= 1) {
+            v0 += __shfl_xor(v0, off); v1 += __shfl_xor(v1, off); v2 += __shfl_xor(v2, off);
+            v3 += __shfl_xor(v3, off); v4 += __shfl_xor(v4, off);
+        }
+        if (lane() == 0) {
+            PassCounts &P = out[S.res];
+            if (v0) atomicAdd(&P.pairs, v0);
+            if (v1) atomicAdd(&P.raw, v1);
+            if (v2) atomicAdd(&P.waw, v2);
+            if (v3) atomicAdd(&P.war, v3);
+            if (v4) atomicAdd(&P.deploc, v4);
+        }
+        __syncthreads();     // tables and keys are reused by the next bucket
+    }
+}
+
 // ------------------------------------------------------ barrier divergence
 // One workgroup per (guarded barrier, block) item, dealt out cyclically: the
 // threads of the block evaluate the barrier's guards into an LDS byte map,
@@ -2153,6 +2569,33 @@ void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned 
     hipLaunchKernelGGL(k_mid, dim3(ncu * occ_mid), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
     hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot,
                        res);
+}
+
+void launch_small(const DevSub *subs, uint32_t n, SubResult *res, unsigned ncu, hipStream_t st) {
+    if (!n) return;
+    static const unsigned occ = occupancy(k_small, BKT_WG, 1);
+    const unsigned grid = (unsigned)std::min<uint64_t>(n, (uint64_t)ncu * occ);
+    hipLaunchKernelGGL(k_small, dim3(grid), dim3(BKT_WG), 0, st, subs, n, res);
+}
+
+void launch_counts(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
+                   unsigned long long *tmp, const uint32_t *starts, const uint32_t *counts, int ordered,
+                   PassCounts *out, unsigned ncu, hipStream_t st) {
+    if (!nbuckets) return;
+    static const unsigned occ = occupancy(k_counts, BKT_WG, 2);
+    const unsigned grid = (unsigned)std::min<uint64_t>(nbuckets, (uint64_t)ncu * occ);
+    hipLaunchKernelGGL(k_counts, dim3(grid), dim3(BKT_WG), 0, st, subs, nsub, (uint32_t)nbuckets, rec, tmp, starts,
+                       counts, ordered ? (int)CNT_ORDERED : (int)CNT_PAIRS, out);
+}
+
+__global__ void k_fill_counts(PassCounts *p, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { PassCounts z{}; p[i] = z; }
+}
+
+void launch_init_counts(PassCounts *p, size_t n, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_counts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, (uint32_t)n);
 }
 
 __global__ void k_init_barrier_results(BarrierResult *r, uint32_t n) {

@@ -131,7 +131,7 @@ static uint32_t ceil_log2(uint64_t n) {
 rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::string &msg, int semantics) {
     rv_status st = validate(d, msg);
     if (st) return st;
-    if (semantics != RV_SEM_INTERVAL && semantics != RV_SEM_STRICT) {
+    if (semantics != RV_SEM_INTERVAL && semantics != RV_SEM_STRICT && semantics != RV_SEM_ORDERED) {
         msg = "unknown semantics"; return RV_ERR_INVALID;
     }
     k.semantics = semantics;
@@ -226,7 +226,10 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
     // blocks as the units (blocks are never ordered).
     struct Virt { uint32_t d0, d1, space_mask; bool strict_global; };
     std::vector<Virt> virt;
-    {
+    if (semantics == RV_SEM_ORDERED) {
+        // the sequential schedule: one space over every dynamic phase
+        virt.push_back(Virt{0, (uint32_t)k.dyn_phase.size(), 3u, false});
+    } else {
         uint32_t d0 = 0;
         for (uint32_t iv = 0; iv < k.n_intervals; iv++) {
             uint32_t d1 = d0;
@@ -265,6 +268,7 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
             msg = fmt("interval %lld: %lld barrier-separated parts exceed the sub-key (at most 512)", iv, nsubk);
             return RV_ERR_UNSUPPORTED;
         }
+        if (semantics == RV_SEM_ORDERED) { I.w = 0; nsubk = 1; }
         if (I.w) k.has_subkeys = true;
         auto subkey = [&](uint32_t dd) {
             return virt[iv].strict_global ? k.dyn_interval[dd] : dyn_fine[dd] - sub0;
@@ -289,9 +293,19 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
         }
         // entries
         uint64_t M = 0;
+        uint64_t obase = 0;     // ordered: id base of the dynamic phase (phase-major ids)
         for (uint32_t dd = d0; dd < d1; dd++) {
             const rv_phase &ph = k.phases[k.dyn_phase[dd]];
             const int32_t kval = k.dyn_k[dd];
+            uint64_t pbox = 0;  // ordered: the phase's statement instances per thread
+            if (semantics == RV_SEM_ORDERED) {
+                for (int a = ph.access_begin; a < ph.access_begin + ph.access_count; a++) {
+                    const rv_access &ac = k.accesses[a];
+                    uint64_t b = 1;
+                    for (int l = 0; l < ac.nloops; l++) b *= (uint64_t)((int64_t)ac.loop_hi[l] - ac.loop_lo[l]);
+                    pbox = std::max(pbox, b);
+                }
+            }
             for (int a = ph.access_begin; a < ph.access_begin + ph.access_count; a++) {
                 if (!in_space(a)) continue;
                 const rv_access &ac = k.accesses[a];
@@ -312,6 +326,10 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 E.nloops = ac.nloops;
                 E.box = (uint32_t)box;
                 E.off = (uint32_t)M;   // checked below through P
+                if (semantics == RV_SEM_ORDERED) {
+                    E.off = (uint32_t)obase;     // checked below through obase
+                    E.tmul = (uint32_t)pbox;
+                }
                 E.rw = ac.is_write ? 1u : 0u;
                 for (int j = 0; j < 3; j++) E.dim[j] = j < ar.ndim ? (uint32_t)ar.dim[j] : 1u;
                 if (ar.space == RV_SHARED) { E.loc_mul = (uint32_t)S; E.loc_base = (uint32_t)I.arr_off[ac.array]; }
@@ -447,7 +465,16 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 k.entries.push_back(E);
                 k.hentries.push_back(HostEntry{dd, (uint32_t)a, kval});
             }
+            if (semantics == RV_SEM_ORDERED) {
+                obase += pbox * nthreads;
+                if (obase >= (1ull << 32)) {
+                    msg = "the sequential schedule has 2^32 or more statement instances";
+                    return RV_ERR_TOO_LARGE;
+                }
+            }
         }
+        if (semantics != RV_SEM_ORDERED)
+            for (uint32_t e = I.entry_begin; e < (uint32_t)k.entries.size(); e++) k.entries[e].tmul = (uint32_t)M;
         I.entry_count = (uint32_t)k.entries.size() - I.entry_begin;
         I.M = M;
         I.P = M * nthreads;

@@ -28,6 +28,7 @@ constexpr int FOLD_RPL = 8;              // fold: records per lane in one slice
 constexpr uint32_t FOLD_CAP = 256 * FOLD_RPL;   // fold: buckets above this many records are medium
 constexpr uint32_t HOT = 1u << 15;       // fold: buckets above this many records are split over workgroups
 constexpr int TBL = 1 << SMAX;           // locations of one bucket (LDS table entries)
+constexpr uint32_t SMALL_CAP = 2048;     // batched check: passes of at most this many instances run on chip
 
 static_assert((1 << SMAX) % BKT_WG == 0, "bucket locations split evenly over sort+scan threads");
 static_assert(BINCAP % EXP_WG == 0, "tile bins split evenly over expansion threads");
@@ -76,7 +77,9 @@ struct DevEntry {
     uint32_t ext[3];
     uint32_t nloops;
     uint32_t box;              // loop points per thread
-    uint32_t off;              // first instance offset inside the interval's per-thread range
+    uint32_t off;              // first instance id offset (interval: inside the per-thread range)
+    uint32_t tmul;             // instance id = thread * tmul + off + loop index (interval: the
+                               // per-thread instance count M; ordered: the phase's loop box)
     uint32_t loc_mul;          // location = block * loc_mul + loc_base + flat
     uint32_t loc_base;
     uint32_t rw;
@@ -179,6 +182,14 @@ struct BarrierResult {
     uint32_t pad[2];
 };
 static_assert(sizeof(BarrierResult) == 32, "BarrierResult layout");
+
+// Per-pass exact counts (rv_check_counts): distinct-thread pairs of the
+// interval semantics, or the ordered semantics' dependences.
+struct PassCounts {
+    unsigned long long pairs, raw, waw, war, deploc;
+    unsigned long long pad[3];
+};
+static_assert(sizeof(PassCounts) == 64, "PassCounts layout");
 
 // Device witness of the collect mode: the SubResult-style words plus the pass.
 struct DevWitness {
@@ -283,6 +294,7 @@ struct rv_kernel {
     bool static_ok = false;
     std::string static_msg;          // why static_ok is false
     rv_ctx *owner = nullptr;
+    uint64_t serial = 0;             // unique per load in the process (batch table cache key)
 };
 
 namespace rv {
@@ -335,6 +347,15 @@ void launch_gather(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const u
                    unsigned long long base, unsigned long long lo, unsigned long long hi,
                    DevWitness *out, hipStream_t st);
 size_t scan_bsum_words(size_t n);
+// Exact per-location counts of a chunk's buckets (after the expansion):
+// pairs (ordered = 0) or dependences (ordered = 1) into out[pass result slot];
+// tmp holds the chunk's records again (buckets above one LDS tile sort there).
+void launch_counts(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
+                   unsigned long long *tmp, const uint32_t *starts, const uint32_t *counts, int ordered,
+                   PassCounts *out, unsigned ncu, hipStream_t st);
+void launch_init_counts(PassCounts *p, size_t n, hipStream_t st);
+// On-chip check of n small passes subs[0..n) (each at most SMALL_CAP instances).
+void launch_small(const DevSub *subs, uint32_t n, SubResult *res, unsigned ncu, hipStream_t st);
 // Divergence of the guarded barriers bars[0..n): res[0..n) receives the
 // divergent scope instances of each (its first instance included).
 void launch_barriers(const DevBarrier *bars, uint32_t n, const DevKernel *kc, const int32_t *guards,

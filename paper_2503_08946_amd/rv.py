@@ -22,7 +22,7 @@ RV_NV = 10
 STATUS = {0: "RV_OK", -1: "RV_ERR_INVALID", -2: "RV_ERR_UNSUPPORTED", -3: "RV_ERR_KEY_BITS",
           -4: "RV_ERR_RANGE", -5: "RV_ERR_OOB", -6: "RV_ERR_TOO_LARGE", -7: "RV_ERR_BUDGET",
           -8: "RV_ERR_DEVICE", -9: "RV_ERR_STATE"}
-STAGES = ("fill", "count", "scan", "expand", "sort_scan", "finish")
+STAGES = ("fill", "count", "scan", "expand", "sort_scan", "finish", "small")
 
 
 class RVError(RuntimeError):
@@ -97,7 +97,7 @@ class rv_result(ctypes.Structure):
 
 
 class rv_timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 6), ("launches", u64 * 6)]
+    _fields_ = [("ms", ctypes.c_double * 7), ("launches", u64 * 7), ("small_records", u64)]
 
 
 class rv_kernel_info(ctypes.Structure):
@@ -122,12 +122,18 @@ class rv_load_options(ctypes.Structure):
     _fields_ = [("semantics", i32), ("reserved", i32 * 3)]
 
 
-SEMANTICS = {"interval": 0, "strict": 1}
+SEMANTICS = {"interval": 0, "strict": 1, "ordered": 2}
+
+
+class rv_counts(ctypes.Structure):
+    _fields_ = [("n_records", u64), ("n_conflicts", u64), ("n_pairs", u64), ("n_raw", u64), ("n_waw", u64),
+                ("n_war", u64), ("n_dep_locations", u64)]
 
 
 class rv_tuning(ctypes.Structure):
-    _fields_ = [("target", i32), ("group", i32), ("n_candidates", i32), ("reserved", i32),
-                ("candidates", i32 * 8), ("cand_group", i32 * 8), ("ms", ctypes.c_double * 8)]
+    _fields_ = [("target", i32), ("group", i32), ("n_candidates", i32), ("small_cap", i32),
+                ("candidates", i32 * 8), ("cand_group", i32 * 8), ("cand_small", i32 * 8),
+                ("ms", ctypes.c_double * 8)]
 
 
 GROUPS = {"fold": 0, "sort_scan": 1}
@@ -167,6 +173,7 @@ def lib():
             "rv_check_batch": [V, P(V), S, P(rv_result)],
             "rv_check_static": [V, V, P(rv_result)],
             "rv_check_barriers": [V, V, P(rv_barrier_result)],
+            "rv_check_counts": [V, V, P(rv_counts)],
             "rv_get_witnesses": [V, V, u64, P(rv_witness), S, P(S)],
             "rv_debug_records": [V, V, u32, ctypes.c_int, P(rv_record), S, P(S)],
             "rv_set_timing": [V, ctypes.c_int],
@@ -195,7 +202,7 @@ def lib():
 EXPORTED = ("rv_validate_desc", "rv_plan_desc", "rv_ctx_create", "rv_ctx_destroy", "rv_last_error", "rv_load_kernel_desc",
             "rv_load_kernel_desc_ex",
             "rv_free_kernel", "rv_kernel_get_info", "rv_check", "rv_check_batch", "rv_check_static",
-            "rv_check_barriers",
+            "rv_check_barriers", "rv_check_counts",
             "rv_get_witnesses",
             "rv_debug_records", "rv_set_timing", "rv_get_timing", "rv_selftest", "rv_ctx_get_tuning",
             "rv_ctx_set_tuning", "rv_autotune", "rv_server_create",
@@ -432,8 +439,9 @@ class Context:
 
     # ---------------------------------------------------------------- API
     def load(self, desc, semantics: str = "interval") -> Kernel:
-        """Load a description; ``semantics`` "interval" (the default) or
-        "strict" (blocks are never ordered: rv_load_kernel_desc_ex)."""
+        """Load a description; ``semantics`` "interval" (the default),
+        "strict" (blocks are never ordered) or "ordered" (the sequential
+        schedule, for rv_check_counts): rv_load_kernel_desc_ex."""
         m = Marshalled(desc)
         h = ctypes.c_void_p()
         if semantics == "interval":
@@ -456,6 +464,13 @@ class Context:
         out = rv_result()
         self._call(lib().rv_check_static, self.handle, k.handle, ctypes.byref(out))
         return _result(out)
+
+    def check_counts(self, k: Kernel) -> dict:
+        """rv_check_counts: distinct-thread pairs (interval semantics) or
+        RaW / WaW / WaR dependences (a kernel loaded with semantics="ordered")."""
+        out = rv_counts()
+        self._call(lib().rv_check_counts, self.handle, k.handle, ctypes.byref(out))
+        return {name: getattr(out, name) for name, _ in rv_counts._fields_}
 
     def check_barriers(self, k: Kernel) -> dict:
         """rv_check_barriers: divergent barrier instances of a kernel."""
@@ -515,6 +530,20 @@ class Context:
         self._call(lib().rv_ctx_set_tuning, self.handle, ctypes.byref(t))
 
     @property
+    def small_cap(self) -> int:
+        """Batched checks: passes of at most this many instances run on chip."""
+        t = rv_tuning()
+        self._call(lib().rv_ctx_get_tuning, self.handle, ctypes.byref(t))
+        return t.small_cap
+
+    @small_cap.setter
+    def small_cap(self, value: int):
+        t = rv_tuning()
+        self._call(lib().rv_ctx_get_tuning, self.handle, ctypes.byref(t))
+        t.small_cap = int(value)
+        self._call(lib().rv_ctx_set_tuning, self.handle, ctypes.byref(t))
+
+    @property
     def group(self) -> str:
         """Per-bucket grouping kernel: "fold" or "sort_scan"."""
         t = rv_tuning()
@@ -546,13 +575,15 @@ class Context:
             if key in db:
                 self.target = db[key]["target"]
                 self.group = db[key]["group"]
+                self.small_cap = db[key].get("small_cap", self.small_cap)
                 return db[key]
         arr = (rv_kernel_desc * max(1, len(ms)))(*[m.desc for m in ms])
         t = rv_tuning()
         self._call(lib().rv_autotune, self.handle, arr, len(ms), int(trials), ctypes.byref(t))
         names = {v: k for k, v in GROUPS.items()}
-        rec = {"target": t.target, "group": names[t.group],
-               "ms": {f"{t.candidates[i]}/{names[t.cand_group[i]]}": t.ms[i] for i in range(t.n_candidates)}}
+        rec = {"target": t.target, "group": names[t.group], "small_cap": t.small_cap,
+               "ms": {f"{t.candidates[i]}/{names[t.cand_group[i]]}/{t.cand_small[i]}": t.ms[i]
+                      for i in range(t.n_candidates)}}
         if cache:
             db = {}
             if os.path.exists(cache):
@@ -569,7 +600,9 @@ class Context:
     def timing(self, reset: bool = True) -> dict:
         t = rv_timing()
         self._call(lib().rv_get_timing, self.handle, ctypes.byref(t), int(reset))
-        return {name: (t.ms[i], t.launches[i]) for i, name in enumerate(STAGES)}
+        out = {name: (t.ms[i], t.launches[i]) for i, name in enumerate(STAGES)}
+        out["small_records"] = t.small_records
+        return out
 
 
 @dataclass

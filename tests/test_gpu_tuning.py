@@ -39,15 +39,19 @@ def test_targets_give_identical_results():
         ks = [ctx.load(d) for d in descs]
         for group in ("fold", "sort_scan"):
             ctx.group = group
-            res = ctx.check_batch(ks)
-            for d, o, r in zip(descs, refs, res):
-                say(f"[target {target} {group}] {d.name}")
-                assert (r.n_records, r.n_conflicts) == (o.n_records, o.n_conflicts)
-                assert _wkey(r.witness) == (_wkey(o.witnesses[0]) if o.n_conflicts else None)
+            for small in (0, 1000, 2048):
+                ctx.small_cap = small
+                res = ctx.check_batch(ks)
+                for d, o, r in zip(descs, refs, res):
+                    say(f"[target {target} {group} small {small}] {d.name}")
+                    assert (r.n_records, r.n_conflicts) == (o.n_records, o.n_conflicts)
+                    assert _wkey(r.witness) == (_wkey(o.witnesses[0]) if o.n_conflicts else None)
         for k in ks:
             k.free()
     with pytest.raises(rv.RVError):
         ctx.target = 5000
+    with pytest.raises(rv.RVError):
+        ctx.small_cap = 3000
     ctx.close()
 
 
@@ -58,9 +62,9 @@ def test_autotune_and_cache(tmp_path):
     cache = str(tmp_path / "tune.json")
     rec = ctx.autotune(descs, trials=2, cache=cache)
     say(f"[autotune] {rec}")
-    assert f"{rec['target']}/{rec['group']}" in rec["ms"]
+    assert f"{rec['target']}/{rec['group']}/{rec['small_cap']}" in rec["ms"]
     assert len(rec["ms"]) == 8 and all(v > 0 for v in rec["ms"].values())
-    assert ctx.target == rec["target"] and ctx.group == rec["group"]
+    assert ctx.target == rec["target"] and ctx.group == rec["group"] and ctx.small_cap == rec["small_cap"]
     db = json.load(open(cache))
     assert len(db) == 1
     ctx.target = 2048
