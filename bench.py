@@ -238,6 +238,7 @@ def bench_batch(args, rv, torch):
     ctx.set_timing(False)
     stages = ctx.timing(reset=True)
     small_records = stages.pop("small_records") // max(1, args.steps)
+    stages.pop("direct_records")
     res = batch.results()
     assert [(r.n_records, r.n_conflicts) for r in res] == [(r.n_records, r.n_conflicts) for r in single]
     per_step = {k: v[0] / args.steps for k, v in stages.items()}
@@ -313,6 +314,7 @@ def bench_gespmm(args, rv, torch):
         ctx.set_timing(False)
         stages = ctx.timing(reset=True)
         stages.pop("small_records")
+        stages.pop("direct_records")
         k.free()
         if (r.n_records, r.n_conflicts) != (exp["records"], 0):
             raise SystemExit(f"gespmm {M}x{N} T={T} K={Kb}: {r} differs from the closed form {exp}")
@@ -467,6 +469,9 @@ def main():
     ap.add_argument("--group", choices=("fold", "sort_scan"), default="fold",
                     help="per-bucket grouping kernel")
     ap.add_argument("--target", type=int, default=2048, help="planner: mean records per location bucket")
+    ap.add_argument("--direct", type=int, choices=(0, 1), default=1,
+                    help="rv_check: group block-local (shared-array) locations on chip (1) or send every "
+                         "record through the HBM pipeline (0)")
     ap.add_argument("--small-cap", type=int, default=2048,
                     help="batched checks: passes of at most this many instances run on chip (0: off)")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="server budget (serve workload)")
@@ -513,6 +518,7 @@ def main():
     ctx = rv.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
     ctx.group = args.group
     ctx.target = args.target
+    ctx.direct = bool(args.direct)
     ks = [ctx.load(d) for d in descs]
     batch = len(ks) > 1
 
@@ -538,14 +544,16 @@ def main():
     elapsed = time.perf_counter() - t0
     ctx.set_timing(False)
     stages = ctx.timing(reset=True)
-    stages.pop("small_records")
+    small_records = stages.pop("small_records") // args.steps
+    direct_records = stages.pop("direct_records") // args.steps
     assert sum(r.n_records for r in res) == n_records
     value = n_records * args.steps / elapsed
     p50 = percentile(lat, 0.5)
     p99 = percentile(lat, 0.99)
     per_step = {k: v[0] / args.steps for k, v in stages.items()}
     log("[bench] GPU ms per step by stage: " + ", ".join(f"{k}={v:.3f}" for k, v in per_step.items()))
-    roofline = roofline_from(stages, n_records * args.steps, GROUP_KERNEL[ctx.group])
+    roofline = roofline_from(stages, (n_records - small_records - direct_records) * args.steps,
+                             GROUP_KERNEL[ctx.group])
     out = {
         "metric": "access records race-checked/sec + % HBM peak; p50/p99 verify latency",
         "value": value,
@@ -560,7 +568,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": wl_text, "records": n_records, "kernels": len(ks),
-                   "conflicts": sum(r.n_conflicts for r in res)},
+                   "conflicts": sum(r.n_conflicts for r in res), "direct": int(ctx.direct),
+                   "records_on_chip": small_records + direct_records},
         "latency_ms": {"p50": round(p50 * 1e3, 3), "p99": round(p99 * 1e3, 3)},
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "roofline": roofline,

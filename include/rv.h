@@ -166,11 +166,13 @@ typedef struct {
 /* Per-stage GPU time, accumulated while timing is enabled (HIP events on the
  * context's stream around each launch). */
 enum { RV_STAGE_FILL = 0, RV_STAGE_COUNT, RV_STAGE_SCAN, RV_STAGE_EXPAND, RV_STAGE_SORT_SCAN,
-       RV_STAGE_FINISH, RV_STAGE_SMALL /* batched passes checked on chip */, RV_NSTAGE };
+       RV_STAGE_FINISH, RV_STAGE_SMALL /* batched passes checked on chip */,
+       RV_STAGE_DIRECT /* block-local units checked on chip */, RV_NSTAGE };
 typedef struct {
     double ms[RV_NSTAGE];
     uint64_t launches[RV_NSTAGE];
     uint64_t small_records;   /* records of the batched passes checked on chip (RV_STAGE_SMALL) */
+    uint64_t direct_records;  /* records of block-local units checked on chip (RV_STAGE_DIRECT) */
 } rv_timing;
 
 /* Static facts about a loaded kernel. */
@@ -191,7 +193,9 @@ typedef struct {
     uint32_t n_proven_entries; /* of which every index is proven inside its dimension over the
                                   launch and the loop box (no per-record bounds test); a fast
                                   entry that is not proven has an out-of-bounds instance */
-    uint32_t reserved;         /* 0 */
+    uint32_t n_direct_intervals; /* intervals whose block-local (shared-array) locations are
+                                  grouped on chip, a unit of blocks per LDS table, when
+                                  rv_check runs with the tuning's `direct` on */
 } rv_kernel_info;
 
 /* A decoded record (debugging and expansion-parity tests). */
@@ -440,7 +444,17 @@ rv_status rv_get_timing(rv_ctx *ctx, rv_timing *out, int reset);
  *    instances (at most 2048; 0 turns the path off) is checked entirely on
  *    chip by one workgroup -- its records folded into an LDS hash table of
  *    per-location summaries, then judged -- instead of going through the
- *    record buffer in HBM and the bucket kernels.  Passes whose interval has warp barriers never take it. */
+ *    record buffer in HBM and the bucket kernels.  Passes whose interval has warp barriers never take it.
+ *  - `direct`, block-local spaces on chip: shared arrays are allocated per
+ *    block (Section 2, component 5), so in a barrier interval a block's
+ *    shared locations are touched by its own threads only.  With `direct`
+ *    on, rv_check groups them per unit of consecutive blocks whose shared
+ *    locations (at most 2048) fit one LDS table -- the unit's threads'
+ *    records expanded and folded into per-location summaries on chip, then
+ *    judged -- and only global-array records go through the record buffer
+ *    in HBM.  Intervals with warp barriers, and intervals whose blocks hold
+ *    more than 2048 shared elements, keep the HBM path.  rv_get_witnesses,
+ *    rv_check_counts, rv_check_static and batched checks do not use it. */
 enum {
     RV_GROUP_FOLD = 0,       /* fold records into per-location LDS tables with atomics (default) */
     RV_GROUP_SORT_SCAN = 1   /* LDS counting sort of each bucket + DPP segmented scan */
@@ -450,13 +464,16 @@ typedef struct {
     int32_t group;           /* RV_GROUP_*: how a bucket's records are grouped by location */
     int32_t n_candidates;    /* rv_autotune: candidates measured */
     int32_t small_cap;       /* batched small-pass threshold in [0, 2048]; default 2048 */
+    int32_t direct;          /* 1 (default): rv_check groups block-local locations on chip; 0: every
+                                record goes through the HBM pipeline */
+    int32_t reserved;        /* 0 */
     int32_t candidates[8];   /* rv_autotune: target of each candidate */
     int32_t cand_group[8];   /* rv_autotune: grouping of each candidate */
     int32_t cand_small[8];   /* rv_autotune: small-pass threshold of each candidate */
     double ms[8];            /* rv_autotune: median wall time of one batched check per candidate */
 } rv_tuning;
 rv_status rv_ctx_get_tuning(rv_ctx *ctx, rv_tuning *out);
-rv_status rv_ctx_set_tuning(rv_ctx *ctx, const rv_tuning *t);   /* reads target, group and small_cap */
+rv_status rv_ctx_set_tuning(rv_ctx *ctx, const rv_tuning *t);   /* reads target, group, small_cap and direct */
 /* Measure a batched check of descs[0..n) (host memory, as rv_load_kernel_desc
  * takes them) under each candidate (target in {1024, 2048}, group, small_cap
  * in {0, 2048}), `trials` timed runs after one

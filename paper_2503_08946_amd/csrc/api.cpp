@@ -41,6 +41,9 @@ struct Lane {
     size_t cnt_cap = 0;
     unsigned long long *d_tmp = nullptr;   // a second record area (rv_check_counts' large buckets)
     size_t tmp_cap = 0;
+    uint32_t *d_uwit = nullptr;   // first witness of each block-local unit of a chunk (4 words each)
+    size_t uwit_cap = 0;
+    uint64_t unit_records = 0;    // records of the last check's block-local units
     void *h_up = nullptr;       // pinned: pass tables going up
     size_t up_cap = 0;
     void *h_down = nullptr;     // pinned: results coming down
@@ -100,6 +103,7 @@ struct rv_ctx {
     std::atomic<int> target{DEFAULT_TARGET};   // planner: mean records per bucket for kernels loaded next
     std::atomic<int> group{RV_GROUP_FOLD};     // per-bucket grouping kernel (read by a server's worker)
     std::atomic<int> small_cap{(int)SMALL_CAP};   // batched passes of at most this many instances run on chip
+    std::atomic<int> direct{1};     // rv_check: block-local spaces grouped on chip
     // timing
     bool timing = false;
     struct Ev { int stage; hipEvent_t a, b; };
@@ -211,12 +215,14 @@ void lane_release(Lane &ln) {
     if (ln.d_bres) (void)hipFree(ln.d_bres);
     if (ln.d_cnt) (void)hipFree(ln.d_cnt);
     if (ln.d_tmp) (void)hipFree(ln.d_tmp);
+    if (ln.d_uwit) (void)hipFree(ln.d_uwit);
     if (ln.h_up) (void)hipHostFree(ln.h_up);
     if (ln.h_down) (void)hipHostFree(ln.h_down);
     if (ln.done) (void)hipEventDestroy(ln.done);
     ln.d_res = nullptr; ln.d_subs = nullptr; ln.d_win = nullptr; ln.d_bres = nullptr; ln.h_up = nullptr;
     ln.h_down = nullptr; ln.bres_cap = 0;
     ln.d_cnt = nullptr; ln.cnt_cap = 0; ln.d_tmp = nullptr; ln.tmp_cap = 0;
+    ln.d_uwit = nullptr; ln.uwit_cap = 0;
     ln.done = nullptr;
     ln.res_cap = ln.subs_cap = ln.win_cap = ln.up_cap = ln.down_cap = 0;
 }
@@ -249,14 +255,18 @@ void run_group(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t 
                     ln.stream);
 }
 
+// units[0..nunits): the chunk's block-local units checked on chip (their
+// passes in `subs` leave those locations out of the HBM pipeline).
 void run_check_chunk(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets,
-                     bool subkeys) {
+                     bool subkeys, const DevUnit *units = nullptr, uint32_t nunits = 0) {
     hipStream_t st = ln.stream;
+    if (nunits)
+        timed(c, ln, RV_STAGE_DIRECT, [&] { launch_direct(subs, units, nunits, ln.d_res, ln.d_uwit, c->ncu, st); });
     run_expand(c, ln, subs, nsub, items, buckets);
     timed(c, ln, RV_STAGE_SORT_SCAN, [&] { run_group(c, ln, subs, nsub, buckets, subkeys); });
     timed(c, ln, RV_STAGE_FINISH, [&] {
         launch_finish(subs, nsub, buckets, ln.conf(), ln.d_res, st);
-        launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_res, st);
+        launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_uwit, ln.d_res, st);
     });
 }
 
@@ -353,11 +363,22 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
     const bool resident = n == 1 && ks[0]->plan_cap_records == ln.L.cap_records &&
                           ks[0]->plan_cap_buckets == ln.L.cap_buckets;
     timed(c, ln, RV_STAGE_FILL, [&] { launch_init_results(ln.d_res, ns, s); });
+    ln.unit_records = 0;
     if (resident) {
         const rv_kernel *k = ks[0];
-        for (auto &ch : k->chunks)
-            run_check_chunk(c, ln, k->d_subs + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets,
-                            k->has_subkeys);
+        const bool direct = c->direct && !k->units.empty();
+        if (direct) {
+            st = grow_device(ln, ln.d_uwit, ln.uwit_cap, 4 * (size_t)k->max_chunk_units);
+            if (st) return st;
+        }
+        for (auto &ch : k->chunks) {
+            if (direct)
+                run_check_chunk(c, ln, k->d_subs_dir + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items_d,
+                                ch.buckets_d, k->has_subkeys, k->d_units + ch.unit_begin, ch.unit_end - ch.unit_begin);
+            else
+                run_check_chunk(c, ln, k->d_subs + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items, ch.buckets,
+                                k->has_subkeys);
+        }
     } else {
         // the same kernels as the last batch on this lane: its table is on the device
         std::vector<uint64_t> key(n + 1);
@@ -469,6 +490,8 @@ rv_status lane_collect(Lane &ln, rv_result *out, rv_status *status, std::string 
     const SubResult *hr = reinterpret_cast<const SubResult *>(ln.h_down);
     ln.small_records = 0;
     for (uint32_t slot : ln.small_slots) ln.small_records += hr[slot].records;
+    ln.unit_records = 0;
+    for (size_t i = 0; i < ln.ns; i++) ln.unit_records += hr[i].unit_records;
     const size_t n = ln.jobs.size();
     std::vector<rv_status> sts(n);
     std::vector<std::string> ms(n);
@@ -694,6 +717,7 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     try {
         st = plan_kernel(desc, target, *k, m, semantics);
         if (!st) st = plan_chunks(*k, c->main.L, m);
+        if (!st) plan_units(*k);
     } catch (const std::bad_alloc &) {
         st = RV_ERR_TOO_LARGE;
         m = "out of host memory";
@@ -727,9 +751,13 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     const size_t o_en = al(o_kc + sizeof(DevKernel));
     const size_t o_gr = al(o_en + k->entries.size() * sizeof(DevEntry));
     const size_t o_ei = al(o_gr + k->guard_rows.size() * sizeof(int32_t));
-    const size_t o_sb = al(o_ei + k->entry_items.size() * sizeof(uint32_t));
+    const size_t o_eg = al(o_ei + k->entry_items.size() * sizeof(uint32_t));
+    const size_t o_sb = al(o_eg + k->entry_items_g.size() * sizeof(uint32_t));
     const size_t o_ss = al(o_sb + k->subs.size() * sizeof(DevSub));
-    const size_t o_br = al(o_ss + (k->static_ok ? k->subs.size() : 0) * sizeof(DevSub));
+    const size_t o_sd = al(o_ss + (k->static_ok ? k->subs.size() : 0) * sizeof(DevSub));
+    const size_t n_dir = k->units.empty() ? 0 : k->subs.size();
+    const size_t o_un = al(o_sd + n_dir * sizeof(DevSub));
+    const size_t o_br = al(o_un + k->units.size() * sizeof(DevUnit));
     const size_t total = al(o_br + k->barriers.size() * sizeof(DevBarrier) + 1);
     hipError_t e = hipMalloc(&k->d_mem, total);
     if (e != hipSuccess) { delete k; return fail(c, RV_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e)); }
@@ -738,6 +766,9 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     k->d_entries = reinterpret_cast<DevEntry *>(base + o_en);
     k->d_guards = reinterpret_cast<int32_t *>(base + o_gr);
     k->d_entry_items = reinterpret_cast<uint32_t *>(base + o_ei);
+    k->d_entry_items_g = reinterpret_cast<uint32_t *>(base + o_eg);
+    k->d_subs_dir = n_dir ? reinterpret_cast<DevSub *>(base + o_sd) : nullptr;
+    k->d_units = k->units.empty() ? nullptr : reinterpret_cast<DevUnit *>(base + o_un);
     k->d_subs = reinterpret_cast<DevSub *>(base + o_sb);
     k->d_subs_static = k->static_ok ? reinterpret_cast<DevSub *>(base + o_ss) : nullptr;
     k->d_barriers = reinterpret_cast<DevBarrier *>(base + o_br);
@@ -747,6 +778,13 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
         make_devsubs(*k, ch.sub_begin, ch.sub_end, 0, k->h_subs, items, buckets);
         for (uint32_t i = ch.sub_begin; i < ch.sub_end; i++) k->h_subs[i].res = i;
     }
+    std::vector<DevSub> h_dir;
+    if (n_dir)
+        for (auto &ch : k->chunks) {
+            uint64_t items = 0, buckets = 0;
+            make_devsubs(*k, ch.sub_begin, ch.sub_end, 0, h_dir, items, buckets, true);
+            for (uint32_t i = ch.sub_begin; i < ch.sub_end; i++) h_dir[i].res = i;
+        }
     std::vector<DevSub> h_static;
     for (auto &ch : k->chunks_static) {
         uint64_t items = 0, buckets = 0;
@@ -758,6 +796,10 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     if (!k->entries.empty()) memcpy(host.data() + o_en, k->entries.data(), k->entries.size() * sizeof(DevEntry));
     if (!k->guard_rows.empty()) memcpy(host.data() + o_gr, k->guard_rows.data(), k->guard_rows.size() * 4);
     if (!k->entry_items.empty()) memcpy(host.data() + o_ei, k->entry_items.data(), k->entry_items.size() * 4);
+    if (!k->entry_items_g.empty())
+        memcpy(host.data() + o_eg, k->entry_items_g.data(), k->entry_items_g.size() * 4);
+    if (!h_dir.empty()) memcpy(host.data() + o_sd, h_dir.data(), h_dir.size() * sizeof(DevSub));
+    if (!k->units.empty()) memcpy(host.data() + o_un, k->units.data(), k->units.size() * sizeof(DevUnit));
     if (!k->h_subs.empty()) memcpy(host.data() + o_sb, k->h_subs.data(), k->h_subs.size() * sizeof(DevSub));
     if (!h_static.empty()) memcpy(host.data() + o_ss, h_static.data(), h_static.size() * sizeof(DevSub));
     if (!k->barriers.empty())
@@ -790,6 +832,7 @@ void fill_info(const rv_kernel &k, rv_kernel_info *out) {
         out->n_fast_entries += e.fast != 0;
         out->n_proven_entries += e.fast == 2;
     }
+    for (const auto &I : k.intervals) out->n_direct_intervals += I.direct;
 }
 
 void free_kernel(rv_kernel *k) {
@@ -865,6 +908,7 @@ rv_status rv_check(rv_ctx *c, rv_kernel *k, rv_result *out) {
     if (st) return main_fail(c, st);
     rv_result r;
     st = lane_collect(c->main, &r, nullptr);
+    if (c->timing) c->acc.direct_records += c->main.unit_records;
     if (!st) *out = r;
     return main_fail(c, st);
 }
@@ -961,7 +1005,7 @@ rv_status rv_check_counts(rv_ctx *c, rv_kernel *k, rv_counts *out) {
         if (!ordered)
             timed(c, ln, RV_STAGE_FINISH, [&] {
                 launch_finish(subs, nsub, ch.buckets, ln.conf(), ln.d_res, s);
-                launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_res, s);
+                launch_first(subs, nsub, ln.rec(), ln.starts(), nullptr, ln.d_res, s);
             });
     }
     if ((st = check_launch(ln))) return main_fail(c, st);
@@ -1304,6 +1348,7 @@ rv_status rv_ctx_get_tuning(rv_ctx *c, rv_tuning *out) {
     out->target = c->target;
     out->group = c->group;
     out->small_cap = c->small_cap;
+    out->direct = c->direct;
     return RV_OK;
 }
 
@@ -1313,9 +1358,12 @@ rv_status rv_ctx_set_tuning(rv_ctx *c, const rv_tuning *t) {
     if (t->group != RV_GROUP_FOLD && t->group != RV_GROUP_SORT_SCAN) return fail(c, RV_ERR_INVALID, "unknown grouping");
     if (t->small_cap < 0 || t->small_cap > (int)SMALL_CAP)
         return fail(c, RV_ERR_INVALID, "small_cap must be in [0, 2048]");
+    if (t->direct != 0 && t->direct != 1) return fail(c, RV_ERR_INVALID, "direct must be 0 or 1");
+    if (t->reserved) return fail(c, RV_ERR_INVALID, "reserved must be 0");
     c->target = t->target;
     c->group = t->group;
     c->small_cap = t->small_cap;
+    c->direct = t->direct;
     return RV_OK;
 }
 
@@ -1379,6 +1427,7 @@ rv_status rv_autotune(rv_ctx *c, const rv_kernel_desc *descs, size_t n, int32_t 
     t.target = c->target;
     t.group = c->group;
     t.small_cap = c->small_cap;
+    t.direct = c->direct;
     *out = t;
     return RV_OK;
 }

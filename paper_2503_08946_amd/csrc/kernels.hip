@@ -493,8 +493,16 @@ struct LinItem {
     uint64_t starts;    // lanes j that start a run of points
 };
 
+// One lane of a linear item: its lcnt points start at location loc and
+// instance id (gg * tmul + off + first point) and step by dl and by one;
+// inb: every point is inside the array (tested at the first and the last).
+struct LinLane {
+    uint32_t lcnt, loc, dl, id;
+    bool inb;
+};
+
 template <bool FLAT, bool PROVEN>
-__device__ __forceinline__ bool lin_probe(CSub &S, CEnt &E, CKer &K, uint32_t item, LinItem &L) {
+__device__ __forceinline__ LinLane lin_lane(CEnt &E, CKer &K, uint32_t item) {
     const ItemStart<FLAT> st = item_start<FLAT>(E, K, item);
     const bool gval = st.g0 < K.nthreads;
     const uint32_t gg = gval ? st.g0 : 0u;
@@ -504,24 +512,35 @@ __device__ __forceinline__ bool lin_probe(CSub &S, CEnt &E, CKer &K, uint32_t it
     const uint32_t tyy = udiv(tid, ldm(K.mg_bdx));
     const uint32_t tx = tid - tyy * K.bdx, ty = tyy, bx = blk - byy * K.gdx, by = byy;
     const uint32_t L0 = (uint32_t)E.lo[0] + st.c0, L1 = (uint32_t)E.lo[1] + st.c1, L2 = (uint32_t)E.lo[2] + st.c2;
-    const uint32_t lcnt = gval ? min(E.lch, E.box - st.lstart) : 0u;
-    const uint32_t last = lcnt - 1u;
+    LinLane r;
+    r.lcnt = gval ? min(E.lch, E.box - st.lstart) : 0u;
+    const uint32_t last = r.lcnt - 1u;
     const uint32_t inner = E.linner;
-    const uint32_t loc = blk * E.loc_mul + E.fr[C_TX] * tx + E.fr[C_TY] * ty + E.fr[C_BX] * bx +
-                         E.fr[C_BY] * by + E.fr[C_C0] + E.fr[C_L0] * L0 + E.fr[C_L1] * L1 + E.fr[C_L2] * L2;
-    const uint32_t dl = E.fr[C_L0 + inner];
+    r.loc = blk * E.loc_mul + E.fr[C_TX] * tx + E.fr[C_TY] * ty + E.fr[C_BX] * bx +
+            E.fr[C_BY] * by + E.fr[C_C0] + E.fr[C_L0] * L0 + E.fr[C_L1] * L1 + E.fr[C_L2] * L2;
+    r.dl = E.fr[C_L0 + inner];
+    r.id = gg * E.tmul + E.off + st.lstart;
     bool good = true;
     if constexpr (!PROVEN) {
 #pragma unroll
-        for (int r = 0; r < 3; r++) {
-            const uint32_t i0 = (uint32_t)E.row[r][C_TX] * tx + (uint32_t)E.row[r][C_TY] * ty +
-                                (uint32_t)E.row[r][C_BX] * bx + (uint32_t)E.row[r][C_BY] * by +
-                                (uint32_t)E.row[r][C_C0] + (uint32_t)E.row[r][C_L0] * L0 +
-                                (uint32_t)E.row[r][C_L1] * L1 + (uint32_t)E.row[r][C_L2] * L2;
-            const uint32_t iN = i0 + last * (uint32_t)E.row[r][C_L0 + inner];
-            good = good && i0 < E.dim[r] && iN < E.dim[r];
+        for (int q = 0; q < 3; q++) {
+            const uint32_t i0 = (uint32_t)E.row[q][C_TX] * tx + (uint32_t)E.row[q][C_TY] * ty +
+                                (uint32_t)E.row[q][C_BX] * bx + (uint32_t)E.row[q][C_BY] * by +
+                                (uint32_t)E.row[q][C_C0] + (uint32_t)E.row[q][C_L0] * L0 +
+                                (uint32_t)E.row[q][C_L1] * L1 + (uint32_t)E.row[q][C_L2] * L2;
+            const uint32_t iN = i0 + last * (uint32_t)E.row[q][C_L0 + inner];
+            good = good && i0 < E.dim[q] && iN < E.dim[q];
         }
     }
+    r.inb = good;
+    return r;
+}
+
+template <bool FLAT, bool PROVEN>
+__device__ __forceinline__ bool lin_probe(CSub &S, CEnt &E, CKer &K, uint32_t item, LinItem &L) {
+    const LinLane ln = lin_lane<FLAT, PROVEN>(E, K, item);
+    const uint32_t lcnt = ln.lcnt, last = lcnt - 1u, loc = ln.loc, dl = ln.dl;
+    bool good = ln.inb;
     const uint32_t span = S.khi - S.klo;
     const uint32_t r0 = loc - S.klo, rN = loc + last * dl - S.klo;
     good = lcnt == 0u || (good && r0 < span && rN < span);
@@ -530,7 +549,7 @@ __device__ __forceinline__ bool lin_probe(CSub &S, CEnt &E, CKer &K, uint32_t it
     L.lcnt = lcnt;
     L.hi = (loc << 1) | E.rw;
     L.dhi = dl << 1;
-    L.id = gg * E.tmul + E.off + st.lstart;
+    L.id = ln.id;
     L.live = live;
     if (!live) {
         L.n = 0;
@@ -699,7 +718,8 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
 __global__ void k_init_results(SubResult *r, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         SubResult z;
-        z.records = 0; z.conflicts = 0; z.oob = ~0ull; z.first_bucket = ~0u; z.pad = 0;
+        z.records = 0; z.conflicts = 0; z.oob = ~0ull; z.unit_records = 0;
+        z.first_bucket = ~0u; z.first_unit = ~0u; z.pad = 0; z.pad2 = 0;
         z.w[0] = z.w[1] = z.w[2] = z.w[3] = 0;
         r[i] = z;
     }
@@ -1911,12 +1931,21 @@ __global__ void k_finish(const DevSub *subs_g, uint32_t nsub, size_t nbuckets, c
     atomicMin(&res[slot].first_bucket, (uint32_t)b);
 }
 
+// The pass's first witness: from its first conflicting block-local unit
+// (whose locations precede every bucket's), else from its first bucket.
 __global__ void k_first(const DevSub *subs_g, uint32_t nsub, const unsigned long long *__restrict__ rec,
-                        const uint32_t *__restrict__ starts, SubResult *__restrict__ res) {
+                        const uint32_t *__restrict__ starts, const uint32_t *__restrict__ uwit,
+                        SubResult *__restrict__ res) {
     CSub *subs = cptr(subs_g);
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nsub) return;
     SubResult &R = res[subs[j].res];
+    const uint32_t fu = R.first_unit;
+    if (fu != 0xFFFFFFFFu) {
+        const uint32_t *w = uwit + 4 * (size_t)fu;
+        R.w[0] = w[0]; R.w[1] = w[1]; R.w[2] = w[2]; R.w[3] = w[3];
+        return;
+    }
     const uint32_t fb = R.first_bucket;
     if (fb == 0xFFFFFFFFu) return;
     const uint32_t *w = reinterpret_cast<const uint32_t *>(rec + starts[fb]);
@@ -2067,6 +2096,177 @@ __global__ void __launch_bounds__(BKT_WG) k_small(const DevSub *subs_g, uint32_t
             if (s_over) R.pad = 1u;
         }
         __syncthreads();     // the table is reset for the next pass
+    }
+}
+
+// ------------------------------------- block-local spaces, on chip
+// In a barrier interval, the shared-array locations of block b are the keys
+// [b * S, (b + 1) * S) (S shared elements per block), and only block b's
+// threads touch them (Section 2: shared memory is allocated per block).  So
+// a unit -- consecutive blocks whose S-ranges together fit one LDS table --
+// is grouped by location without any record reaching HBM: one workgroup
+// expands the shared entries' work items that cover the unit's threads,
+// folds each record of the unit's range into the table slot of its location
+// and judges the table, as the fold does for a bucket.  Work items at the
+// edge of the unit also hold other blocks' threads; their records fall
+// outside the range and are left to those blocks' units.
+
+// Linear items: a lane's lcnt records sit at loc + p * dl with ids id + p.
+// Lanes are in instance order, so neighbouring lanes with the same first
+// location and count hold the same locations at every point p; such a run
+// of lanes folds as one summary per point (min id: its first lane's,
+// max id: its last lane's), written by the run's first lane.  False when a
+// record of the wave is out of bounds or outside the unit (the per-record
+// path then takes the item).
+template <bool FLAT, bool PROVEN>
+__device__ __forceinline__ bool dir_lin(CEnt &E, CKer &K, uint32_t item, uint32_t ulo, uint32_t width,
+                                        uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
+                                        uint32_t &nrec) {
+    const LinLane L = lin_lane<FLAT, PROVEN>(E, K, item);
+    const uint32_t r0 = L.loc - ulo, rN = r0 + (L.lcnt - 1u) * L.dl;
+    const bool live = L.lcnt != 0u;
+    if (__ballot(live && !(L.inb && r0 < width && rN < width))) return false;
+    const uint64_t lm = __ballot(live);
+    if (!lm) return true;
+    const uint32_t j = lane();
+    const uint32_t pr = __shfl_up(r0, 1u), pc = __shfl_up(L.lcnt, 1u);
+    const bool head = live && (j == 0u || pr != r0 || pc != L.lcnt);
+    const uint64_t hm = __ballot(head);
+    // the run of a head ends before the next head, or at the last live lane
+    // (lanes without records only follow the live ones)
+    const uint64_t after = j < 63u ? hm >> (j + 1u) : 0ull;
+    const uint32_t tail = after ? j + (uint32_t)__builtin_ctzll(after) : 63u - (uint32_t)__builtin_clzll(lm);
+    const uint32_t idt = __shfl(L.id, (int)tail);
+    if (head) {
+        const uint32_t rw = E.rw;
+        if (L.dl == 0u) {
+            // one location at every point
+            atomicMin(&t_mn[r0], L.id);
+            atomicMax(&t_mx[r0], idt + L.lcnt - 1u);
+            if (rw) { atomicMin(&t_mnw[r0], L.id); atomicMax(&t_mxw1[r0], idt + L.lcnt); }
+        } else {
+            uint32_t k = r0;
+            for (uint32_t p = 0; p < L.lcnt; p++, k += L.dl) {
+                atomicMin(&t_mn[k], L.id + p);
+                atomicMax(&t_mx[k], idt + p);
+                if (rw) { atomicMin(&t_mnw[k], L.id + p); atomicMax(&t_mxw1[k], idt + p + 1u); }
+            }
+        }
+    }
+    nrec += L.lcnt;
+    return true;
+}
+
+__global__ void __launch_bounds__(BKT_WG) k_direct(const DevSub *subs_g, const DevUnit *__restrict__ units,
+                                                   uint32_t nunits, SubResult *__restrict__ res,
+                                                   uint32_t *__restrict__ uwit) {
+    __shared__ uint32_t t_mn[DIR_CAP], t_mx[DIR_CAP], t_mnw[DIR_CAP], t_mxw1[DIR_CAP];
+    __shared__ uint32_t red[BKT_WG / 64];
+    __shared__ uint32_t s_first;
+    __shared__ unsigned long long s_oob;
+    CSub *subs = cptr(subs_g);
+    const uint32_t t = threadIdx.x;
+    for (uint32_t k = t; k < DIR_CAP; k += BKT_WG) {
+        t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+    }
+    if (t == 0) { s_first = 0xFFFFFFFFu; s_oob = ~0ull; }
+    __syncthreads();
+    for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const DevUnit U = units[u];
+        CSub &S = subs[U.sub];
+        CKer &K = *cptr(S.kc);
+        const uint32_t ulo = U.lo, width = U.hi - U.lo;
+        uint32_t nrec = 0;
+        CEnt *ents = cptr(S.entries);
+        for (uint32_t e = 0; e < S.n_entries; e++) {
+            CEnt &E = ents[e];
+            if (E.loc_mul == 0u || E.n_lchunks == 0u) continue;     // global array, or an empty loop box
+            // the entry's work items holding threads [t0, t1)
+            const uint32_t nl = E.n_lchunks;
+            uint64_t ia, ib;
+            if (!E.flat) {
+                const uint32_t per = (uint32_t)EXP_WG * E.gt;
+                ia = (uint64_t)(U.t0 / per) * nl;
+                ib = (uint64_t)((U.t1 + per - 1u) / per) * nl;
+            } else {
+                const uint64_t q0 = (uint64_t)(U.t0 / E.gt) * nl;
+                const uint64_t q1 = min((uint64_t)((U.t1 + E.gt - 1u) / E.gt) * nl, (uint64_t)E.nq);
+                ia = q0 / EXP_WG;
+                ib = (q1 + EXP_WG - 1) / EXP_WG;
+            }
+            const uint32_t rwbit = E.rw;
+            const uint32_t v = (E.flat ? 3u : 0u) + (E.fast == 2 ? 0u : E.fast ? 1u : 2u);
+            auto run = [&](auto variant) {
+                constexpr int V = decltype(variant)::value;
+                for (uint32_t li = (uint32_t)ia; li < (uint32_t)ib; li++) {
+                    if constexpr (V % 3 != 2) {
+                        if (E.lin && dir_lin<(V >= 3), (V % 3 == 0)>(E, K, li, ulo, width, t_mn, t_mx, t_mnw,
+                                                                     t_mxw1, nrec))
+                            continue;
+                    }
+                    Seg cur{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                    uint32_t pk = 0xFFFFFFFFu;
+                    expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {
+                        if (ok && !inb) atomicMin(&s_oob, ((unsigned long long)S.interval << 32) | id);
+                        const uint32_t rel = loc - ulo;
+                        if (!(ok && inb && rel < width)) return;
+                        nrec++;
+                        if (rel != pk) {
+                            if (pk != 0xFFFFFFFFu) fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
+                            cur = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                            pk = rel;
+                        }
+                        seg_add(cur, id, rwbit);
+                    });
+                    if (pk != 0xFFFFFFFFu) fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
+                }
+            };
+            switch (v) {
+                case 0: run(Variant<0>{}); break;
+                case 1: run(Variant<1>{}); break;
+                case 2: run(Variant<2>{}); break;
+                case 3: run(Variant<3>{}); break;
+                case 4: run(Variant<4>{}); break;
+                default: run(Variant<5>{}); break;
+            }
+        }
+        uint32_t total_rec;
+        block_excl_add<BKT_WG>(nrec, red, &total_rec);      // its barriers also end the folding
+        // judge each location, resetting its slot; keep this thread's first conflict
+        const Magic mgM = ldm(S.mgM);
+        uint32_t nc = 0, fk = 0xFFFFFFFFu, fsc = 0, fsr = 0, fmnw = 0;
+        for (uint32_t k = t; k < width; k += BKT_WG) {
+            const Seg x{0u, t_mn[k], t_mx[k], t_mnw[k], t_mxw1[k]};
+            if (x.mn == 0xFFFFFFFFu) continue;
+            t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+            uint32_t sc, sr;
+            if (judge(x, mgM, sc, sr)) {
+                if (!nc) { fk = k; fsc = sc; fsr = sr; fmnw = x.mnw; }
+                nc++;
+            }
+        }
+        if (nc) atomicMin(&s_first, fk);
+        uint32_t total;
+        block_excl_add<BKT_WG>(nc, red, &total);           // its barriers order s_first
+        if (nc && fk == s_first) {
+            uint32_t *w = uwit + 4 * (size_t)u;
+            w[0] = ulo + fk; w[1] = fmnw; w[2] = fsc; w[3] = fsr;
+        }
+        if (t == 0) {
+            SubResult &R = res[S.res];
+            if (total_rec) {
+                atomicAdd(&R.records, (unsigned long long)total_rec);
+                atomicAdd(&R.unit_records, (unsigned long long)total_rec);
+            }
+            if (total) {
+                atomicAdd(&R.conflicts, (unsigned long long)total);
+                atomicMin(&R.first_unit, u);
+            }
+            if (s_oob != ~0ull) atomicMin(&R.oob, s_oob);
+            s_oob = ~0ull;       // no thread touches it again before this unit's last barrier
+        }
+        __syncthreads();         // every thread has read s_first
+        if (t == 0) s_first = 0xFFFFFFFFu;   // next used after the next unit's first barrier
     }
 }
 
@@ -2621,9 +2821,17 @@ void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const u
 }
 
 void launch_first(const DevSub *subs, uint32_t nsub, const unsigned long long *rec, const uint32_t *starts,
-                  SubResult *res, hipStream_t st) {
+                  const uint32_t *uwit, SubResult *res, hipStream_t st) {
     if (!nsub) return;
-    hipLaunchKernelGGL(k_first, dim3((nsub + 63) / 64), dim3(64), 0, st, subs, nsub, rec, starts, res);
+    hipLaunchKernelGGL(k_first, dim3((nsub + 63) / 64), dim3(64), 0, st, subs, nsub, rec, starts, uwit, res);
+}
+
+void launch_direct(const DevSub *subs, const DevUnit *units, uint32_t n, SubResult *res, uint32_t *uwit,
+                   unsigned ncu, hipStream_t st) {
+    if (!n) return;
+    static const unsigned occ = occupancy(k_direct, BKT_WG, 2);
+    const unsigned grid = (unsigned)std::min<uint64_t>(n, (uint64_t)ncu * occ);
+    hipLaunchKernelGGL(k_direct, dim3(grid), dim3(BKT_WG), 0, st, subs, units, n, res, uwit);
 }
 
 void launch_gather(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const unsigned long long *rec,

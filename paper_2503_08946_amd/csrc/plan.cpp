@@ -241,7 +241,7 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
     }
 
     // ---- per planned space: entries, layout, ranges, buckets
-    k.entries.clear(); k.hentries.clear(); k.entry_items.clear();
+    k.entries.clear(); k.hentries.clear(); k.entry_items.clear(); k.entry_items_g.clear();
     k.intervals.assign(virt.size(), IntervalPlan());
     k.subs.clear();
     k.n_instances = 0; k.max_interval_instances = 0; k.n_buckets = 0;
@@ -291,6 +291,12 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
             msg = fmt("interval %lld: %lld location keys do not fit 31 bits", iv, (long long)I.K);
             return RV_ERR_KEY_BITS;
         }
+        // Block-local spaces on chip are considered when the shared
+        // locations of a block (S, no sub-keys) fit one unit's LDS table; a
+        // unit then spans Tu threads (DIR_CAP / S blocks).  Ordered
+        // semantics keep one space of kernel-wide time order.
+        const bool dcand = semantics != RV_SEM_ORDERED && I.w == 0 && S > 0 && S <= DIR_CAP;
+        const uint64_t Tu = dcand ? std::max<uint64_t>(1, DIR_CAP / S) * tpb : 0;
         // entries
         uint64_t M = 0;
         uint64_t obase = 0;     // ordered: id base of the dynamic phase (phase-major ids)
@@ -427,6 +433,11 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 if (E.box > 0) {
                     E.lch = std::min<uint32_t>(E.box, RPL);
                     E.gt = RPL / E.lch;
+                    // a shared entry of a unit-checked interval: work items of
+                    // at most one unit's threads where it can, so that a unit
+                    // does not expand threads of its neighbours
+                    if (dcand && ar.space == RV_SHARED && Tu < (uint64_t)EXP_WG * E.gt)
+                        E.gt = (uint32_t)std::max<uint64_t>(1, Tu / EXP_WG);
                     E.n_lchunks = (E.box + E.lch - 1) / E.lch;
                 } else {
                     E.lch = 1; E.gt = 1; E.n_lchunks = 0;
@@ -484,21 +495,45 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
         }
         k.n_instances += I.P;
         k.max_interval_instances = std::max(k.max_interval_instances, I.P);
-        // entry work-item prefix
+        // A unit expands every work item holding one of its threads; an item
+        // of `per` threads at the unit's edges is expanded by each unit it
+        // overlaps, so a shared entry costs about (1 + per / Tu) times its
+        // records.  Units take the interval when that averages at most 2.
+        if (dcand) {
+            long double recs = 0, work = 0;
+            for (uint32_t e = 0; e < I.entry_count; e++) {
+                const DevEntry &E = k.entries[I.entry_begin + e];
+                if (E.loc_mul == 0 || E.box == 0) continue;
+                const long double per = E.flat ? std::max(1.0L, (long double)EXP_WG / E.n_lchunks) * E.gt
+                                               : (long double)EXP_WG * E.gt;
+                const long double w = (long double)E.box * (long double)nthreads;
+                recs += w;
+                work += w * (1.0L + per / (long double)Tu);
+            }
+            I.direct = recs > 0 && work <= 2.0L * recs;
+        }
+        // entry work-item prefix (and the one without the shared entries of
+        // a direct interval)
         I.items_begin = (uint32_t)k.entry_items.size();
-        uint64_t items = 0;
+        uint64_t items = 0, items_g = 0;
         for (uint32_t e = 0; e < I.entry_count; e++) {
             DevEntry &E = k.entries[I.entry_begin + e];
             k.entry_items.push_back((uint32_t)items);
+            k.entry_items_g.push_back((uint32_t)items_g);
+            uint64_t ei;
             if (E.flat) {
-                items += ((uint64_t)E.nq + EXP_WG - 1) / EXP_WG;
+                ei = ((uint64_t)E.nq + EXP_WG - 1) / EXP_WG;
             } else {
                 uint64_t per = (uint64_t)EXP_WG * E.gt;
                 uint64_t gtiles = (nthreads + per - 1) / per;
-                items += (uint64_t)E.n_lchunks * gtiles;
+                ei = (uint64_t)E.n_lchunks * gtiles;
             }
+            items += ei;
+            if (!(I.direct && E.loc_mul != 0)) items_g += ei;
         }
         k.entry_items.push_back((uint32_t)items);
+        k.entry_items_g.push_back((uint32_t)items_g);
+        I.items_g = (uint32_t)items_g;
         if (items >= (1ull << 31)) { msg = "too many work items"; return RV_ERR_TOO_LARGE; }
         I.items = (uint32_t)items;
         // buckets: aim for `target` records per bucket on average
@@ -594,15 +629,66 @@ rv_status plan_chunks(rv_kernel &k, const WorkspaceLayout &L, std::string &msg) 
     return RV_OK;
 }
 
+// The part of pass sp left to the HBM pipeline when its interval's
+// block-local spaces are checked on chip: the locations from the end of the
+// shared ones, and their buckets.
+static void hbm_range(const rv_kernel &k, const SubPlan &sp, uint32_t &klo, uint32_t &nb) {
+    const IntervalPlan &I = k.intervals[sp.interval];
+    const uint64_t shared_end = (uint64_t)k.kc.nblocks * I.S;
+    klo = (uint32_t)std::min<uint64_t>(sp.khi, std::max<uint64_t>(sp.klo, shared_end));
+    nb = (uint32_t)(((uint64_t)sp.khi - klo + (1ull << sp.s) - 1) >> sp.s);
+}
+
+void plan_units(rv_kernel &k) {
+    k.units.clear();
+    k.max_chunk_units = 0;
+    const uint32_t tpb = k.kc.tpb;
+    for (ChunkPlan &ch : k.chunks) {
+        ch.unit_begin = (uint32_t)k.units.size();
+        ch.items_d = ch.buckets_d = 0;
+        for (uint32_t i = ch.sub_begin; i < ch.sub_end; i++) {
+            const SubPlan &sp = k.subs[i];
+            const IntervalPlan &I = k.intervals[sp.interval];
+            if (!I.direct) {
+                ch.items_d += I.items;
+                ch.buckets_d += sp.nb;
+                continue;
+            }
+            uint32_t hlo, hnb;
+            hbm_range(k, sp, hlo, hnb);
+            ch.items_d += I.items_g;
+            ch.buckets_d += hnb;
+            // units of nbu consecutive blocks over the pass's shared locations [klo, hlo)
+            const uint64_t S = I.S;
+            const uint64_t nbu = std::max<uint64_t>(1, DIR_CAP / S);
+            if (sp.klo >= hlo) continue;
+            const uint64_t bf = sp.klo / S, bl = (hlo - 1) / S;
+            for (uint64_t b0 = bf; b0 <= bl; b0 += nbu) {
+                const uint64_t b1 = std::min<uint64_t>(b0 + nbu, bl + 1);
+                DevUnit U{};
+                U.sub = i - ch.sub_begin;
+                U.lo = (uint32_t)std::max<uint64_t>(sp.klo, b0 * S);
+                U.hi = (uint32_t)std::min<uint64_t>(hlo, b1 * S);
+                U.t0 = (uint32_t)(b0 * tpb);
+                U.t1 = (uint32_t)(b1 * tpb);
+                k.units.push_back(U);
+            }
+        }
+        ch.unit_end = (uint32_t)k.units.size();
+        k.max_chunk_units = std::max(k.max_chunk_units, ch.unit_end - ch.unit_begin);
+    }
+}
+
 void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0, std::vector<DevSub> &out,
-                  uint64_t &items, uint64_t &buckets) {
+                  uint64_t &items, uint64_t &buckets, bool direct) {
     for (uint32_t i = sb; i < se; i++) {
         const SubPlan &sp = k.subs[i];
         const IntervalPlan &I = k.intervals[sp.interval];
+        const bool dir = direct && I.direct;
         DevSub D{};
         D.entries = k.d_entries + I.entry_begin;
         D.guards = k.d_guards;
-        D.entry_items = k.d_entry_items + I.items_begin;
+        D.entry_items = (dir ? k.d_entry_items_g : k.d_entry_items) + I.items_begin;
         D.kc = k.d_kc;
         D.n_entries = I.entry_count;
         D.item_begin = (uint32_t)items;
@@ -611,6 +697,7 @@ void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0, s
         D.s = sp.s;
         D.klo = sp.klo;
         D.khi = sp.khi;
+        if (dir) hbm_range(k, sp, D.klo, D.nb);
         D.M = (uint32_t)I.M;
         D.mgM = make_magic((uint32_t)I.M);
         D.interval = sp.interval;
@@ -618,8 +705,8 @@ void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0, s
         D.wshift = I.w;
         D.upb = I.upb ? I.upb : 1u;
         D.mg_unit = make_magic(I.unit ? I.unit : 1u);
-        items += I.items;
-        buckets += sp.nb;
+        items += dir ? I.items_g : I.items;
+        buckets += D.nb;
         out.push_back(D);
     }
 }

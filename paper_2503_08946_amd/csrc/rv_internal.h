@@ -29,6 +29,7 @@ constexpr uint32_t FOLD_CAP = 256 * FOLD_RPL;   // fold: buckets above this many
 constexpr uint32_t HOT = 1u << 15;       // fold: buckets above this many records are split over workgroups
 constexpr int TBL = 1 << SMAX;           // locations of one bucket (LDS table entries)
 constexpr uint32_t SMALL_CAP = 2048;     // batched check: passes of at most this many instances run on chip
+constexpr uint32_t DIR_CAP = 2048;       // block-local spaces: locations of one on-chip unit's LDS table
 
 static_assert((1 << SMAX) % BKT_WG == 0, "bucket locations split evenly over sort+scan threads");
 static_assert(BINCAP % EXP_WG == 0, "tile bins split evenly over expansion threads");
@@ -151,16 +152,28 @@ struct DevSub {
     Magic mg_unit;
 };
 
+// One unit of the on-chip check of block-local spaces: the shared-array
+// locations [lo, hi) of consecutive blocks in one pass, whose records all
+// come from the threads [t0, t1) (global thread numbers); `sub` indexes the
+// chunk's pass table.
+struct DevUnit {
+    uint32_t sub, lo, hi, t0, t1;
+    uint32_t pad[3];
+};
+
 // Per-pass result slot (device).
 struct SubResult {
     unsigned long long records;
     unsigned long long conflicts;
     unsigned long long oob;        // (interval << 32) | instance id; ~0 when none
+    unsigned long long unit_records;   // records checked on chip in block-local units (part of records)
     uint32_t first_bucket;         // chunk-relative; ~0 when none
+    uint32_t first_unit;           // chunk-relative unit with the pass's first witness; ~0 when none
     uint32_t pad;                  // nonzero: an internal capacity was exceeded (the result is void)
+    uint32_t pad2;
     uint32_t w[4];                 // location, first id, second id, second is_write
 };
-static_assert(sizeof(SubResult) == 48, "SubResult layout");
+static_assert(sizeof(SubResult) == 64, "SubResult layout");
 
 // A barrier that carries guards (the threads that reach it), at one dynamic
 // phase: its scopes are the block (scope = threads per block, nscope = 1)
@@ -217,6 +230,11 @@ struct IntervalPlan {
     uint32_t dphase_begin = 0, dphase_end = 0;
     uint32_t w = 0;                // sub-key bits below the location
     uint32_t unit = 0, upb = 0;    // unordered units across sub-intervals: threads per unit, units per block
+    // Block-local spaces checked on chip: shared entries are left out of the
+    // HBM pipeline's work items (items_g counts the others) and their
+    // locations are grouped per unit of consecutive blocks in LDS.
+    bool direct = false;
+    uint32_t items_g = 0;
 };
 
 struct SubPlan {
@@ -227,6 +245,10 @@ struct SubPlan {
 struct ChunkPlan {
     uint32_t sub_begin, sub_end;
     uint64_t items, buckets, records_bound;
+    // the same passes with block-local spaces on chip: HBM work items and
+    // buckets, and the chunk's units in rv_kernel::units
+    uint64_t items_d = 0, buckets_d = 0;
+    uint32_t unit_begin = 0, unit_end = 0;
 };
 
 struct WorkspaceLayout {
@@ -267,6 +289,7 @@ struct rv_kernel {
     std::vector<rv::HostEntry> hentries;
     std::vector<int32_t> guard_rows;
     std::vector<uint32_t> entry_items;
+    std::vector<uint32_t> entry_items_g;   // the same prefixes with the shared entries of direct intervals empty
     std::vector<rv::IntervalPlan> intervals;
     std::vector<rv::SubPlan> subs;
     std::vector<rv::ChunkPlan> chunks;
@@ -284,8 +307,15 @@ struct rv_kernel {
     rv::DevEntry *d_entries = nullptr;
     int32_t *d_guards = nullptr;
     uint32_t *d_entry_items = nullptr;
+    uint32_t *d_entry_items_g = nullptr;
     rv::DevSub *d_subs = nullptr;   // all passes, begins relative to this kernel's own chunks
     std::vector<rv::DevSub> h_subs;
+    // block-local spaces on chip: the passes with shared entries left out of
+    // the HBM pipeline, and the units of each chunk
+    std::vector<rv::DevUnit> units;
+    rv::DevSub *d_subs_dir = nullptr;
+    rv::DevUnit *d_units = nullptr;
+    uint32_t max_chunk_units = 0;
     size_t plan_cap_records = 0;     // the workspace layout `chunks` was planned for
     size_t plan_cap_buckets = 0;
     // the same passes chunked for the static scratch of rv_check_static
@@ -308,8 +338,14 @@ rv_status plan_chunks(rv_kernel &k, const WorkspaceLayout &L, std::string &msg);
 // Append DevSub entries for passes [sb, se) of k.  Item and bucket begins
 // continue from *items / *buckets (relative to the chunk); pass i gets result
 // slot res0 + (i - sb).
+// direct: block-local spaces of direct intervals are checked on chip (their
+// shared entries get no work items, their buckets start after the shared
+// locations).
 void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0,
-                  std::vector<DevSub> &out, uint64_t &items, uint64_t &buckets);
+                  std::vector<DevSub> &out, uint64_t &items, uint64_t &buckets, bool direct = false);
+// Units of the block-local spaces of k's chunks (main workspace layout):
+// fills k.units and each chunk's unit range, HBM items and buckets.
+void plan_units(rv_kernel &k);
 // Decode helpers (host)
 void decode_instance(const rv_kernel &k, uint32_t interval, uint32_t id, rv_side &side,
                      uint32_t &gthread, uint32_t &lidx);
@@ -341,7 +377,12 @@ void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned 
 void launch_finish(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const uint32_t *conf,
                    SubResult *res, hipStream_t st);
 void launch_first(const DevSub *subs, uint32_t nsub, const unsigned long long *rec,
-                  const uint32_t *starts, SubResult *res, hipStream_t st);
+                  const uint32_t *starts, const uint32_t *uwit, SubResult *res, hipStream_t st);
+// On-chip check of block-local units[0..n) of a chunk (pass table subs):
+// records, conflicts and out-of-bounds instances into the passes' slots,
+// each unit's first witness into uwit[4 * unit].
+void launch_direct(const DevSub *subs, const DevUnit *units, uint32_t n, SubResult *res, uint32_t *uwit,
+                   unsigned ncu, hipStream_t st);
 void launch_gather(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const unsigned long long *rec,
                    const uint32_t *starts, const uint32_t *conf, const uint32_t *wpos,
                    unsigned long long base, unsigned long long lo, unsigned long long hi,

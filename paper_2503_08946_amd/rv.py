@@ -22,7 +22,7 @@ RV_NV = 10
 STATUS = {0: "RV_OK", -1: "RV_ERR_INVALID", -2: "RV_ERR_UNSUPPORTED", -3: "RV_ERR_KEY_BITS",
           -4: "RV_ERR_RANGE", -5: "RV_ERR_OOB", -6: "RV_ERR_TOO_LARGE", -7: "RV_ERR_BUDGET",
           -8: "RV_ERR_DEVICE", -9: "RV_ERR_STATE"}
-STAGES = ("fill", "count", "scan", "expand", "sort_scan", "finish", "small")
+STAGES = ("fill", "count", "scan", "expand", "sort_scan", "finish", "small", "direct")
 
 
 class RVError(RuntimeError):
@@ -97,14 +97,15 @@ class rv_result(ctypes.Structure):
 
 
 class rv_timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 7), ("launches", u64 * 7), ("small_records", u64)]
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", u64 * 8), ("small_records", u64),
+                ("direct_records", u64)]
 
 
 class rv_kernel_info(ctypes.Structure):
     _fields_ = [("n_instances", u64), ("n_intervals", u32), ("n_subintervals", u32),
                 ("n_chunks", u32), ("n_buckets", u32), ("max_interval_instances", u64),
                 ("n_entries", u32), ("n_flat_entries", u32), ("n_linear_entries", u32),
-                ("n_fast_entries", u32), ("n_proven_entries", u32), ("reserved", u32)]
+                ("n_fast_entries", u32), ("n_proven_entries", u32), ("n_direct_intervals", u32)]
 
 
 class rv_record(ctypes.Structure):
@@ -132,7 +133,7 @@ class rv_counts(ctypes.Structure):
 
 class rv_tuning(ctypes.Structure):
     _fields_ = [("target", i32), ("group", i32), ("n_candidates", i32), ("small_cap", i32),
-                ("candidates", i32 * 8), ("cand_group", i32 * 8), ("cand_small", i32 * 8),
+                ("direct", i32), ("reserved", i32), ("candidates", i32 * 8), ("cand_group", i32 * 8), ("cand_small", i32 * 8),
                 ("ms", ctypes.c_double * 8)]
 
 
@@ -544,6 +545,20 @@ class Context:
         self._call(lib().rv_ctx_set_tuning, self.handle, ctypes.byref(t))
 
     @property
+    def direct(self) -> bool:
+        """rv_check groups block-local (shared-array) locations on chip."""
+        t = rv_tuning()
+        self._call(lib().rv_ctx_get_tuning, self.handle, ctypes.byref(t))
+        return bool(t.direct)
+
+    @direct.setter
+    def direct(self, value: bool):
+        t = rv_tuning()
+        self._call(lib().rv_ctx_get_tuning, self.handle, ctypes.byref(t))
+        t.direct = 1 if value else 0
+        self._call(lib().rv_ctx_set_tuning, self.handle, ctypes.byref(t))
+
+    @property
     def group(self) -> str:
         """Per-bucket grouping kernel: "fold" or "sort_scan"."""
         t = rv_tuning()
@@ -602,6 +617,7 @@ class Context:
         self._call(lib().rv_get_timing, self.handle, ctypes.byref(t), int(reset))
         out = {name: (t.ms[i], t.launches[i]) for i, name in enumerate(STAGES)}
         out["small_records"] = t.small_records
+        out["direct_records"] = t.direct_records
         return out
 
 

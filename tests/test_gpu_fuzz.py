@@ -72,6 +72,7 @@ def _fuzz_one(ctx, desc):
         g = ctx.check(k)
         assert (g.n_records, g.n_conflicts) == (o.n_records, o.n_conflicts)
         if o.n_conflicts:
+            assert _wkey(g.witness) == _wkey(o.witnesses[0])
             n = min(o.n_conflicts, 1 << 16)
             assert [_wkey(w) for w in ctx.witnesses(k, 0, n)] == [_wkey(w) for w in o.witnesses[:n]]
         else:
