@@ -43,6 +43,10 @@ struct Lane {
     size_t tmp_cap = 0;
     uint32_t *d_uwit = nullptr;   // first witness of each block-local unit of a chunk (4 words each)
     size_t uwit_cap = 0;
+    // a second stream (default priority) on which the block-local units run
+    // beside the HBM pipeline, forked from and joined back into `stream`
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     uint64_t unit_records = 0;    // records of the last check's block-local units
     void *h_up = nullptr;       // pinned: pass tables going up
     size_t up_cap = 0;
@@ -159,9 +163,9 @@ hipEvent_t get_event(rv_ctx *c) {
 }
 
 template <class F>
-void timed(rv_ctx *c, const Lane &ln, int stage, F &&f) {
+void timed(rv_ctx *c, const Lane &ln, int stage, F &&f, hipStream_t on = nullptr) {
     if (c->serving || !c->timing || ln.untimed) { f(); return; }
-    hipStream_t st = ln.stream;
+    hipStream_t st = on ? on : ln.stream;
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) { f(); return; }
     (void)hipEventRecord(a, st);
@@ -216,6 +220,10 @@ void lane_release(Lane &ln) {
     if (ln.d_cnt) (void)hipFree(ln.d_cnt);
     if (ln.d_tmp) (void)hipFree(ln.d_tmp);
     if (ln.d_uwit) (void)hipFree(ln.d_uwit);
+    if (ln.side) (void)hipStreamDestroy(ln.side);
+    if (ln.fork) (void)hipEventDestroy(ln.fork);
+    if (ln.join) (void)hipEventDestroy(ln.join);
+    ln.side = nullptr; ln.fork = ln.join = nullptr;
     if (ln.h_up) (void)hipHostFree(ln.h_up);
     if (ln.h_down) (void)hipHostFree(ln.h_down);
     if (ln.done) (void)hipEventDestroy(ln.done);
@@ -257,13 +265,23 @@ void run_group(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t 
 
 // units[0..nunits): the chunk's block-local units checked on chip (their
 // passes in `subs` leave those locations out of the HBM pipeline).
+// The units run on the lane's side stream when it has one, overlapping the
+// HBM pipeline (on-chip work beside memory-bound work); both update the
+// passes' slots with atomics, and the finish waits for the units.
 void run_check_chunk(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t items, uint64_t buckets,
                      bool subkeys, const DevUnit *units = nullptr, uint32_t nunits = 0) {
     hipStream_t st = ln.stream;
+    const bool side = nunits && ln.side && hipEventRecord(ln.fork, st) == hipSuccess &&
+                      hipStreamWaitEvent(ln.side, ln.fork, 0) == hipSuccess;
+    const hipStream_t ust = side ? ln.side : st;
     if (nunits)
-        timed(c, ln, RV_STAGE_DIRECT, [&] { launch_direct(subs, units, nunits, ln.d_res, ln.d_uwit, c->ncu, st); });
+        timed(c, ln, RV_STAGE_DIRECT, [&] { launch_direct(subs, units, nunits, ln.d_res, ln.d_uwit, c->ncu, ust); },
+              ust);
+    const bool joined = side && hipEventRecord(ln.join, ln.side) == hipSuccess;
     run_expand(c, ln, subs, nsub, items, buckets);
     timed(c, ln, RV_STAGE_SORT_SCAN, [&] { run_group(c, ln, subs, nsub, buckets, subkeys); });
+    if (side && (!joined || hipStreamWaitEvent(st, ln.join, 0) != hipSuccess))
+        (void)hipStreamSynchronize(ln.side);     // the join failed: wait for the units from the host
     timed(c, ln, RV_STAGE_FINISH, [&] {
         launch_finish(subs, nsub, buckets, ln.conf(), ln.d_res, st);
         launch_first(subs, nsub, ln.rec(), ln.starts(), ln.d_uwit, ln.d_res, st);
@@ -370,6 +388,16 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
         if (direct) {
             st = grow_device(ln, ln.d_uwit, ln.uwit_cap, 4 * (size_t)k->max_chunk_units);
             if (st) return st;
+            if (!ln.side && !ln.untimed) {
+                // best effort: without a side stream the units run in line
+                if (hipStreamCreateWithFlags(&ln.side, hipStreamNonBlocking) != hipSuccess) ln.side = nullptr;
+                if (ln.side && (hipEventCreateWithFlags(&ln.fork, hipEventDisableTiming) != hipSuccess ||
+                                hipEventCreateWithFlags(&ln.join, hipEventDisableTiming) != hipSuccess)) {
+                    if (ln.fork) (void)hipEventDestroy(ln.fork);
+                    (void)hipStreamDestroy(ln.side);
+                    ln.side = nullptr; ln.fork = nullptr; ln.join = nullptr;
+                }
+            }
         }
         for (auto &ch : k->chunks) {
             if (direct)

@@ -501,25 +501,27 @@ struct LinLane {
     bool inb;
 };
 
-template <bool FLAT, bool PROVEN>
-__device__ __forceinline__ LinLane lin_lane(CEnt &E, CKer &K, uint32_t item) {
-    const ItemStart<FLAT> st = item_start<FLAT>(E, K, item);
-    const bool gval = st.g0 < K.nthreads;
-    const uint32_t gg = gval ? st.g0 : 0u;
+// The lane's records from loop point lstart (loop counters c0, c1, c2 from
+// the lower bounds) of global thread g0: at most lmax points.
+template <bool PROVEN>
+__device__ __forceinline__ LinLane lin_lane_at(CEnt &E, CKer &K, uint32_t g0, uint32_t lstart, uint32_t c0,
+                                               uint32_t c1, uint32_t c2, uint32_t lmax) {
+    const bool gval = g0 < K.nthreads;
+    const uint32_t gg = gval ? g0 : 0u;
     const uint32_t blk = udiv(gg, ldm(K.mg_tpb));
     const uint32_t tid = gg - blk * K.tpb;
     const uint32_t byy = udiv(blk, ldm(K.mg_gdx));
     const uint32_t tyy = udiv(tid, ldm(K.mg_bdx));
     const uint32_t tx = tid - tyy * K.bdx, ty = tyy, bx = blk - byy * K.gdx, by = byy;
-    const uint32_t L0 = (uint32_t)E.lo[0] + st.c0, L1 = (uint32_t)E.lo[1] + st.c1, L2 = (uint32_t)E.lo[2] + st.c2;
+    const uint32_t L0 = (uint32_t)E.lo[0] + c0, L1 = (uint32_t)E.lo[1] + c1, L2 = (uint32_t)E.lo[2] + c2;
     LinLane r;
-    r.lcnt = gval ? min(E.lch, E.box - st.lstart) : 0u;
+    r.lcnt = gval ? min(lmax, E.box - lstart) : 0u;
     const uint32_t last = r.lcnt - 1u;
     const uint32_t inner = E.linner;
     r.loc = blk * E.loc_mul + E.fr[C_TX] * tx + E.fr[C_TY] * ty + E.fr[C_BX] * bx +
             E.fr[C_BY] * by + E.fr[C_C0] + E.fr[C_L0] * L0 + E.fr[C_L1] * L1 + E.fr[C_L2] * L2;
     r.dl = E.fr[C_L0 + inner];
-    r.id = gg * E.tmul + E.off + st.lstart;
+    r.id = gg * E.tmul + E.off + lstart;
     bool good = true;
     if constexpr (!PROVEN) {
 #pragma unroll
@@ -534,6 +536,12 @@ __device__ __forceinline__ LinLane lin_lane(CEnt &E, CKer &K, uint32_t item) {
     }
     r.inb = good;
     return r;
+}
+
+template <bool FLAT, bool PROVEN>
+__device__ __forceinline__ LinLane lin_lane(CEnt &E, CKer &K, uint32_t item) {
+    const ItemStart<FLAT> st = item_start<FLAT>(E, K, item);
+    return lin_lane_at<PROVEN>(E, K, st.g0, st.lstart, st.c0, st.c1, st.c2, E.lch);
 }
 
 template <bool FLAT, bool PROVEN>
@@ -2111,48 +2119,178 @@ __global__ void __launch_bounds__(BKT_WG) k_small(const DevSub *subs_g, uint32_t
 // edge of the unit also hold other blocks' threads; their records fall
 // outside the range and are left to those blocks' units.
 
-// Linear items: a lane's lcnt records sit at loc + p * dl with ids id + p.
-// Lanes are in instance order, so neighbouring lanes with the same first
-// location and count hold the same locations at every point p; such a run
-// of lanes folds as one summary per point (min id: its first lane's,
-// max id: its last lane's), written by the run's first lane.  False when a
-// record of the wave is out of bounds or outside the unit (the per-record
-// path then takes the item).
-template <bool FLAT, bool PROVEN>
-__device__ __forceinline__ bool dir_lin(CEnt &E, CKer &K, uint32_t item, uint32_t ulo, uint32_t width,
-                                        uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
-                                        uint32_t &nrec) {
-    const LinLane L = lin_lane<FLAT, PROVEN>(E, K, item);
-    const uint32_t r0 = L.loc - ulo, rN = r0 + (L.lcnt - 1u) * L.dl;
-    const bool live = L.lcnt != 0u;
-    if (__ballot(live && !(L.inb && r0 < width && rN < width))) return false;
+// Linear records: lane j holds lcnt records at unit slots r0 + p * dl with
+// ids id + p (p < lcnt), all inside the unit.  Lanes are in instance order,
+// so neighbouring lanes with the same r0 and count hold the same locations at
+// every point p; such a run of lanes folds as one summary per point (min id:
+// its first lane's, max id: its last lane's).  With few runs each run's
+// points are spread over the lanes; with many, each run's first lane walks
+// its points.  UNIFORM: every live lane has the same count.
+template <bool UNIFORM>
+__device__ __forceinline__ void fold_lin(uint32_t r0, uint32_t lcnt, uint32_t id, uint32_t dl, uint32_t rw,
+                                         uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1) {
+    const bool live = lcnt != 0u;
     const uint64_t lm = __ballot(live);
-    if (!lm) return true;
+    if (!lm) return;
     const uint32_t j = lane();
-    const uint32_t pr = __shfl_up(r0, 1u), pc = __shfl_up(L.lcnt, 1u);
-    const bool head = live && (j == 0u || pr != r0 || pc != L.lcnt);
+    const uint32_t pr = __shfl_up(r0, 1u), pc = __shfl_up(lcnt, 1u);
+    const bool head = live && (j == 0u || pr != r0 || pc != lcnt);
     const uint64_t hm = __ballot(head);
     // the run of a head ends before the next head, or at the last live lane
     // (lanes without records only follow the live ones)
     const uint64_t after = j < 63u ? hm >> (j + 1u) : 0ull;
     const uint32_t tail = after ? j + (uint32_t)__builtin_ctzll(after) : 63u - (uint32_t)__builtin_clzll(lm);
-    const uint32_t idt = __shfl(L.id, (int)tail);
-    if (head) {
-        const uint32_t rw = E.rw;
-        if (L.dl == 0u) {
-            // one location at every point
-            atomicMin(&t_mn[r0], L.id);
-            atomicMax(&t_mx[r0], idt + L.lcnt - 1u);
-            if (rw) { atomicMin(&t_mnw[r0], L.id); atomicMax(&t_mxw1[r0], idt + L.lcnt); }
+    const uint32_t idt = __shfl(id, (int)tail);
+    if (dl == 0u) {
+        // every point of a lane at one location
+        if (head) {
+            atomicMin(&t_mn[r0], id);
+            atomicMax(&t_mx[r0], idt + lcnt - 1u);
+            if (rw) { atomicMin(&t_mnw[r0], id); atomicMax(&t_mxw1[r0], idt + lcnt); }
+        }
+        return;
+    }
+    const uint32_t nh = (uint32_t)__popcll(hm);
+    const uint32_t cnt = UNIFORM ? readlane(lcnt, (uint32_t)__builtin_ctzll(lm)) : wave_max(lcnt);
+    if (2u * nh <= cnt) {
+        for (uint64_t m = hm; m; m &= m - 1u) {
+            const uint32_t h = (uint32_t)__builtin_ctzll(m);
+            const uint32_t hr = readlane(r0, h), hid = readlane(id, h), hidt = readlane(idt, h),
+                           hc = readlane(lcnt, h);
+            for (uint32_t p = j; p < hc; p += 64u) {
+                const uint32_t k = hr + p * dl;
+                atomicMin(&t_mn[k], hid + p);
+                atomicMax(&t_mx[k], hidt + p);
+                if (rw) { atomicMin(&t_mnw[k], hid + p); atomicMax(&t_mxw1[k], hidt + p + 1u); }
+            }
+        }
+    } else if (head) {
+        uint32_t k = r0, a = id, b = idt;
+        const uint32_t n = UNIFORM ? cnt : lcnt;
+        if (rw) {
+#pragma unroll 4
+            for (uint32_t p = 0; p < n; p++, k += dl, a++, b++) {
+                atomicMin(&t_mn[k], a);
+                atomicMax(&t_mx[k], b);
+                atomicMin(&t_mnw[k], a);
+                atomicMax(&t_mxw1[k], b + 1u);
+            }
         } else {
-            uint32_t k = r0;
-            for (uint32_t p = 0; p < L.lcnt; p++, k += L.dl) {
-                atomicMin(&t_mn[k], L.id + p);
-                atomicMax(&t_mx[k], idt + p);
-                if (rw) { atomicMin(&t_mnw[k], L.id + p); atomicMax(&t_mxw1[k], idt + p + 1u); }
+#pragma unroll 4
+            for (uint32_t p = 0; p < n; p++, k += dl, a++, b++) {
+                atomicMin(&t_mn[k], a);
+                atomicMax(&t_mx[k], b);
             }
         }
     }
+}
+
+// Unit slots of a lane's linear records; false (wave-uniformly) when a
+// record of the wave is out of bounds or outside the unit.
+__device__ __forceinline__ bool lin_in_unit(const LinLane &L, uint32_t ulo, uint32_t width, uint32_t &r0) {
+    r0 = L.loc - ulo;
+    const uint32_t rN = r0 + (L.lcnt - 1u) * L.dl;
+    return !__ballot(L.lcnt != 0u && !(L.inb && r0 < width && rN < width));
+}
+
+// A linear work item of the HBM pipeline's mapping, folded on chip; false
+// when the per-record path has to take it.
+template <bool FLAT, bool PROVEN>
+__device__ __forceinline__ bool dir_lin(CEnt &E, CKer &K, uint32_t item, uint32_t ulo, uint32_t width,
+                                        uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
+                                        uint32_t &nrec) {
+    const LinLane L = lin_lane<FLAT, PROVEN>(E, K, item);
+    uint32_t r0;
+    if (!lin_in_unit(L, ulo, width, r0)) return false;
+    fold_lin<!FLAT>(r0, L.lcnt, L.id, L.dl, E.rw, t_mn, t_mx, t_mnw, t_mxw1);
+    nrec += L.lcnt;
+    return true;
+}
+
+// A thread-linear work item (one instance per thread, a lane's gt
+// consecutive threads differ in tx alone), folded on chip: lane records s <
+// lcnt at unit slot r0 + s * fr[tx] with ids id + s * tmul.  When every
+// lane's records share one slot, the wave folds them as one summary.  False
+// when a record of the wave is out of bounds or outside the unit.
+template <bool PROVEN>
+__device__ __forceinline__ bool dir_tlin(CEnt &E, CKer &K, uint32_t item, uint32_t ulo, uint32_t width,
+                                         uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
+                                         uint32_t &nrec) {
+    const ItemStart<true> st = item_start<true>(E, K, item);
+    const bool gval = st.g0 < K.nthreads;
+    const uint32_t gg = gval ? st.g0 : 0u;
+    const uint32_t blk = udiv(gg, ldm(K.mg_tpb));
+    const uint32_t tid = gg - blk * K.tpb;
+    const uint32_t byy = udiv(blk, ldm(K.mg_gdx));
+    const uint32_t tyy = udiv(tid, ldm(K.mg_bdx));
+    const uint32_t tx = tid - tyy * K.bdx, ty = tyy, bx = blk - byy * K.gdx, by = byy;
+    const uint32_t L0 = (uint32_t)E.lo[0], L1 = (uint32_t)E.lo[1], L2 = (uint32_t)E.lo[2];
+    const uint32_t lcnt = gval ? min(E.gt, K.nthreads - gg) : 0u;
+    const uint32_t loc = blk * E.loc_mul + E.fr[C_TX] * tx + E.fr[C_TY] * ty + E.fr[C_BX] * bx +
+                         E.fr[C_BY] * by + E.fr[C_C0] + E.fr[C_L0] * L0 + E.fr[C_L1] * L1 + E.fr[C_L2] * L2;
+    const uint32_t dl = E.fr[C_TX], did = E.tmul;
+    bool good = true;
+    if constexpr (!PROVEN) {
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const uint32_t i0 = (uint32_t)E.row[q][C_TX] * tx + (uint32_t)E.row[q][C_TY] * ty +
+                                (uint32_t)E.row[q][C_BX] * bx + (uint32_t)E.row[q][C_BY] * by +
+                                (uint32_t)E.row[q][C_C0] + (uint32_t)E.row[q][C_L0] * L0 +
+                                (uint32_t)E.row[q][C_L1] * L1 + (uint32_t)E.row[q][C_L2] * L2;
+            const uint32_t iN = i0 + (lcnt - 1u) * (uint32_t)E.row[q][C_TX];
+            good = good && i0 < E.dim[q] && iN < E.dim[q];
+        }
+    }
+    const uint32_t r0 = loc - ulo, rN = r0 + (lcnt - 1u) * dl;
+    if (__ballot(lcnt != 0u && !(good && r0 < width && rN < width))) return false;
+    const uint64_t lm = __ballot(lcnt != 0u);
+    if (!lm) return true;
+    const uint32_t id = gg * E.tmul + E.off, rw = E.rw;
+    if (dl == 0u) {
+        const uint32_t f = (uint32_t)__builtin_ctzll(lm), l = 63u - (uint32_t)__builtin_clzll(lm);
+        const uint32_t rf = readlane(r0, f);
+        if (!__ballot(lcnt != 0u && r0 != rf)) {
+            // the wave's records all at one location: ids increase with the lane
+            const uint32_t mn = readlane(id, f), mx = readlane(id + (lcnt - 1u) * did, l);
+            if (lane() == f) {
+                atomicMin(&t_mn[rf], mn);
+                atomicMax(&t_mx[rf], mx);
+                if (rw) { atomicMin(&t_mnw[rf], mn); atomicMax(&t_mxw1[rf], mx + 1u); }
+            }
+        } else if (lcnt) {
+            const uint32_t mx = id + (lcnt - 1u) * did;
+            atomicMin(&t_mn[r0], id);
+            atomicMax(&t_mx[r0], mx);
+            if (rw) { atomicMin(&t_mnw[r0], id); atomicMax(&t_mxw1[r0], mx + 1u); }
+        }
+    } else {
+        uint32_t k = r0, a = id;
+        if (rw) {
+            for (uint32_t q = 0; q < lcnt; q++, k += dl, a += did) {
+                atomicMin(&t_mn[k], a); atomicMax(&t_mx[k], a);
+                atomicMin(&t_mnw[k], a); atomicMax(&t_mxw1[k], a + 1u);
+            }
+        } else {
+            for (uint32_t q = 0; q < lcnt; q++, k += dl, a += did) {
+                atomicMin(&t_mn[k], a); atomicMax(&t_mx[k], a);
+            }
+        }
+    }
+    nrec += lcnt;
+    return true;
+}
+
+// A tile of 256 consecutive threads of an entry whose loop box is one loop
+// (every point of a thread is linear): lane = thread, all the box's points
+// at once.  False when the per-record path has to take the tile.
+template <bool PROVEN>
+__device__ __forceinline__ bool dir_lin_box(CEnt &E, CKer &K, uint32_t tile, uint32_t ulo, uint32_t width,
+                                            uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
+                                            uint32_t &nrec) {
+    const LinLane L = lin_lane_at<PROVEN>(E, K, tile * EXP_WG + threadIdx.x, 0u, 0u, 0u, 0u, E.box);
+    uint32_t r0;
+    if (!lin_in_unit(L, ulo, width, r0)) return false;
+    fold_lin<true>(r0, L.lcnt, L.id, L.dl, E.rw, t_mn, t_mx, t_mnw, t_mxw1);
     nrec += L.lcnt;
     return true;
 }
@@ -2198,12 +2336,7 @@ __global__ void __launch_bounds__(BKT_WG) k_direct(const DevSub *subs_g, const D
             const uint32_t v = (E.flat ? 3u : 0u) + (E.fast == 2 ? 0u : E.fast ? 1u : 2u);
             auto run = [&](auto variant) {
                 constexpr int V = decltype(variant)::value;
-                for (uint32_t li = (uint32_t)ia; li < (uint32_t)ib; li++) {
-                    if constexpr (V % 3 != 2) {
-                        if (E.lin && dir_lin<(V >= 3), (V % 3 == 0)>(E, K, li, ulo, width, t_mn, t_mx, t_mnw,
-                                                                     t_mxw1, nrec))
-                            continue;
-                    }
+                auto per_record = [&](uint32_t li) {
                     Seg cur{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
                     uint32_t pk = 0xFFFFFFFFu;
                     expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {
@@ -2219,6 +2352,28 @@ __global__ void __launch_bounds__(BKT_WG) k_direct(const DevSub *subs_g, const D
                         seg_add(cur, id, rwbit);
                     });
                     if (pk != 0xFFFFFFFFu) fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
+                };
+                if constexpr (V < 2) {
+                    // one loop with points: a tile of threads takes the whole box
+                    if (E.lin && E.box == E.ext[E.linner]) {
+                        const uint32_t ta = U.t0 / EXP_WG, tb = (U.t1 + EXP_WG - 1u) / EXP_WG;
+                        for (uint32_t tile = ta; tile < tb; tile++)
+                            if (!dir_lin_box<(V == 0)>(E, K, tile, ulo, width, t_mn, t_mx, t_mnw, t_mxw1, nrec))
+                                for (uint32_t c = 0; c < nl; c++) per_record(tile * nl + c);
+                        return;
+                    }
+                }
+                for (uint32_t li = (uint32_t)ia; li < (uint32_t)ib; li++) {
+                    if constexpr (V == 3 || V == 4) {
+                        if (E.tlin && dir_tlin<(V == 3)>(E, K, li, ulo, width, t_mn, t_mx, t_mnw, t_mxw1, nrec))
+                            continue;
+                    }
+                    if constexpr (V % 3 != 2) {
+                        if (E.lin && dir_lin<(V >= 3), (V % 3 == 0)>(E, K, li, ulo, width, t_mn, t_mx, t_mnw,
+                                                                     t_mxw1, nrec))
+                            continue;
+                    }
+                    per_record(li);
                 }
             };
             switch (v) {
