@@ -2119,35 +2119,66 @@ __global__ void __launch_bounds__(BKT_WG) k_small(const DevSub *subs_g, uint32_t
 // edge of the unit also hold other blocks' threads; their records fall
 // outside the range and are left to those blocks' units.
 
+// A unit's LDS table: per slot the smallest id, the largest 2 id + rw (the
+// largest id and whether that record writes; ids of a unit-checked interval
+// stay below 2^31) and the smallest write id.  Three words per location
+// instead of the fold's four, so six units share a CU.
+struct UnitTab {
+    uint32_t *mn, *mx2, *mnw;
+    // records of one kind (rw) at slot k with ids from a to b
+    __device__ __forceinline__ void run(uint32_t k, uint32_t a, uint32_t b, uint32_t rw) const {
+        atomicMin(&mn[k], a);
+        atomicMax(&mx2[k], 2u * b + rw);
+        if (rw) atomicMin(&mnw[k], a);
+    }
+    __device__ __forceinline__ void seg(uint32_t k, const Seg &x) const {
+        atomicMin(&mn[k], x.mn);
+        atomicMax(&mx2[k], 2u * x.mx + (x.mxw1 == x.mx + 1u ? 1u : 0u));
+        if (x.mxw1) atomicMin(&mnw[k], x.mnw);
+    }
+    // the slot as the judge reads a summary: mxw1 is max write id + 1 when
+    // the largest id writes, 0 without writes, and otherwise a value that is
+    // neither (the judge only tests it against 0 and mx + 1)
+    __device__ __forceinline__ Seg get(uint32_t k) const {
+        const uint32_t a = mn[k], m2 = mx2[k], w = mnw[k];
+        const uint32_t mx = m2 >> 1;
+        return Seg{0u, a, mx, w, w == 0xFFFFFFFFu ? 0u : ((m2 & 1u) ? mx + 1u : mx)};
+    }
+};
+
 // Linear records: lane j holds lcnt records at unit slots r0 + p * dl with
 // ids id + p (p < lcnt), all inside the unit.  Lanes are in instance order,
 // so neighbouring lanes with the same r0 and count hold the same locations at
 // every point p; such a run of lanes folds as one summary per point (min id:
-// its first lane's, max id: its last lane's).  With few runs each run's
-// points are spread over the lanes; with many, each run's first lane walks
-// its points.  UNIFORM: every live lane has the same count.
+// its first lane's, max id: its last lane's).  When the two halves of a full
+// wave hold the same locations lane for lane (two rows of a block reading
+// locations that do not depend on the row), lane j + 32 joins lane j's run,
+// its ids being the larger.  With few runs each run's points are spread over
+// the lanes; with many, the runs' points are walked by their first lanes
+// (and, for paired halves, by their upper partners, odd points).  UNIFORM:
+// every live lane has the same count.
 template <bool UNIFORM>
 __device__ __forceinline__ void fold_lin(uint32_t r0, uint32_t lcnt, uint32_t id, uint32_t dl, uint32_t rw,
-                                         uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1) {
+                                         const UnitTab &T) {
     const bool live = lcnt != 0u;
     const uint64_t lm = __ballot(live);
     if (!lm) return;
     const uint32_t j = lane();
+    bool pair = false;
+    if (UNIFORM && lm == ~0ull) pair = !__ballot(__shfl_xor(r0, 32) != r0);
     const uint32_t pr = __shfl_up(r0, 1u), pc = __shfl_up(lcnt, 1u);
-    const bool head = live && (j == 0u || pr != r0 || pc != lcnt);
+    const bool head = live && (!pair || j < 32u) && (j == 0u || pr != r0 || pc != lcnt);
     const uint64_t hm = __ballot(head);
     // the run of a head ends before the next head, or at the last live lane
-    // (lanes without records only follow the live ones)
+    // of its half (lanes without records only follow the live ones); with
+    // paired halves the run's last id is the upper partner's
     const uint64_t after = j < 63u ? hm >> (j + 1u) : 0ull;
-    const uint32_t tail = after ? j + (uint32_t)__builtin_ctzll(after) : 63u - (uint32_t)__builtin_clzll(lm);
+    const uint32_t last = pair ? 31u : 63u - (uint32_t)__builtin_clzll(lm);
+    const uint32_t tail = (after ? j + (uint32_t)__builtin_ctzll(after) : last) + (pair ? 32u : 0u);
     const uint32_t idt = __shfl(id, (int)tail);
     if (dl == 0u) {
         // every point of a lane at one location
-        if (head) {
-            atomicMin(&t_mn[r0], id);
-            atomicMax(&t_mx[r0], idt + lcnt - 1u);
-            if (rw) { atomicMin(&t_mnw[r0], id); atomicMax(&t_mxw1[r0], idt + lcnt); }
-        }
+        if (head) T.run(r0, id, idt + lcnt - 1u, rw);
         return;
     }
     const uint32_t nh = (uint32_t)__popcll(hm);
@@ -2157,29 +2188,32 @@ __device__ __forceinline__ void fold_lin(uint32_t r0, uint32_t lcnt, uint32_t id
             const uint32_t h = (uint32_t)__builtin_ctzll(m);
             const uint32_t hr = readlane(r0, h), hid = readlane(id, h), hidt = readlane(idt, h),
                            hc = readlane(lcnt, h);
-            for (uint32_t p = j; p < hc; p += 64u) {
-                const uint32_t k = hr + p * dl;
-                atomicMin(&t_mn[k], hid + p);
-                atomicMax(&t_mx[k], hidt + p);
-                if (rw) { atomicMin(&t_mnw[k], hid + p); atomicMax(&t_mxw1[k], hidt + p + 1u); }
-            }
+            for (uint32_t p = j; p < hc; p += 64u) T.run(hr + p * dl, hid + p, hidt + p, rw);
         }
-    } else if (head) {
-        uint32_t k = r0, a = id, b = idt;
+        return;
+    }
+    // many runs: lane j walks the points p = p0, p0 + ps, ... of the run
+    // headed by lane hl
+    const uint32_t hl = pair ? (j & 31u) : j;
+    const uint32_t p0 = pair ? (j >> 5) : 0u, ps = pair ? 2u : 1u;
+    const uint32_t hr = pair ? __shfl(r0, (int)hl) : r0, hid = pair ? __shfl(id, (int)hl) : id,
+                   hidt = pair ? __shfl(idt, (int)hl) : idt;
+    if ((hm >> hl) & 1u) {
         const uint32_t n = UNIFORM ? cnt : lcnt;
+        uint32_t k = hr + p0 * dl, a = hid + p0, b2 = 2u * (hidt + p0) + rw;
+        const uint32_t dk = ps * dl, db2 = 2u * ps;
         if (rw) {
 #pragma unroll 4
-            for (uint32_t p = 0; p < n; p++, k += dl, a++, b++) {
-                atomicMin(&t_mn[k], a);
-                atomicMax(&t_mx[k], b);
-                atomicMin(&t_mnw[k], a);
-                atomicMax(&t_mxw1[k], b + 1u);
+            for (uint32_t p = p0; p < n; p += ps, k += dk, a += ps, b2 += db2) {
+                atomicMin(&T.mn[k], a);
+                atomicMax(&T.mx2[k], b2);
+                atomicMin(&T.mnw[k], a);
             }
         } else {
 #pragma unroll 4
-            for (uint32_t p = 0; p < n; p++, k += dl, a++, b++) {
-                atomicMin(&t_mn[k], a);
-                atomicMax(&t_mx[k], b);
+            for (uint32_t p = p0; p < n; p += ps, k += dk, a += ps, b2 += db2) {
+                atomicMin(&T.mn[k], a);
+                atomicMax(&T.mx2[k], b2);
             }
         }
     }
@@ -2197,28 +2231,29 @@ __device__ __forceinline__ bool lin_in_unit(const LinLane &L, uint32_t ulo, uint
 // when the per-record path has to take it.
 template <bool FLAT, bool PROVEN>
 __device__ __forceinline__ bool dir_lin(CEnt &E, CKer &K, uint32_t item, uint32_t ulo, uint32_t width,
-                                        uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
-                                        uint32_t &nrec) {
+                                        const UnitTab &T, uint32_t &nrec) {
     const LinLane L = lin_lane<FLAT, PROVEN>(E, K, item);
     uint32_t r0;
     if (!lin_in_unit(L, ulo, width, r0)) return false;
-    fold_lin<!FLAT>(r0, L.lcnt, L.id, L.dl, E.rw, t_mn, t_mx, t_mnw, t_mxw1);
+    fold_lin<!FLAT>(r0, L.lcnt, L.id, L.dl, E.rw, T);
     nrec += L.lcnt;
     return true;
 }
 
 // A thread-linear work item (one instance per thread, a lane's gt
-// consecutive threads differ in tx alone), folded on chip: lane records s <
-// lcnt at unit slot r0 + s * fr[tx] with ids id + s * tmul.  When every
-// lane's records share one slot, the wave folds them as one summary.  False
-// when a record of the wave is out of bounds or outside the unit.
+// consecutive threads differ in tx alone; the loop box is one point), folded
+// on chip: lane records s < lcnt at unit slot r0 + s * fr[tx] with ids id +
+// s * tmul.  When every lane's records share one slot, the wave folds them
+// as one summary.  False when a record of the wave is out of bounds or
+// outside the unit.
 template <bool PROVEN>
 __device__ __forceinline__ bool dir_tlin(CEnt &E, CKer &K, uint32_t item, uint32_t ulo, uint32_t width,
-                                         uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
-                                         uint32_t &nrec) {
-    const ItemStart<true> st = item_start<true>(E, K, item);
-    const bool gval = st.g0 < K.nthreads;
-    const uint32_t gg = gval ? st.g0 : 0u;
+                                         const UnitTab &T, uint32_t &nrec) {
+    // flat mapping with one loop chunk: lane q of the entry takes threads q gt ..
+    const uint32_t q = item * EXP_WG + threadIdx.x;
+    const uint32_t g0 = q < E.nq ? q * E.gt : K.nthreads;
+    const bool gval = g0 < K.nthreads;
+    const uint32_t gg = gval ? g0 : 0u;
     const uint32_t blk = udiv(gg, ldm(K.mg_tpb));
     const uint32_t tid = gg - blk * K.tpb;
     const uint32_t byy = udiv(blk, ldm(K.mg_gdx));
@@ -2232,13 +2267,13 @@ __device__ __forceinline__ bool dir_tlin(CEnt &E, CKer &K, uint32_t item, uint32
     bool good = true;
     if constexpr (!PROVEN) {
 #pragma unroll
-        for (int q = 0; q < 3; q++) {
-            const uint32_t i0 = (uint32_t)E.row[q][C_TX] * tx + (uint32_t)E.row[q][C_TY] * ty +
-                                (uint32_t)E.row[q][C_BX] * bx + (uint32_t)E.row[q][C_BY] * by +
-                                (uint32_t)E.row[q][C_C0] + (uint32_t)E.row[q][C_L0] * L0 +
-                                (uint32_t)E.row[q][C_L1] * L1 + (uint32_t)E.row[q][C_L2] * L2;
-            const uint32_t iN = i0 + (lcnt - 1u) * (uint32_t)E.row[q][C_TX];
-            good = good && i0 < E.dim[q] && iN < E.dim[q];
+        for (int r = 0; r < 3; r++) {
+            const uint32_t i0 = (uint32_t)E.row[r][C_TX] * tx + (uint32_t)E.row[r][C_TY] * ty +
+                                (uint32_t)E.row[r][C_BX] * bx + (uint32_t)E.row[r][C_BY] * by +
+                                (uint32_t)E.row[r][C_C0] + (uint32_t)E.row[r][C_L0] * L0 +
+                                (uint32_t)E.row[r][C_L1] * L1 + (uint32_t)E.row[r][C_L2] * L2;
+            const uint32_t iN = i0 + (lcnt - 1u) * (uint32_t)E.row[r][C_TX];
+            good = good && i0 < E.dim[r] && iN < E.dim[r];
         }
     }
     const uint32_t r0 = loc - ulo, rN = r0 + (lcnt - 1u) * dl;
@@ -2252,29 +2287,13 @@ __device__ __forceinline__ bool dir_tlin(CEnt &E, CKer &K, uint32_t item, uint32
         if (!__ballot(lcnt != 0u && r0 != rf)) {
             // the wave's records all at one location: ids increase with the lane
             const uint32_t mn = readlane(id, f), mx = readlane(id + (lcnt - 1u) * did, l);
-            if (lane() == f) {
-                atomicMin(&t_mn[rf], mn);
-                atomicMax(&t_mx[rf], mx);
-                if (rw) { atomicMin(&t_mnw[rf], mn); atomicMax(&t_mxw1[rf], mx + 1u); }
-            }
+            if (lane() == f) T.run(rf, mn, mx, rw);
         } else if (lcnt) {
-            const uint32_t mx = id + (lcnt - 1u) * did;
-            atomicMin(&t_mn[r0], id);
-            atomicMax(&t_mx[r0], mx);
-            if (rw) { atomicMin(&t_mnw[r0], id); atomicMax(&t_mxw1[r0], mx + 1u); }
+            T.run(r0, id, id + (lcnt - 1u) * did, rw);
         }
     } else {
         uint32_t k = r0, a = id;
-        if (rw) {
-            for (uint32_t q = 0; q < lcnt; q++, k += dl, a += did) {
-                atomicMin(&t_mn[k], a); atomicMax(&t_mx[k], a);
-                atomicMin(&t_mnw[k], a); atomicMax(&t_mxw1[k], a + 1u);
-            }
-        } else {
-            for (uint32_t q = 0; q < lcnt; q++, k += dl, a += did) {
-                atomicMin(&t_mn[k], a); atomicMax(&t_mx[k], a);
-            }
-        }
+        for (uint32_t s = 0; s < lcnt; s++, k += dl, a += did) T.run(k, a, a, rw);
     }
     nrec += lcnt;
     return true;
@@ -2285,12 +2304,11 @@ __device__ __forceinline__ bool dir_tlin(CEnt &E, CKer &K, uint32_t item, uint32
 // at once.  False when the per-record path has to take the tile.
 template <bool PROVEN>
 __device__ __forceinline__ bool dir_lin_box(CEnt &E, CKer &K, uint32_t tile, uint32_t ulo, uint32_t width,
-                                            uint32_t *t_mn, uint32_t *t_mx, uint32_t *t_mnw, uint32_t *t_mxw1,
-                                            uint32_t &nrec) {
+                                            const UnitTab &T, uint32_t &nrec) {
     const LinLane L = lin_lane_at<PROVEN>(E, K, tile * EXP_WG + threadIdx.x, 0u, 0u, 0u, 0u, E.box);
     uint32_t r0;
     if (!lin_in_unit(L, ulo, width, r0)) return false;
-    fold_lin<true>(r0, L.lcnt, L.id, L.dl, E.rw, t_mn, t_mx, t_mnw, t_mxw1);
+    fold_lin<true>(r0, L.lcnt, L.id, L.dl, E.rw, T);
     nrec += L.lcnt;
     return true;
 }
@@ -2298,130 +2316,137 @@ __device__ __forceinline__ bool dir_lin_box(CEnt &E, CKer &K, uint32_t tile, uin
 __global__ void __launch_bounds__(BKT_WG) k_direct(const DevSub *subs_g, const DevUnit *__restrict__ units,
                                                    uint32_t nunits, SubResult *__restrict__ res,
                                                    uint32_t *__restrict__ uwit) {
-    __shared__ uint32_t t_mn[DIR_CAP], t_mx[DIR_CAP], t_mnw[DIR_CAP], t_mxw1[DIR_CAP];
+    __shared__ __align__(16) uint32_t t_mn[DIR_CAP], t_mx2[DIR_CAP], t_mnw[DIR_CAP];
     __shared__ uint32_t red[BKT_WG / 64];
     __shared__ uint32_t s_first;
     __shared__ unsigned long long s_oob;
+    static_assert(DIR_CAP % (4 * BKT_WG) == 0, "unit slots split evenly over the threads, four at a time");
+    const UnitTab T{t_mn, t_mx2, t_mnw};
     CSub *subs = cptr(subs_g);
     const uint32_t t = threadIdx.x;
-    for (uint32_t k = t; k < DIR_CAP; k += BKT_WG) {
-        t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+    // one workgroup per unit
+    const uint32_t u = blockIdx.x;
+    if (u >= nunits) return;
+    const DevUnit U = units[u];
+    CSub &S = subs[U.sub];
+    CKer &K = *cptr(S.kc);
+    const uint32_t ulo = U.lo, width = U.hi - U.lo;
+    // empty summaries over the unit's slots, four at a time
+    for (uint32_t k = 4u * t; k < width; k += 4u * BKT_WG) {
+        *reinterpret_cast<uint4 *>(&t_mn[k]) = make_uint4(~0u, ~0u, ~0u, ~0u);
+        *reinterpret_cast<uint4 *>(&t_mx2[k]) = make_uint4(0u, 0u, 0u, 0u);
+        *reinterpret_cast<uint4 *>(&t_mnw[k]) = make_uint4(~0u, ~0u, ~0u, ~0u);
     }
     if (t == 0) { s_first = 0xFFFFFFFFu; s_oob = ~0ull; }
     __syncthreads();
-    for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
-        const DevUnit U = units[u];
-        CSub &S = subs[U.sub];
-        CKer &K = *cptr(S.kc);
-        const uint32_t ulo = U.lo, width = U.hi - U.lo;
-        uint32_t nrec = 0;
-        CEnt *ents = cptr(S.entries);
-        for (uint32_t e = 0; e < S.n_entries; e++) {
-            CEnt &E = ents[e];
-            if (E.loc_mul == 0u || E.n_lchunks == 0u) continue;     // global array, or an empty loop box
-            // the entry's work items holding threads [t0, t1)
-            const uint32_t nl = E.n_lchunks;
-            uint64_t ia, ib;
-            if (!E.flat) {
-                const uint32_t per = (uint32_t)EXP_WG * E.gt;
-                ia = (uint64_t)(U.t0 / per) * nl;
-                ib = (uint64_t)((U.t1 + per - 1u) / per) * nl;
-            } else {
-                const uint64_t q0 = (uint64_t)(U.t0 / E.gt) * nl;
-                const uint64_t q1 = min((uint64_t)((U.t1 + E.gt - 1u) / E.gt) * nl, (uint64_t)E.nq);
-                ia = q0 / EXP_WG;
-                ib = (q1 + EXP_WG - 1) / EXP_WG;
-            }
-            const uint32_t rwbit = E.rw;
-            const uint32_t v = (E.flat ? 3u : 0u) + (E.fast == 2 ? 0u : E.fast ? 1u : 2u);
-            auto run = [&](auto variant) {
-                constexpr int V = decltype(variant)::value;
-                auto per_record = [&](uint32_t li) {
-                    Seg cur{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
-                    uint32_t pk = 0xFFFFFFFFu;
-                    expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {
-                        if (ok && !inb) atomicMin(&s_oob, ((unsigned long long)S.interval << 32) | id);
-                        const uint32_t rel = loc - ulo;
-                        if (!(ok && inb && rel < width)) return;
-                        nrec++;
-                        if (rel != pk) {
-                            if (pk != 0xFFFFFFFFu) fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
-                            cur = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
-                            pk = rel;
-                        }
-                        seg_add(cur, id, rwbit);
-                    });
-                    if (pk != 0xFFFFFFFFu) fold(t_mn, t_mx, t_mnw, t_mxw1, pk, cur);
-                };
-                if constexpr (V < 2) {
-                    // one loop with points: a tile of threads takes the whole box
-                    if (E.lin && E.box == E.ext[E.linner]) {
-                        const uint32_t ta = U.t0 / EXP_WG, tb = (U.t1 + EXP_WG - 1u) / EXP_WG;
-                        for (uint32_t tile = ta; tile < tb; tile++)
-                            if (!dir_lin_box<(V == 0)>(E, K, tile, ulo, width, t_mn, t_mx, t_mnw, t_mxw1, nrec))
-                                for (uint32_t c = 0; c < nl; c++) per_record(tile * nl + c);
-                        return;
+    uint32_t nrec = 0;
+    CEnt *ents = cptr(S.entries);
+    for (uint32_t e = 0; e < S.n_entries; e++) {
+        CEnt &E = ents[e];
+        if (E.loc_mul == 0u || E.n_lchunks == 0u) continue;     // global array, or an empty loop box
+        // the entry's work items holding threads [t0, t1): thread-major
+        // items of 256 gt threads (x n_lchunks), or flat lanes of gt threads
+        // each (x n_lchunks) in items of 256 lanes; all below 2^32
+        const uint32_t nl = E.n_lchunks;
+        const Magic mg_gt = ldm(E.mg_gt);
+        uint32_t ia, ib;
+        if (!E.flat) {
+            ia = udiv(U.t0 >> 8, mg_gt) * nl;
+            ib = udiv((U.t1 + (uint32_t)EXP_WG * E.gt - 1u) >> 8, mg_gt) * nl;
+        } else {
+            const uint32_t q0 = udiv(U.t0, mg_gt) * nl;
+            const uint32_t q1 = min(udiv(U.t1 + E.gt - 1u, mg_gt) * nl, E.nq);
+            ia = q0 >> 8;
+            ib = (q1 >> 8) + ((q1 & 255u) ? 1u : 0u);
+        }
+        static_assert(EXP_WG == 256, "item ranges divide by 256 with shifts");
+        const uint32_t rwbit = E.rw;
+        const uint32_t v = (E.flat ? 3u : 0u) + (E.fast == 2 ? 0u : E.fast ? 1u : 2u);
+        auto run = [&](auto variant) {
+            constexpr int V = decltype(variant)::value;
+            auto per_record = [&](uint32_t li) {
+                Seg cur{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                uint32_t pk = 0xFFFFFFFFu;
+                expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {
+                    if (ok && !inb) atomicMin(&s_oob, ((unsigned long long)S.interval << 32) | id);
+                    const uint32_t rel = loc - ulo;
+                    if (!(ok && inb && rel < width)) return;
+                    nrec++;
+                    if (rel != pk) {
+                        if (pk != 0xFFFFFFFFu) T.seg(pk, cur);
+                        cur = Seg{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+                        pk = rel;
                     }
-                }
-                for (uint32_t li = (uint32_t)ia; li < (uint32_t)ib; li++) {
-                    if constexpr (V == 3 || V == 4) {
-                        if (E.tlin && dir_tlin<(V == 3)>(E, K, li, ulo, width, t_mn, t_mx, t_mnw, t_mxw1, nrec))
-                            continue;
-                    }
-                    if constexpr (V % 3 != 2) {
-                        if (E.lin && dir_lin<(V >= 3), (V % 3 == 0)>(E, K, li, ulo, width, t_mn, t_mx, t_mnw,
-                                                                     t_mxw1, nrec))
-                            continue;
-                    }
-                    per_record(li);
-                }
+                    seg_add(cur, id, rwbit);
+                });
+                if (pk != 0xFFFFFFFFu) T.seg(pk, cur);
             };
-            switch (v) {
-                case 0: run(Variant<0>{}); break;
-                case 1: run(Variant<1>{}); break;
-                case 2: run(Variant<2>{}); break;
-                case 3: run(Variant<3>{}); break;
-                case 4: run(Variant<4>{}); break;
-                default: run(Variant<5>{}); break;
+            if constexpr (V < 2) {
+                // one loop with points: a tile of threads takes the whole box
+                if (E.lin && E.box == E.ext[E.linner]) {
+                    const uint32_t ta = U.t0 / EXP_WG, tb = (U.t1 + EXP_WG - 1u) / EXP_WG;
+                    for (uint32_t tile = ta; tile < tb; tile++)
+                        if (!dir_lin_box<(V == 0)>(E, K, tile, ulo, width, T, nrec))
+                            for (uint32_t c = 0; c < nl; c++) per_record(tile * nl + c);
+                    return;
+                }
             }
-        }
-        uint32_t total_rec;
-        block_excl_add<BKT_WG>(nrec, red, &total_rec);      // its barriers also end the folding
-        // judge each location, resetting its slot; keep this thread's first conflict
-        const Magic mgM = ldm(S.mgM);
-        uint32_t nc = 0, fk = 0xFFFFFFFFu, fsc = 0, fsr = 0, fmnw = 0;
-        for (uint32_t k = t; k < width; k += BKT_WG) {
-            const Seg x{0u, t_mn[k], t_mx[k], t_mnw[k], t_mxw1[k]};
-            if (x.mn == 0xFFFFFFFFu) continue;
-            t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
-            uint32_t sc, sr;
-            if (judge(x, mgM, sc, sr)) {
-                if (!nc) { fk = k; fsc = sc; fsr = sr; fmnw = x.mnw; }
-                nc++;
+            for (uint32_t li = ia; li < ib; li++) {
+                if constexpr (V == 3 || V == 4) {
+                    if (E.tlin && dir_tlin<(V == 3)>(E, K, li, ulo, width, T, nrec)) continue;
+                }
+                if constexpr (V % 3 != 2) {
+                    if (E.lin && dir_lin<(V >= 3), (V % 3 == 0)>(E, K, li, ulo, width, T, nrec)) continue;
+                }
+                per_record(li);
             }
+        };
+        switch (v) {
+            case 0: run(Variant<0>{}); break;
+            case 1: run(Variant<1>{}); break;
+            case 2: run(Variant<2>{}); break;
+            case 3: run(Variant<3>{}); break;
+            case 4: run(Variant<4>{}); break;
+            default: run(Variant<5>{}); break;
         }
-        if (nc) atomicMin(&s_first, fk);
-        uint32_t total;
-        block_excl_add<BKT_WG>(nc, red, &total);           // its barriers order s_first
-        if (nc && fk == s_first) {
-            uint32_t *w = uwit + 4 * (size_t)u;
-            w[0] = ulo + fk; w[1] = fmnw; w[2] = fsc; w[3] = fsr;
+    }
+    uint32_t total_rec;
+    block_excl_add<BKT_WG>(nrec, red, &total_rec);      // its barriers also end the folding
+    // judge each location (all of a thread's slots read first); keep this
+    // thread's first conflict
+    const Magic mgM = ldm(S.mgM);
+    uint32_t nc = 0, fk = 0xFFFFFFFFu, fsc = 0, fsr = 0, fmnw = 0;
+    constexpr int JPT = DIR_CAP / BKT_WG;
+    Seg x[JPT];
+#pragma unroll
+    for (int i = 0; i < JPT; i++) x[i] = T.get(min(t + (uint32_t)i * BKT_WG, width - 1u));
+#pragma unroll
+    for (int i = 0; i < JPT; i++) {
+        const uint32_t k = t + (uint32_t)i * BKT_WG;
+        uint32_t sc, sr;
+        if (k < width && x[i].mn != 0xFFFFFFFFu && judge(x[i], mgM, sc, sr)) {
+            if (!nc) { fk = k; fsc = sc; fsr = sr; fmnw = x[i].mnw; }
+            nc++;
         }
-        if (t == 0) {
-            SubResult &R = res[S.res];
-            if (total_rec) {
-                atomicAdd(&R.records, (unsigned long long)total_rec);
-                atomicAdd(&R.unit_records, (unsigned long long)total_rec);
-            }
-            if (total) {
-                atomicAdd(&R.conflicts, (unsigned long long)total);
-                atomicMin(&R.first_unit, u);
-            }
-            if (s_oob != ~0ull) atomicMin(&R.oob, s_oob);
-            s_oob = ~0ull;       // no thread touches it again before this unit's last barrier
+    }
+    if (nc) atomicMin(&s_first, fk);
+    uint32_t total;
+    block_excl_add<BKT_WG>(nc, red, &total);           // its barriers order s_first
+    if (nc && fk == s_first) {
+        uint32_t *w = uwit + 4 * (size_t)u;
+        w[0] = ulo + fk; w[1] = fmnw; w[2] = fsc; w[3] = fsr;
+    }
+    if (t == 0) {
+        SubResult &R = res[S.res];
+        if (total_rec) {
+            atomicAdd(&R.records, (unsigned long long)total_rec);
+            atomicAdd(&R.unit_records, (unsigned long long)total_rec);
         }
-        __syncthreads();         // every thread has read s_first
-        if (t == 0) s_first = 0xFFFFFFFFu;   // next used after the next unit's first barrier
+        if (total) {
+            atomicAdd(&R.conflicts, (unsigned long long)total);
+            atomicMin(&R.first_unit, u);
+        }
+        if (s_oob != ~0ull) atomicMin(&R.oob, s_oob);
     }
 }
 
@@ -2984,9 +3009,12 @@ void launch_first(const DevSub *subs, uint32_t nsub, const unsigned long long *r
 void launch_direct(const DevSub *subs, const DevUnit *units, uint32_t n, SubResult *res, uint32_t *uwit,
                    unsigned ncu, hipStream_t st) {
     if (!n) return;
-    static const unsigned occ = occupancy(k_direct, BKT_WG, 2);
-    const unsigned grid = (unsigned)std::min<uint64_t>(n, (uint64_t)ncu * occ);
-    hipLaunchKernelGGL(k_direct, dim3(grid), dim3(BKT_WG), 0, st, subs, units, n, res, uwit);
+    // one workgroup per unit, not a persistent grid: as units retire, the
+    // dispatcher can hand their slots to the HBM pipeline's kernels running
+    // beside them on the other stream (measured faster than 2, 3 or 4
+    // persistent workgroups per CU)
+    (void)ncu;
+    hipLaunchKernelGGL(k_direct, dim3(n), dim3(BKT_WG), 0, st, subs, units, n, res, uwit);
 }
 
 void launch_gather(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, const unsigned long long *rec,

@@ -453,6 +453,7 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                              (only || E.ext[inner] % E.lch == 0)) ? 1u : 0u;
                 }
                 E.mg_nl = make_magic(std::max<uint32_t>(E.n_lchunks, 1));
+                E.mg_gt = make_magic(std::max<uint32_t>(E.gt, 1));
                 E.mg_e1 = make_magic(std::max<uint32_t>(E.ext[1], 1));
                 E.mg_e2 = make_magic(std::max<uint32_t>(E.ext[2], 1));
                 {
@@ -510,7 +511,8 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 recs += w;
                 work += w * (1.0L + per / (long double)Tu);
             }
-            I.direct = recs > 0 && work <= 2.0L * recs;
+            // (the unit tables keep 2 id + rw in 32 bits: ids below 2^31)
+            I.direct = recs > 0 && work <= 2.0L * recs && I.P < (1ull << 31);
         }
         // entry work-item prefix (and the one without the shared entries of
         // a direct interval)

@@ -97,6 +97,7 @@ struct DevEntry {
     uint32_t flat;
     uint32_t nq;               // flat: thread groups x loop chunks
     Magic mg_nl, mg_e1, mg_e2; // divisions by n_lchunks, ext[1], ext[2]
+    Magic mg_gt;               // division by gt
     // Fast path (no aux terms, no guards): the location as one affine row
     // modulo 2^32, loc = fr . (tx,ty,bx,by,l0,l1,l2) + fr[C_C0] + block *
     // loc_mul; exact for every in-bounds record.  2: fast and every index of
