@@ -53,6 +53,30 @@ PACKED_BYTES = 8.0
 # the grouping stage's kernels (fold: buckets of one slice, medium and hot
 # buckets; their HIP-event time is taken together)
 GROUP_KERNEL = {"fold": "k_fold+k_mid+k_hot", "sort_scan": "k_bucket"}
+# Block-local units checked on chip (k_direct): no record reaches HBM; each
+# record is folded into its location's 12-byte summary in LDS (smallest id,
+# largest 2 id + rw, smallest write id).  Algorithmic LDS bytes per record:
+# one read-modify-write of that summary, 12 bytes.  LDS peak: 256 CUs x 32
+# banks x 4 bytes per clock x 2.4 GHz.
+UNIT_ALG_BYTES = 12.0
+LDS_PEAK_GBS = 256 * 32 * 4 * 2.4
+
+
+def roofline_units(stages, unit_records_timed):
+    """The on-chip units' kernel against the LDS roofline: the 12-byte
+    summary update per record x records per launch / average launch time
+    (HIP events on the stream it runs on)."""
+    launches = stages["direct"][1]
+    if not launches or stages["direct"][0] <= 0:
+        return None
+    avg_ms = stages["direct"][0] / launches
+    recs = unit_records_timed / launches
+    achieved = UNIT_ALG_BYTES * recs / (avg_ms * 1e-3) / 1e9
+    return {"bound": "lds", "kernel": "k_direct", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
+            "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
+            "traffic": traffic_for("k_direct", int(recs)), "avg_launch_ms": round(avg_ms, 4),
+            "alg_bytes_per_record": UNIT_ALG_BYTES, "records_per_launch": int(recs),
+            "note": "records of block-local units never reach HBM; traffic is the kernel's measured HBM bytes"}
 
 
 def log(*a):
@@ -554,6 +578,16 @@ def main():
     log("[bench] GPU ms per step by stage: " + ", ".join(f"{k}={v:.3f}" for k, v in per_step.items()))
     roofline = roofline_from(stages, (n_records - small_records - direct_records) * args.steps,
                              GROUP_KERNEL[ctx.group])
+    roofline_hbm = None
+    if direct_records:
+        # the units' kernel dominates when its launch time exceeds every HBM
+        # stage's; the HBM pipeline's own roofline is reported beside it
+        ru = roofline_units(stages, direct_records * args.steps)
+        hbm_ms = max(stages["expand"][0], stages["sort_scan"][0])
+        if ru is not None and stages["direct"][0] >= hbm_ms:
+            roofline, roofline_hbm = ru, roofline
+        elif ru is not None:
+            roofline_hbm = ru
     out = {
         "metric": "access records race-checked/sec + % HBM peak; p50/p99 verify latency",
         "value": value,
@@ -574,6 +608,8 @@ def main():
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "roofline": roofline,
     }
+    if roofline_hbm is not None:
+        out["roofline_other"] = roofline_hbm
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = (cpu_baseline_kernels(descs, args.cpu_seconds) if len(descs) > 1
