@@ -231,6 +231,7 @@ def bench_batch(args, rv, torch):
     ctx.group = args.group
     ctx.target = args.target
     ctx.small_cap = args.small_cap
+    ctx.direct = bool(args.direct)
     ks = [ctx.load(d) for d in descs]
     log(f"[bench] loaded 4096 kernels")
     batch = rv.Batch(ctx, ks)
@@ -262,7 +263,8 @@ def bench_batch(args, rv, torch):
     ctx.set_timing(False)
     stages = ctx.timing(reset=True)
     small_records = stages.pop("small_records") // max(1, args.steps)
-    stages.pop("direct_records")
+    direct_records = stages.pop("direct_records") // max(1, args.steps)
+    counted_records = stages.pop("counted_records") // max(1, args.steps)
     res = batch.results()
     assert [(r.n_records, r.n_conflicts) for r in res] == [(r.n_records, r.n_conflicts) for r in single]
     per_step = {k: v[0] / args.steps for k, v in stages.items()}
@@ -278,14 +280,18 @@ def bench_batch(args, rv, torch):
                    "records": n_records, "kernels": len(ks),
                    "buckets": sum(k.info().n_buckets for k in ks),
                    "kernels_with_conflicts": sum(1 for r in res if r.n_conflicts),
-                   "small_cap": ctx.small_cap, "records_on_chip": small_records},
+                   "small_cap": ctx.small_cap, "direct": int(ctx.direct),
+                   "records_on_chip": small_records + direct_records,
+                   "records_counted_without_writes": counted_records},
         "latency_ms": {"p50": round(percentile(lat, 0.5) * 1e3, 3), "p99": round(percentile(lat, 0.99) * 1e3, 3)},
         "per_kernel_launches": None if args.no_per_kernel else {
             "ms_per_batch": round(t_single * 1e3, 2), "value": n_records / t_single,
             "batched_speedup": round(t_single / (elapsed / args.steps), 2)},
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
-        # the HBM kernels see only the records outside the on-chip passes
-        "roofline": roofline_from(stages, (n_records - small_records) * args.steps, GROUP_KERNEL[ctx.group]),
+        # the HBM kernels see only the records outside the on-chip passes and
+        # units and the passes without writes
+        "roofline": roofline_from(stages, (n_records - small_records - direct_records - counted_records) * args.steps,
+                                  GROUP_KERNEL[ctx.group]),
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -339,6 +345,7 @@ def bench_gespmm(args, rv, torch):
         stages = ctx.timing(reset=True)
         stages.pop("small_records")
         stages.pop("direct_records")
+        stages.pop("counted_records")
         k.free()
         if (r.n_records, r.n_conflicts) != (exp["records"], 0):
             raise SystemExit(f"gespmm {M}x{N} T={T} K={Kb}: {r} differs from the closed form {exp}")
@@ -382,6 +389,7 @@ def bench_serve(args, rv, torch):
     log(f"[bench] generated {len(descs)} jobs in {time.perf_counter() - t0:.1f} s")
     ctx = rv.Context(0, workspace_bytes=1 << 30)
     ctx.group = args.group
+    ctx.direct = bool(args.direct)
     ctx.target = args.target
     ks = [ctx.load(d) for d in descs]
     log(f"[bench] loaded {len(ks)} jobs")
@@ -570,13 +578,14 @@ def main():
     stages = ctx.timing(reset=True)
     small_records = stages.pop("small_records") // args.steps
     direct_records = stages.pop("direct_records") // args.steps
+    counted_records = stages.pop("counted_records") // args.steps
     assert sum(r.n_records for r in res) == n_records
     value = n_records * args.steps / elapsed
     p50 = percentile(lat, 0.5)
     p99 = percentile(lat, 0.99)
     per_step = {k: v[0] / args.steps for k, v in stages.items()}
     log("[bench] GPU ms per step by stage: " + ", ".join(f"{k}={v:.3f}" for k, v in per_step.items()))
-    roofline = roofline_from(stages, (n_records - small_records - direct_records) * args.steps,
+    roofline = roofline_from(stages, (n_records - small_records - direct_records - counted_records) * args.steps,
                              GROUP_KERNEL[ctx.group])
     roofline_hbm = None
     if direct_records:
@@ -603,7 +612,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl_text, "records": n_records, "kernels": len(ks),
                    "conflicts": sum(r.n_conflicts for r in res), "direct": int(ctx.direct),
-                   "records_on_chip": small_records + direct_records},
+                   "records_on_chip": small_records + direct_records,
+                   "records_counted_without_writes": counted_records},
         "latency_ms": {"p50": round(p50 * 1e3, 3), "p99": round(p99 * 1e3, 3)},
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "roofline": roofline,

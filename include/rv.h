@@ -173,6 +173,8 @@ typedef struct {
     uint64_t launches[RV_NSTAGE];
     uint64_t small_records;   /* records of the batched passes checked on chip (RV_STAGE_SMALL) */
     uint64_t direct_records;  /* records of block-local units checked on chip (RV_STAGE_DIRECT) */
+    uint64_t counted_records; /* records of passes without writes (no location there can conflict):
+                                 counted by RV_STAGE_COUNT, never placed or grouped */
 } rv_timing;
 
 /* Static facts about a loaded kernel. */
@@ -453,8 +455,11 @@ rv_status rv_get_timing(rv_ctx *ctx, rv_timing *out, int reset);
  *    records expanded and folded into per-location summaries on chip, then
  *    judged -- and only global-array records go through the record buffer
  *    in HBM.  Intervals with warp barriers, and intervals whose blocks hold
- *    more than 2048 shared elements, keep the HBM path.  rv_get_witnesses,
- *    rv_check_counts, rv_check_static and batched checks do not use it. */
+ *    more than 2048 shared elements, keep the HBM path.  With `direct` on,
+ *    a pass whose HBM-side accesses are all reads is only counted (its
+ *    records and out-of-bounds instances): without a write no location
+ *    conflicts (Section 2.1 step 6: RaW, WaW and WaR all need a write).
+ *    rv_get_witnesses, rv_check_counts and rv_check_static do not use it. */
 enum {
     RV_GROUP_FOLD = 0,       /* fold records into per-location LDS tables with atomics (default) */
     RV_GROUP_SORT_SCAN = 1   /* LDS counting sort of each bucket + DPP segmented scan */

@@ -48,6 +48,8 @@ struct Lane {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     uint64_t unit_records = 0;    // records of the last check's block-local units
+    std::vector<uint32_t> count_slots;   // result slots of the last check's passes without writes
+    uint64_t counted_records = 0;        // their records (counted, never placed or grouped)
     void *h_up = nullptr;       // pinned: pass tables going up
     size_t up_cap = 0;
     void *h_down = nullptr;     // pinned: results coming down
@@ -58,11 +60,18 @@ struct Lane {
     uint64_t small_records = 0;          // their records, summed when the batch is collected
     // the last batch's pass table, still in d_subs: reused when the next batch
     // has the same kernels (load serials) and small-pass threshold
-    struct TabChunk { size_t sub_begin, sub_end; uint64_t items, buckets; bool subkeys; };
+    struct TabChunk {
+        size_t sub_begin, sub_end;
+        uint64_t items, buckets;
+        bool subkeys;
+        size_t unit_begin, unit_end;   // the chunk's block-local units in d_units
+    };
+    DevUnit *d_units = nullptr;        // the last batch's units (after its pass table)
+    size_t units_cap = 0;
     std::vector<uint64_t> tab_key;
     std::vector<TabChunk> tab_chunks;
     size_t tab_nreg = 0, tab_nsmall = 0;
-    std::vector<uint32_t> tab_small_slots;
+    std::vector<uint32_t> tab_small_slots, tab_count_slots;
     bool tab_valid = false;
     // the batch in flight
     std::vector<rv_kernel *> jobs;
@@ -191,7 +200,7 @@ rv_status drain_timing(rv_ctx *c) {
 template <class T>
 rv_status grow_device(Lane &ln, T *&p, size_t &cap, size_t n) {
     if (n <= cap) return RV_OK;
-    if ((void *)p == (void *)ln.d_subs) ln.tab_valid = false;
+    if ((void *)p == (void *)ln.d_subs || (void *)p == (void *)ln.d_units) ln.tab_valid = false;
     HIP_TRY_L(ln, hipStreamSynchronize(ln.stream));
     if (p) HIP_TRY_L(ln, hipFree(p));
     p = nullptr;
@@ -220,6 +229,8 @@ void lane_release(Lane &ln) {
     if (ln.d_cnt) (void)hipFree(ln.d_cnt);
     if (ln.d_tmp) (void)hipFree(ln.d_tmp);
     if (ln.d_uwit) (void)hipFree(ln.d_uwit);
+    if (ln.d_units) (void)hipFree(ln.d_units);
+    ln.d_units = nullptr; ln.units_cap = 0;
     if (ln.side) (void)hipStreamDestroy(ln.side);
     if (ln.fork) (void)hipEventDestroy(ln.fork);
     if (ln.join) (void)hipEventDestroy(ln.join);
@@ -265,6 +276,22 @@ void run_group(rv_ctx *c, Lane &ln, const DevSub *subs, uint32_t nsub, uint64_t 
 
 // units[0..nunits): the chunk's block-local units checked on chip (their
 // passes in `subs` leave those locations out of the HBM pipeline).
+// The lane's side stream and its fork / join events, created on first use
+// (best effort: without them the units run in line on the lane's stream).
+void ensure_side(Lane &ln) {
+    if (ln.side || ln.untimed) return;
+    if (hipStreamCreateWithFlags(&ln.side, hipStreamNonBlocking) != hipSuccess) {
+        ln.side = nullptr;
+        return;
+    }
+    if (hipEventCreateWithFlags(&ln.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ln.join, hipEventDisableTiming) != hipSuccess) {
+        if (ln.fork) (void)hipEventDestroy(ln.fork);
+        (void)hipStreamDestroy(ln.side);
+        ln.side = nullptr; ln.fork = nullptr; ln.join = nullptr;
+    }
+}
+
 // The units run on the lane's side stream when it has one, overlapping the
 // HBM pipeline (on-chip work beside memory-bound work); both update the
 // passes' slots with atomics, and the finish waits for the units.
@@ -382,23 +409,18 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
                           ks[0]->plan_cap_buckets == ln.L.cap_buckets;
     timed(c, ln, RV_STAGE_FILL, [&] { launch_init_results(ln.d_res, ns, s); });
     ln.unit_records = 0;
+    ln.count_slots.clear();
     if (resident) {
         const rv_kernel *k = ks[0];
-        const bool direct = c->direct && !k->units.empty();
+        const bool direct = c->direct && k->d_subs_dir != nullptr;
         if (direct) {
             st = grow_device(ln, ln.d_uwit, ln.uwit_cap, 4 * (size_t)k->max_chunk_units);
             if (st) return st;
-            if (!ln.side && !ln.untimed) {
-                // best effort: without a side stream the units run in line
-                if (hipStreamCreateWithFlags(&ln.side, hipStreamNonBlocking) != hipSuccess) ln.side = nullptr;
-                if (ln.side && (hipEventCreateWithFlags(&ln.fork, hipEventDisableTiming) != hipSuccess ||
-                                hipEventCreateWithFlags(&ln.join, hipEventDisableTiming) != hipSuccess)) {
-                    if (ln.fork) (void)hipEventDestroy(ln.fork);
-                    (void)hipStreamDestroy(ln.side);
-                    ln.side = nullptr; ln.fork = nullptr; ln.join = nullptr;
-                }
-            }
+            ensure_side(ln);
         }
+        if (direct)
+            for (uint32_t i = 0; i < k->h_subs_dir.size(); i++)
+                if (k->h_subs_dir[i].count_only) ln.count_slots.push_back(i);
         for (auto &ch : k->chunks) {
             if (direct)
                 run_check_chunk(c, ln, k->d_subs_dir + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items_d,
@@ -409,18 +431,24 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
         }
     } else {
         // the same kernels as the last batch on this lane: its table is on the device
+        const bool direct = c->direct != 0;
         std::vector<uint64_t> key(n + 1);
         for (size_t j = 0; j < n; j++) key[j] = ks[j]->serial;
-        key[n] = (uint64_t)std::max(0, (int)c->small_cap);
+        key[n] = (uint64_t)std::max(0, (int)c->small_cap) | ((uint64_t)direct << 32);
+        auto run_chunks = [&](const std::vector<Lane::TabChunk> &chs) {
+            for (auto &ch : chs)
+                run_check_chunk(c, ln, ln.d_subs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items,
+                                ch.buckets, ch.subkeys, ln.d_units + ch.unit_begin,
+                                (uint32_t)(ch.unit_end - ch.unit_begin));
+        };
         if (ln.tab_valid && key == ln.tab_key) {
             ln.small_slots = ln.tab_small_slots;
+            ln.count_slots = ln.tab_count_slots;
             if (ln.tab_nsmall)
                 timed(c, ln, RV_STAGE_SMALL, [&] {
                     launch_small(ln.d_subs + ln.tab_nreg, (uint32_t)ln.tab_nsmall, ln.d_res, c->ncu, s);
                 });
-            for (auto &ch : ln.tab_chunks)
-                run_check_chunk(c, ln, ln.d_subs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items,
-                                ch.buckets, ch.subkeys);
+            run_chunks(ln.tab_chunks);
             goto launched;
         }
         ln.tab_valid = false;
@@ -430,7 +458,9 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
         std::vector<Chunk> chunks;
         std::vector<DevSub> table;
         table.reserve(ns);
-        Chunk cur{0, 0, 0, 0, false};
+        std::vector<DevUnit> units;    // block-local units, their pass re-based to the chunk
+        Chunk cur{0, 0, 0, 0, false, 0, 0};
+        size_t max_units = 0;
         uint64_t rec_bound = 0;
         std::vector<DevSub> small;     // passes checked on chip (k_small)
         std::vector<uint32_t> small_items;
@@ -447,27 +477,44 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
                     ln.small_slots.push_back(D.res);
                     continue;
                 }
-                const uint32_t nb = k.subs[i].nb;
+                // with units on, a pass of a unit-checked interval leaves its
+                // shared locations to its units (fewer items and buckets)
+                const bool dir = direct && !k.h_subs_dir.empty();
+                DevSub D = dir ? k.h_subs_dir[i] : k.h_subs[i];   // begins and slot re-based here
+                const uint64_t items = dir && I.direct ? I.items_g : I.items;
+                const uint32_t nb = D.nb;
                 if (cur.sub_end > cur.sub_begin &&
                     (rec_bound + I.P > ln.L.cap_records || cur.buckets + nb > ln.L.cap_buckets ||
-                     cur.items + I.items >= (1ull << 31))) {
+                     cur.items + items >= (1ull << 31))) {
+                    cur.unit_end = units.size();
+                    max_units = std::max(max_units, cur.unit_end - cur.unit_begin);
                     chunks.push_back(cur);
-                    cur = Chunk{table.size(), table.size(), 0, 0, false};
+                    cur = Chunk{table.size(), table.size(), 0, 0, false, units.size(), units.size()};
                     rec_bound = 0;
                 }
                 cur.subkeys = cur.subkeys || k.has_subkeys;
-                DevSub D = k.h_subs[i];     // the pass as loaded; begins and slot re-based here
                 D.item_begin = (uint32_t)cur.items;
                 D.bucket_begin = (uint32_t)cur.buckets;
                 D.res = (uint32_t)(ln.res0[j] + i);
+                if (D.count_only) ln.count_slots.push_back(D.res);
+                if (dir)
+                    for (uint32_t q = k.subs[i].unit_begin; q < k.subs[i].unit_end; q++) {
+                        DevUnit U = k.units[q];
+                        U.sub = (uint32_t)(table.size() - cur.sub_begin);
+                        units.push_back(U);
+                    }
                 table.push_back(D);
-                cur.items += I.items;
+                cur.items += items;
                 cur.buckets += nb;
                 cur.sub_end = table.size();
                 rec_bound += I.P;
             }
         }
-        if (cur.sub_end > cur.sub_begin) chunks.push_back(cur);
+        if (cur.sub_end > cur.sub_begin) {
+            cur.unit_end = units.size();
+            max_units = std::max(max_units, cur.unit_end - cur.unit_begin);
+            chunks.push_back(cur);
+        }
         const size_t nreg = table.size();
         // largest first (by work items): the persistent workgroups take the
         // list round-robin, so the long passes do not straggle
@@ -480,23 +527,34 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
         }
         st = grow_device(ln, ln.d_subs, ln.subs_cap, std::max<size_t>(table.size(), 1));
         if (st) return st;
-        st = grow_pinned(ln, ln.h_up, ln.up_cap, std::max<size_t>(table.size(), 1) * sizeof(DevSub));
+        if (!units.empty()) {
+            st = grow_device(ln, ln.d_units, ln.units_cap, units.size());
+            if (!st) st = grow_device(ln, ln.d_uwit, ln.uwit_cap, 4 * max_units);
+            if (st) return st;
+            ensure_side(ln);
+        }
+        const size_t tab_bytes = table.size() * sizeof(DevSub), unit_bytes = units.size() * sizeof(DevUnit);
+        st = grow_pinned(ln, ln.h_up, ln.up_cap, std::max<size_t>(tab_bytes + unit_bytes, 1));
         if (st) return st;
         if (!table.empty()) {
-            memcpy(ln.h_up, table.data(), table.size() * sizeof(DevSub));
-            HIP_TRY_L(ln, hipMemcpyAsync(ln.d_subs, ln.h_up, table.size() * sizeof(DevSub), hipMemcpyHostToDevice, s));
+            memcpy(ln.h_up, table.data(), tab_bytes);
+            HIP_TRY_L(ln, hipMemcpyAsync(ln.d_subs, ln.h_up, tab_bytes, hipMemcpyHostToDevice, s));
+        }
+        if (!units.empty()) {
+            char *up = reinterpret_cast<char *>(ln.h_up) + tab_bytes;
+            memcpy(up, units.data(), unit_bytes);
+            HIP_TRY_L(ln, hipMemcpyAsync(ln.d_units, up, unit_bytes, hipMemcpyHostToDevice, s));
         }
         if (!small.empty())
             timed(c, ln, RV_STAGE_SMALL,
                   [&] { launch_small(ln.d_subs + nreg, (uint32_t)small.size(), ln.d_res, c->ncu, s); });
-        for (auto &ch : chunks)
-            run_check_chunk(c, ln, ln.d_subs + ch.sub_begin, (uint32_t)(ch.sub_end - ch.sub_begin), ch.items,
-                            ch.buckets, ch.subkeys);
+        run_chunks(chunks);
         ln.tab_key = std::move(key);
         ln.tab_chunks = std::move(chunks);
         ln.tab_nreg = nreg;
         ln.tab_nsmall = small.size();
         ln.tab_small_slots = ln.small_slots;
+        ln.tab_count_slots = ln.count_slots;
         ln.tab_valid = true;
         }
     }
@@ -520,6 +578,8 @@ rv_status lane_collect(Lane &ln, rv_result *out, rv_status *status, std::string 
     for (uint32_t slot : ln.small_slots) ln.small_records += hr[slot].records;
     ln.unit_records = 0;
     for (size_t i = 0; i < ln.ns; i++) ln.unit_records += hr[i].unit_records;
+    ln.counted_records = 0;
+    for (uint32_t slot : ln.count_slots) ln.counted_records += hr[slot].records - hr[slot].unit_records;
     const size_t n = ln.jobs.size();
     std::vector<rv_status> sts(n);
     std::vector<std::string> ms(n);
@@ -783,7 +843,7 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
     const size_t o_sb = al(o_eg + k->entry_items_g.size() * sizeof(uint32_t));
     const size_t o_ss = al(o_sb + k->subs.size() * sizeof(DevSub));
     const size_t o_sd = al(o_ss + (k->static_ok ? k->subs.size() : 0) * sizeof(DevSub));
-    const size_t n_dir = k->units.empty() ? 0 : k->subs.size();
+    const size_t n_dir = k->subs.size();
     const size_t o_un = al(o_sd + n_dir * sizeof(DevSub));
     const size_t o_br = al(o_un + k->units.size() * sizeof(DevUnit));
     const size_t total = al(o_br + k->barriers.size() * sizeof(DevBarrier) + 1);
@@ -806,7 +866,8 @@ rv_status load_kernel(rv_ctx *c, const rv_kernel_desc *desc, int target, rv_kern
         make_devsubs(*k, ch.sub_begin, ch.sub_end, 0, k->h_subs, items, buckets);
         for (uint32_t i = ch.sub_begin; i < ch.sub_end; i++) k->h_subs[i].res = i;
     }
-    std::vector<DevSub> h_dir;
+    std::vector<DevSub> &h_dir = k->h_subs_dir;
+    h_dir.clear();
     if (n_dir)
         for (auto &ch : k->chunks) {
             uint64_t items = 0, buckets = 0;
@@ -936,7 +997,10 @@ rv_status rv_check(rv_ctx *c, rv_kernel *k, rv_result *out) {
     if (st) return main_fail(c, st);
     rv_result r;
     st = lane_collect(c->main, &r, nullptr);
-    if (c->timing) c->acc.direct_records += c->main.unit_records;
+    if (c->timing) {
+        c->acc.direct_records += c->main.unit_records;
+        c->acc.counted_records += c->main.counted_records;
+    }
     if (!st) *out = r;
     return main_fail(c, st);
 }
@@ -955,7 +1019,11 @@ rv_status rv_check_batch(rv_ctx *c, rv_kernel *const *ks, size_t n, rv_result *o
     rv_status st = lane_enqueue(c, c->main, ks, n);
     if (st) return main_fail(c, st);
     st = lane_collect(c->main, out, nullptr);
-    if (c->timing) c->acc.small_records += c->main.small_records;
+    if (c->timing) {
+        c->acc.small_records += c->main.small_records;
+        c->acc.direct_records += c->main.unit_records;
+        c->acc.counted_records += c->main.counted_records;
+    }
     return main_fail(c, st);
 }
 

@@ -746,6 +746,19 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
         // entries count per workgroup.
         constexpr int V = decltype(variant)::value;
         constexpr bool WAVE = V % 3 != 2;
+        if (S.count_only) {
+            // a pass without writes: its records and out-of-bounds instances
+            // are counted, nothing else (the whole workgroup takes this branch)
+            uint32_t n = 0;
+            const uint32_t klo = S.klo, span = S.khi - S.klo;
+            expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {
+                if (ok && !inb) atomicMin(&res[S.res].oob, ((unsigned long long)S.interval << 32) | id);
+                n += (ok && inb && loc - klo < span) ? 1u : 0u;
+            });
+            n = readlane(wave_incl_add(n), 63);
+            if (lane() == 0 && n) atomicAdd(&res[S.res].records, (unsigned long long)n);
+            return;
+        }
         uint32_t *gc = counts + S.bucket_begin;
         if constexpr (V == 3 || V == 4) {
             TLinItem T;
@@ -922,6 +935,7 @@ __global__ void __launch_bounds__(EXP_WG) __attribute__((amdgpu_waves_per_eu(5))
     uint32_t *const hw = bins + (threadIdx.x >> 6) * 2 * WBIN, *const gw = hw + WBIN;
     for_my_items(subs, nsub, nitems, [&](CSub &S, CEnt &E, CKer &K, uint32_t li, auto variant) {
         constexpr int V = decltype(variant)::value;
+        if (S.count_only) return;          // a pass without writes has no records to place
         if constexpr (V == 3 || V == 4) {
             TLinItem T;
             if (E.tlin && tlin_probe<(V == 3)>(S, E, K, li, T)) {

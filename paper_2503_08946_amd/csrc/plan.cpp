@@ -500,11 +500,17 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
         // of `per` threads at the unit's edges is expanded by each unit it
         // overlaps, so a shared entry costs about (1 + per / Tu) times its
         // records.  Units take the interval when that averages at most 2.
+        // Units also need every shared entry on a fast path (no aux terms, no
+        // guards): those fold runs of records; the per-record path of general
+        // entries (measured on the batched and served random kernels) costs a
+        // unit more than the HBM pipeline costs the same records.
         if (dcand) {
             long double recs = 0, work = 0;
+            bool fast = true;
             for (uint32_t e = 0; e < I.entry_count; e++) {
                 const DevEntry &E = k.entries[I.entry_begin + e];
                 if (E.loc_mul == 0 || E.box == 0) continue;
+                fast = fast && E.fast != 0;
                 const long double per = E.flat ? std::max(1.0L, (long double)EXP_WG / E.n_lchunks) * E.gt
                                                : (long double)EXP_WG * E.gt;
                 const long double w = (long double)E.box * (long double)nthreads;
@@ -512,7 +518,7 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                 work += w * (1.0L + per / (long double)Tu);
             }
             // (the unit tables keep 2 id + rw in 32 bits: ids below 2^31)
-            I.direct = recs > 0 && work <= 2.0L * recs && I.P < (1ull << 31);
+            I.direct = fast && recs > 0 && work <= 2.0L * recs && I.P < (1ull << 31);
         }
         // entry work-item prefix (and the one without the shared entries of
         // a direct interval)
@@ -631,14 +637,27 @@ rv_status plan_chunks(rv_kernel &k, const WorkspaceLayout &L, std::string &msg) 
     return RV_OK;
 }
 
-// The part of pass sp left to the HBM pipeline when its interval's
-// block-local spaces are checked on chip: the locations from the end of the
-// shared ones, and their buckets.
-static void hbm_range(const rv_kernel &k, const SubPlan &sp, uint32_t &klo, uint32_t &nb) {
+// The part of pass sp left to the HBM pipeline when block-local spaces are
+// checked on chip: in a unit-checked interval, the locations from the end of
+// the shared ones, and their buckets.  count_only: none of the entries the
+// pipeline expands for the pass writes (a location without a write never
+// conflicts), so the pass is counted and has no buckets.
+static void hbm_part(const rv_kernel &k, const SubPlan &sp, uint32_t &klo, uint32_t &nb, uint32_t &count_only) {
     const IntervalPlan &I = k.intervals[sp.interval];
-    const uint64_t shared_end = (uint64_t)k.kc.nblocks * I.S;
-    klo = (uint32_t)std::min<uint64_t>(sp.khi, std::max<uint64_t>(sp.klo, shared_end));
-    nb = (uint32_t)(((uint64_t)sp.khi - klo + (1ull << sp.s) - 1) >> sp.s);
+    klo = sp.klo;
+    nb = sp.nb;
+    if (I.direct) {
+        const uint64_t shared_end = (uint64_t)k.kc.nblocks * I.S;
+        klo = (uint32_t)std::min<uint64_t>(sp.khi, std::max<uint64_t>(sp.klo, shared_end));
+        nb = (uint32_t)(((uint64_t)sp.khi - klo + (1ull << sp.s) - 1) >> sp.s);
+    }
+    bool writes = false;
+    for (uint32_t e = I.entry_begin; e < I.entry_begin + I.entry_count; e++) {
+        const DevEntry &E = k.entries[e];
+        if ((!I.direct || E.loc_mul == 0) && E.box > 0 && E.rw) writes = true;
+    }
+    count_only = writes ? 0u : 1u;
+    if (count_only) nb = 0;
 }
 
 void plan_units(rv_kernel &k) {
@@ -649,17 +668,14 @@ void plan_units(rv_kernel &k) {
         ch.unit_begin = (uint32_t)k.units.size();
         ch.items_d = ch.buckets_d = 0;
         for (uint32_t i = ch.sub_begin; i < ch.sub_end; i++) {
-            const SubPlan &sp = k.subs[i];
+            SubPlan &sp = k.subs[i];
             const IntervalPlan &I = k.intervals[sp.interval];
-            if (!I.direct) {
-                ch.items_d += I.items;
-                ch.buckets_d += sp.nb;
-                continue;
-            }
-            uint32_t hlo, hnb;
-            hbm_range(k, sp, hlo, hnb);
-            ch.items_d += I.items_g;
+            sp.unit_begin = sp.unit_end = (uint32_t)k.units.size();
+            uint32_t hlo, hnb, co;
+            hbm_part(k, sp, hlo, hnb, co);
+            ch.items_d += I.direct ? I.items_g : I.items;
             ch.buckets_d += hnb;
+            if (!I.direct) continue;
             // units of nbu consecutive blocks over the pass's shared locations [klo, hlo)
             const uint64_t S = I.S;
             const uint64_t nbu = std::max<uint64_t>(1, DIR_CAP / S);
@@ -675,6 +691,7 @@ void plan_units(rv_kernel &k) {
                 U.t1 = (uint32_t)(b1 * tpb);
                 k.units.push_back(U);
             }
+            sp.unit_end = (uint32_t)k.units.size();
         }
         ch.unit_end = (uint32_t)k.units.size();
         k.max_chunk_units = std::max(k.max_chunk_units, ch.unit_end - ch.unit_begin);
@@ -699,7 +716,7 @@ void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0, s
         D.s = sp.s;
         D.klo = sp.klo;
         D.khi = sp.khi;
-        if (dir) hbm_range(k, sp, D.klo, D.nb);
+        if (direct) hbm_part(k, sp, D.klo, D.nb, D.count_only);
         D.M = (uint32_t)I.M;
         D.mgM = make_magic((uint32_t)I.M);
         D.interval = sp.interval;

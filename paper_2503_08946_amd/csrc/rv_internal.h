@@ -151,6 +151,10 @@ struct DevSub {
     uint32_t wshift;
     uint32_t upb;
     Magic mg_unit;
+    // 1: no entry this pass expands in the HBM pipeline writes, so none of
+    // its locations can conflict: the count pass counts its records and
+    // out-of-bounds instances, and it has no records and no buckets.
+    uint32_t count_only;
 };
 
 // One unit of the on-chip check of block-local spaces: the shared-array
@@ -241,6 +245,7 @@ struct IntervalPlan {
 struct SubPlan {
     uint32_t interval;
     uint32_t klo, khi, s, nb;
+    uint32_t unit_begin = 0, unit_end = 0;   // its block-local units in rv_kernel::units
 };
 
 struct ChunkPlan {
@@ -314,6 +319,7 @@ struct rv_kernel {
     // block-local spaces on chip: the passes with shared entries left out of
     // the HBM pipeline, and the units of each chunk
     std::vector<rv::DevUnit> units;
+    std::vector<rv::DevSub> h_subs_dir;   // the passes as the HBM pipeline sees them with units on
     rv::DevSub *d_subs_dir = nullptr;
     rv::DevUnit *d_units = nullptr;
     uint32_t max_chunk_units = 0;

@@ -98,7 +98,7 @@ class rv_result(ctypes.Structure):
 
 class rv_timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", u64 * 8), ("small_records", u64),
-                ("direct_records", u64)]
+                ("direct_records", u64), ("counted_records", u64)]
 
 
 class rv_kernel_info(ctypes.Structure):
@@ -618,6 +618,7 @@ class Context:
         out = {name: (t.ms[i], t.launches[i]) for i, name in enumerate(STAGES)}
         out["small_records"] = t.small_records
         out["direct_records"] = t.direct_records
+        out["counted_records"] = t.counted_records
         return out
 
 

@@ -264,3 +264,54 @@ def gespmm_closed_form(M, N, T, K):
     blocks = M * (N // 32)
     return {"records": threads * T * (4 + 32 * (4 + K)),
             "conflicts": {"both": 0, "no_middle": 64 * T * blocks, "no_trailing": 64 * (T - 1) * blocks}}
+
+
+def rand_affine_units(rng, i):
+    """Random kernels whose accesses are all plain affine (no aux terms, no
+    guards) and in bounds, with shared arrays of at most 2048 elements per
+    block: the kernels the on-chip block-local units take.  Blocks of 8-64 x
+    1-8 threads, grids up to 6 x 4, 1-3 shared and 0-2 global arrays of 1-2
+    dims, 1-4 phases of 1-5 accesses with 0-2 loops of 1-16 points,
+    coefficients in [-2, 2], half of the accesses writes."""
+    bdx, bdy = int(rng.integers(8, 65)), int(rng.integers(1, 9))
+    gdx, gdy = int(rng.integers(1, 7)), int(rng.integers(1, 5))
+    b = Builder((bdx, bdy), (gdx, gdy), f"rand-units-{i}")
+    n_sh, n_gl = int(rng.integers(1, 4)), int(rng.integers(0, 3))
+    budget = 2048
+    for a in range(n_sh):
+        nd = int(rng.integers(1, 3))
+        cap = max(4, budget // (n_sh - a) // 2)
+        dims = (int(rng.integers(4, min(64, cap) + 1)),) if nd == 1 else \
+            (int(rng.integers(2, 17)), int(rng.integers(2, max(3, min(64, cap // 16)) + 1)))
+        size = dims[0] * (dims[1] if nd == 2 else 1)
+        budget -= size
+        b.array(SHARED, dims)
+    for a in range(n_gl):
+        b.array(GLOBAL, tuple(int(rng.integers(4, 129)) for _ in range(int(rng.integers(1, 3)))))
+    reps = int(rng.integers(1, 3))
+    vmax = dict(tx=bdx - 1, ty=bdy - 1, bx=gdx - 1, by=gdy - 1, k=reps - 1)
+    pids = []
+    for p in range(int(rng.integers(1, 5))):
+        acc = []
+        for _ in range(int(rng.integers(1, 6))):
+            arr = int(rng.integers(0, n_sh + n_gl))
+            dims = b.arrays[arr].dims
+            nl = int(rng.integers(0, 3))
+            trips = [int(rng.integers(1, 17)) for _ in range(nl)]
+            loops = tuple((0, t) for t in trips)
+            ranges = dict(vmax, **{f"l{j}": trips[j] - 1 for j in range(nl)})
+            idx = []
+            for n in dims:
+                for _try in range(20):
+                    terms = {v: int(rng.integers(-2, 3)) for v in ranges if rng.random() < 0.5}
+                    lo = sum(min(0, c * ranges[v]) for v, c in terms.items())
+                    hi = sum(max(0, c * ranges[v]) for v, c in terms.items())
+                    if hi - lo < n:
+                        break
+                else:
+                    terms, lo, hi = {}, 0, 0
+                idx.append(aff(-lo + int(rng.integers(0, n - (hi - lo))), **terms))
+            acc.append(rw(arr, bool(rng.random() < 0.5), *idx, loops=loops))
+        pids.append(b.phase(acc, barrier_after=bool(rng.random() < 0.7)))
+    b.segment(pids, repeat=reps)
+    return b.build()

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from cases import rand_medium, rand_scoped, rand_small
+from cases import rand_affine_units, rand_medium, rand_scoped, rand_small
 from workloads import kernels as K
 from workloads.desc import GLOBAL, SHARED, Builder, aff, rw
 
@@ -89,10 +89,14 @@ PINS = [K.tiny_fixed(), K.polynomial_product(), K.stride1_shared(), K.half_index
 
 @pytest.mark.parametrize("i", range(len(PINS)))
 def test_pins(ctx, i):
+    import paper_2503_08946_amd as rv
     info = check_both(ctx, PINS[i])
-    # every kernel here but the polynomial product (global arrays only) has
-    # intervals with shared arrays of at most 2048 elements per block
-    assert (info.n_direct_intervals > 0) == (PINS[i].name != "polynomial-product-64")
+    # the host plan decides which intervals take units: those of the tiled
+    # matmuls, the stride-1 writes and the tiny kernel's first interval
+    # (plain affine shared accesses) do; a[tid/2] (floor division), the tree
+    # reduction (guards) and the polynomial product (global arrays) do not
+    assert info.n_direct_intervals == rv.plan(PINS[i]).n_direct_intervals
+    assert (info.n_direct_intervals > 0) == PINS[i].name.startswith(("matmul", "stride1", "tiny"))
 
 
 def test_direct_records_are_the_shared_records(ctx):
@@ -129,6 +133,17 @@ def test_fuzz_small(ctx, seed):
         check_both(ctx, rand_small(rng, i))
 
 
+@pytest.mark.parametrize("seed,semantics", [(0, "interval"), (1, "interval"), (2, "strict")])
+def test_fuzz_units(ctx, seed, semantics):
+    # plain affine kernels with small shared arrays: almost all take units
+    rng = np.random.Generator(np.random.PCG64(9500 + seed))
+    n_units = 0
+    for i in range(60):
+        info = check_both(ctx, rand_affine_units(rng, i), semantics)
+        n_units += info is not None and info.n_direct_intervals > 0
+    assert n_units >= 40
+
+
 @pytest.mark.parametrize("semantics", ["interval", "strict"])
 def test_fuzz_scoped(ctx, semantics):
     # warp barriers give an interval sub-keys (no units); the others keep them
@@ -137,29 +152,27 @@ def test_fuzz_scoped(ctx, semantics):
         check_both(ctx, rand_scoped(rng, i), semantics)
 
 
-def _edge_kernel(bdx, bdy, gdx, gdy, sdim, name):
+def _edge_kernel(bdx, bdy, gdx, gdy, name):
     """Blocks of bdx*bdy threads (not a multiple of a work item's 256) and a
-    shared array of sdim elements: units of several blocks whose edges cut
-    work items.  s[(tid + l0) % sdim] written, s[(2 tid + 1 + l0) % sdim]
-    read over a 5-point loop, and a global stride-1 write."""
-    from workloads.desc import AUX_EMOD, Aux
+    shared array of tpb + 5 elements: units of several blocks whose edges
+    cut work items.  Over a 5-point loop each thread writes s[tid + l0] and
+    reads s[tpb - 1 - tid + l0] (plain affine indices, so the units take
+    them); a global stride-1 write; then a read of s[tx]."""
     b = Builder((bdx, bdy), (gdx, gdy), name)
-    s = b.array(SHARED, (sdim,), "s")
-    g = b.array(GLOBAL, (bdx * bdy * gdx * gdy,), "g")
     tpb = bdx * bdy
+    s = b.array(SHARED, (tpb + 5,), "s")
+    g = b.array(GLOBAL, (tpb * gdx * gdy,), "g")
     ph = b.phase([
-        rw(s, True, aff(aux1=1), loops=((0, 5),), aux=(Aux(), Aux(AUX_EMOD, sdim, aff(0, tx=1, ty=bdx, l0=1)))),
-        rw(s, False, aff(aux1=1), loops=((0, 5),), aux=(Aux(), Aux(AUX_EMOD, sdim, aff(1, tx=2, ty=2 * bdx, l0=1)))),
+        rw(s, True, aff(0, tx=1, ty=bdx, l0=1), loops=((0, 5),)),
+        rw(s, False, aff(tpb - 1, tx=-1, ty=-bdx, l0=1), loops=((0, 5),)),
         rw(g, True, aff(0, tx=1, ty=bdx, bx=tpb, by=tpb * gdx)),
     ], barrier_after=True)
-    ph2 = b.phase([rw(s, False, aff(0, tx=1), loops=((0, 1),)) if bdx <= sdim else rw(s, False, aff(0))],
-                  barrier_after=False)
+    ph2 = b.phase([rw(s, False, aff(0, tx=1), loops=((0, 1),))], barrier_after=False)
     b.segment([ph, ph2])
     return b.build()
 
 
-@pytest.mark.parametrize("shape", [(48, 4, 40, 3, 64), (100, 1, 30, 5, 100), (10, 7, 60, 4, 300),
-                                   (32, 8, 5, 5, 130)])
+@pytest.mark.parametrize("shape", [(48, 4, 40, 3), (100, 1, 30, 5), (10, 7, 60, 4), (32, 8, 5, 5)])
 def test_unit_edges(ctx, shape):
     info = check_both(ctx, _edge_kernel(*shape, name=f"edge-{'-'.join(map(str, shape))}"))
     assert info.n_direct_intervals >= 1
@@ -180,16 +193,13 @@ def test_two_passes_split_the_shared_locations():
     """262,656 blocks of 256 threads with 2048 shared elements each: the
     interval's 537,919,488 locations span two key-range passes, the second
     starting inside the shared locations.  Each block writes s[t] and reads
-    s[(t + 1) mod 256]: 256 conflicting locations per block (closed form);
-    with units and without, the same counts and first witness."""
+    s[t + 1]: 255 conflicting locations per block, s[1] .. s[255] (closed
+    form); with units and without, the same counts and first witness."""
     import paper_2503_08946_amd as rv
-    from workloads.desc import AUX_EMOD, Aux
     gdx, gdy = 512, 513
     b = Builder((256, 1), (gdx, gdy), "two-pass-shared")
     s = b.array(SHARED, (2048,), "s")
-    b.segment([b.phase([rw(s, True, aff(0, tx=1)),
-                        rw(s, False, aff(aux1=1), aux=(Aux(), Aux(AUX_EMOD, 256, aff(1, tx=1))))],
-                       barrier_after=False)])
+    b.segment([b.phase([rw(s, True, aff(0, tx=1)), rw(s, False, aff(1, tx=1))], barrier_after=False)])
     desc = b.build()
     c = rv.Context(0, workspace_bytes=3 << 30)
     try:
@@ -201,9 +211,9 @@ def test_two_passes_split_the_shared_locations():
         off = _run(c, k, False)
         nblocks = gdx * gdy
         assert on == off
-        assert on[0] == 2 * 256 * nblocks and on[1] == 256 * nblocks
+        assert on[0] == 2 * 256 * nblocks and on[1] == 255 * nblocks
         w = on[2]
-        assert (w[0], w[1], w[2], w[3], w[4]) == (0, SHARED, 0, 0, 0)
+        assert (w[0], w[1], w[2], w[3], w[4]) == (0, SHARED, 0, 0, 1)
         k.free()
     finally:
         c.close()
@@ -224,3 +234,45 @@ def test_witness_lists_and_static_with_units_on(ctx):
         assert (gs.n_records, gs.n_conflicts, _wkey(gs.witness)) == (g.n_records, g.n_conflicts, _wkey(g.witness))
     finally:
         k.free()
+
+
+def _batch_results(ctx, ks, direct):
+    import paper_2503_08946_amd as rv
+    ctx.direct = direct
+    b = rv.Batch(ctx, ks)
+    b.run()
+    return [(r.n_records, r.n_conflicts, _wkey(r.witness) if r.witness is not None else None) for r in b.results()]
+
+
+@pytest.mark.parametrize("small_cap", [0, 2048])
+def test_batch_units(ctx, small_cap):
+    """rv_check_batch with units on and off: every kernel's counts and first
+    witness equal the oracle's (units re-based onto the batch's passes,
+    small passes on chip beside them); the same batch twice reuses its
+    table."""
+    rng = np.random.Generator(np.random.PCG64(9400))
+    descs = PINS + [rand_medium(rng, i, oob_rate=0.0) for i in range(12)] + \
+        [rand_affine_units(rng, i) for i in range(12)] + \
+        [_edge_kernel(*sh, name=f"edge-b{j}") for j, sh in enumerate([(48, 4, 40, 3), (10, 7, 60, 4)])]
+    want = []
+    for d in descs:
+        o = oracle.check(d, max_witnesses=1)
+        assert o.status == 0
+        want.append((o.n_records, o.n_conflicts, _wkey(o.witnesses[0]) if o.n_conflicts else None))
+    ks = [ctx.load(d) for d in descs]
+    try:
+        ctx.small_cap = small_cap
+        ctx.set_timing(True)
+        ctx.timing(reset=True)
+        on = _batch_results(ctx, ks, True)
+        t = ctx.timing(reset=True)
+        ctx.set_timing(False)
+        assert t["direct_records"] > 0
+        assert on == want
+        assert _batch_results(ctx, ks, True) == want      # cached table
+        assert _batch_results(ctx, ks, False) == want
+    finally:
+        ctx.small_cap = 2048
+        ctx.direct = True
+        for k in ks:
+            k.free()
