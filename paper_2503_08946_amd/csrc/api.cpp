@@ -49,6 +49,7 @@ struct Lane {
     hipEvent_t fork = nullptr, join = nullptr;
     uint64_t unit_records = 0;    // records of the last check's block-local units
     std::vector<uint32_t> count_slots;   // result slots of the last check's passes without writes
+    std::vector<unsigned long long> count_static;   // their proven entries' records, added on the host
     uint64_t counted_records = 0;        // their records (counted, never placed or grouped)
     void *h_up = nullptr;       // pinned: pass tables going up
     size_t up_cap = 0;
@@ -72,6 +73,7 @@ struct Lane {
     std::vector<TabChunk> tab_chunks;
     size_t tab_nreg = 0, tab_nsmall = 0;
     std::vector<uint32_t> tab_small_slots, tab_count_slots;
+    std::vector<unsigned long long> tab_count_static;
     bool tab_valid = false;
     // the batch in flight
     std::vector<rv_kernel *> jobs;
@@ -410,6 +412,7 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
     timed(c, ln, RV_STAGE_FILL, [&] { launch_init_results(ln.d_res, ns, s); });
     ln.unit_records = 0;
     ln.count_slots.clear();
+    ln.count_static.clear();
     if (resident) {
         const rv_kernel *k = ks[0];
         const bool direct = c->direct && k->d_subs_dir != nullptr;
@@ -420,7 +423,10 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
         }
         if (direct)
             for (uint32_t i = 0; i < k->h_subs_dir.size(); i++)
-                if (k->h_subs_dir[i].count_only) ln.count_slots.push_back(i);
+                if (k->h_subs_dir[i].count_only) {
+                    ln.count_slots.push_back(i);
+                    ln.count_static.push_back(k->h_subs_dir[i].static_records);
+                }
         for (auto &ch : k->chunks) {
             if (direct)
                 run_check_chunk(c, ln, k->d_subs_dir + ch.sub_begin, ch.sub_end - ch.sub_begin, ch.items_d,
@@ -444,6 +450,7 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
         if (ln.tab_valid && key == ln.tab_key) {
             ln.small_slots = ln.tab_small_slots;
             ln.count_slots = ln.tab_count_slots;
+            ln.count_static = ln.tab_count_static;
             if (ln.tab_nsmall)
                 timed(c, ln, RV_STAGE_SMALL, [&] {
                     launch_small(ln.d_subs + ln.tab_nreg, (uint32_t)ln.tab_nsmall, ln.d_res, c->ncu, s);
@@ -496,7 +503,10 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
                 D.item_begin = (uint32_t)cur.items;
                 D.bucket_begin = (uint32_t)cur.buckets;
                 D.res = (uint32_t)(ln.res0[j] + i);
-                if (D.count_only) ln.count_slots.push_back(D.res);
+                if (D.count_only) {
+                    ln.count_slots.push_back(D.res);
+                    ln.count_static.push_back(D.static_records);
+                }
                 if (dir)
                     for (uint32_t q = k.subs[i].unit_begin; q < k.subs[i].unit_end; q++) {
                         DevUnit U = k.units[q];
@@ -555,6 +565,7 @@ rv_status lane_enqueue(rv_ctx *c, Lane &ln, rv_kernel *const *ks, size_t n) {
         ln.tab_nsmall = small.size();
         ln.tab_small_slots = ln.small_slots;
         ln.tab_count_slots = ln.count_slots;
+        ln.tab_count_static = ln.count_static;
         ln.tab_valid = true;
         }
     }
@@ -573,7 +584,8 @@ launched:
 rv_status lane_collect(Lane &ln, rv_result *out, rv_status *status, std::string *msgs = nullptr) {
     HIP_TRY_L(ln, hipEventSynchronize(ln.done));
     ln.busy = false;
-    const SubResult *hr = reinterpret_cast<const SubResult *>(ln.h_down);
+    SubResult *hr = reinterpret_cast<SubResult *>(ln.h_down);
+    for (size_t q = 0; q < ln.count_slots.size(); q++) hr[ln.count_slots[q]].records += ln.count_static[q];
     ln.small_records = 0;
     for (uint32_t slot : ln.small_slots) ln.small_records += hr[slot].records;
     ln.unit_records = 0;

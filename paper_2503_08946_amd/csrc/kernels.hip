@@ -748,7 +748,9 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
         constexpr bool WAVE = V % 3 != 2;
         if (S.count_only) {
             // a pass without writes: its records and out-of-bounds instances
-            // are counted, nothing else (the whole workgroup takes this branch)
+            // are counted, nothing else (the whole workgroup takes this
+            // branch); with count_only 2 the host adds proven entries' records
+            if (V % 3 == 0 && S.count_only == 2) return;
             uint32_t n = 0;
             const uint32_t klo = S.klo, span = S.khi - S.klo;
             expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {

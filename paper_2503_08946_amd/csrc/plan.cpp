@@ -642,22 +642,34 @@ rv_status plan_chunks(rv_kernel &k, const WorkspaceLayout &L, std::string &msg) 
 // the shared ones, and their buckets.  count_only: none of the entries the
 // pipeline expands for the pass writes (a location without a write never
 // conflicts), so the pass is counted and has no buckets.
-static void hbm_part(const rv_kernel &k, const SubPlan &sp, uint32_t &klo, uint32_t &nb, uint32_t &count_only) {
+static void hbm_part(const rv_kernel &k, const SubPlan &sp, uint32_t &klo, uint32_t &nb, uint32_t &count_only,
+                     unsigned long long &static_records) {
     const IntervalPlan &I = k.intervals[sp.interval];
+    const uint64_t hbm_begin = I.direct ? (uint64_t)k.kc.nblocks * I.S : 0;
     klo = sp.klo;
     nb = sp.nb;
     if (I.direct) {
-        const uint64_t shared_end = (uint64_t)k.kc.nblocks * I.S;
-        klo = (uint32_t)std::min<uint64_t>(sp.khi, std::max<uint64_t>(sp.klo, shared_end));
+        klo = (uint32_t)std::min<uint64_t>(sp.khi, std::max<uint64_t>(sp.klo, hbm_begin));
         nb = (uint32_t)(((uint64_t)sp.khi - klo + (1ull << sp.s) - 1) >> sp.s);
     }
     bool writes = false;
+    uint64_t proven = 0;
     for (uint32_t e = I.entry_begin; e < I.entry_begin + I.entry_count; e++) {
         const DevEntry &E = k.entries[e];
-        if ((!I.direct || E.loc_mul == 0) && E.box > 0 && E.rw) writes = true;
+        if (!(!I.direct || E.loc_mul == 0) || E.box == 0) continue;
+        if (E.rw) writes = true;
+        if (E.fast == 2) proven += (uint64_t)E.box * k.kc.nthreads;
     }
     count_only = writes ? 0u : 1u;
-    if (count_only) nb = 0;
+    static_records = 0;
+    if (count_only) {
+        nb = 0;
+        // the pass holds every location its entries can reach
+        if (sp.klo <= hbm_begin && (uint64_t)sp.khi >= I.K) {
+            count_only = 2;
+            static_records = proven;
+        }
+    }
 }
 
 void plan_units(rv_kernel &k) {
@@ -672,7 +684,8 @@ void plan_units(rv_kernel &k) {
             const IntervalPlan &I = k.intervals[sp.interval];
             sp.unit_begin = sp.unit_end = (uint32_t)k.units.size();
             uint32_t hlo, hnb, co;
-            hbm_part(k, sp, hlo, hnb, co);
+            unsigned long long sr;
+            hbm_part(k, sp, hlo, hnb, co, sr);
             ch.items_d += I.direct ? I.items_g : I.items;
             ch.buckets_d += hnb;
             if (!I.direct) continue;
@@ -716,7 +729,7 @@ void make_devsubs(const rv_kernel &k, uint32_t sb, uint32_t se, uint32_t res0, s
         D.s = sp.s;
         D.klo = sp.klo;
         D.khi = sp.khi;
-        if (direct) hbm_part(k, sp, D.klo, D.nb, D.count_only);
+        if (direct) hbm_part(k, sp, D.klo, D.nb, D.count_only, D.static_records);
         D.M = (uint32_t)I.M;
         D.mgM = make_magic((uint32_t)I.M);
         D.interval = sp.interval;

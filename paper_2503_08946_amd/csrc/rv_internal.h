@@ -153,8 +153,13 @@ struct DevSub {
     Magic mg_unit;
     // 1: no entry this pass expands in the HBM pipeline writes, so none of
     // its locations can conflict: the count pass counts its records and
-    // out-of-bounds instances, and it has no records and no buckets.
+    // out-of-bounds instances, and it has no records and no buckets.  2: as
+    // 1, and the pass holds the whole key range of its entries, so the
+    // records of proven entries (every index inside its array over the
+    // launch and the loop box, no guards: box x threads each) are
+    // static_records, added on the host; the count pass evaluates the others.
     uint32_t count_only;
+    unsigned long long static_records;
 };
 
 // One unit of the on-chip check of block-local spaces: the shared-array
