@@ -2398,8 +2398,8 @@ __global__ void __launch_bounds__(BKT_WG) k_direct(const DevSub *subs_g, const D
                 if (pk != 0xFFFFFFFFu) T.seg(pk, cur);
             };
             if constexpr (V < 2) {
-                // one loop with points: a tile of threads takes the whole box
-                if (E.lin && E.box == E.ext[E.linner]) {
+                // the whole box affine in the point: a tile of threads takes it at once
+                if (E.lin && E.lflat) {
                     const uint32_t ta = U.t0 / EXP_WG, tb = (U.t1 + EXP_WG - 1u) / EXP_WG;
                     for (uint32_t tile = ta; tile < tb; tile++)
                         if (!dir_lin_box<(V == 0)>(E, K, tile, ulo, width, T, nrec))

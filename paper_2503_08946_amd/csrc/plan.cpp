@@ -448,9 +448,25 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                     // of the chunk, or it is the only loop with extent > 1)
                     const uint32_t inner = E.ext[2] > 1 ? 2u : E.ext[1] > 1 ? 1u : 0u;
                     const bool only = E.box == E.ext[inner];
+                    // mixed radix over the loops with points (outer to inner):
+                    // then any run of consecutive points is affine too
+                    bool radix = true;
+                    int prev = -1;
+                    for (int l = 0; l < 3; l++) {
+                        if (E.ext[l] <= 1) continue;
+                        if (prev >= 0) {
+                            radix = radix && E.fr[C_L0 + prev] == E.fr[C_L0 + l] * E.ext[l];
+                            if (E.fast != 2)
+                                for (int r = 0; r < 3; r++)
+                                    radix = radix && (int64_t)E.row[r][C_L0 + prev] ==
+                                                         (int64_t)E.row[r][C_L0 + l] * (int64_t)E.ext[l];
+                        }
+                        prev = l;
+                    }
                     E.linner = inner;
+                    E.lflat = (only || radix) ? 1u : 0u;
                     E.lin = (E.fast != 0 && E.box > 0 && E.gt == 1 &&
-                             (only || E.ext[inner] % E.lch == 0)) ? 1u : 0u;
+                             (E.lflat || E.ext[inner] % E.lch == 0)) ? 1u : 0u;
                 }
                 E.mg_nl = make_magic(std::max<uint32_t>(E.n_lchunks, 1));
                 E.mg_gt = make_magic(std::max<uint32_t>(E.gt, 1));

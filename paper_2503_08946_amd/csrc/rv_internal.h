@@ -111,6 +111,11 @@ struct DevEntry {
     // every index and the location are affine in the point of the chunk.
     uint32_t lin;
     uint32_t linner;
+    // The whole loop box is affine in the row-major point index (one loop
+    // with points, or coefficients in mixed radix: an outer loop's
+    // coefficient is the next inner one's times that loop's extent, for the
+    // location and, unless proven, every index), with step fr[linner].
+    uint32_t lflat;
     // Thread-linear items (fast entries of one instance per thread, flat
     // mapping, a lane's gt consecutive threads differ in tx alone): every
     // index and the location are affine in the slot.
