@@ -192,9 +192,12 @@ typedef struct {
                                   instance each of consecutive threads differing in tx alone
                                   (ranked per lane or per run, not per record, when they can be) */
     uint32_t n_fast_entries;   /* entries with neither aux terms nor guards (affine indices) */
-    uint32_t n_proven_entries; /* of which every index is proven inside its dimension over the
-                                  launch and the loop box (no per-record bounds test); a fast
-                                  entry that is not proven has an out-of-bounds instance */
+    uint32_t n_proven_entries; /* entries whose every index is proven inside its dimension (no
+                                  per-record bounds test): fast ones by the exact index range
+                                  over the launch and the loop box (a fast entry that is not
+                                  proven has an out-of-bounds instance), and entries with aux
+                                  terms and no guards by the value ranges of the variables and
+                                  of the aux terms (n mod d in [0, d)) */
     uint32_t n_direct_intervals; /* intervals whose block-local (shared-array) locations are
                                   grouped on chip, a unit of blocks per LDS table, when
                                   rv_check runs with the tuning's `direct` on */

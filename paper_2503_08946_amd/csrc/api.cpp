@@ -931,7 +931,7 @@ void fill_info(const rv_kernel &k, rv_kernel_info *out) {
         out->n_flat_entries += e.flat;
         out->n_linear_entries += e.lin + e.tlin;
         out->n_fast_entries += e.fast != 0;
-        out->n_proven_entries += e.fast == 2;
+        out->n_proven_entries += e.fast == 2 || e.gproven;
     }
     for (const auto &I : k.intervals) out->n_direct_intervals += I.direct;
 }

@@ -246,21 +246,78 @@ __device__ __forceinline__ ItemStart<FLAT> item_start(CEnt &E, CKer &K, uint32_t
     return a;
 }
 
-template <bool FLAT, class F>
-__device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t item, F &&f) {
+// General entries (aux terms or guards) advance with the loop.  A lane keeps
+// n mod d of each aux numerator n and one running sum per row (the location
+// when the entry is proven in bounds, else the three indices) that already
+// holds the aux terms' share.  A step moves n by q * d + r (0 <= r < d, split
+// on the host), so n mod d moves by r, less d on a carry, and floor(n / d) by
+// q plus the carry; each row adds a constant for the step and, on a carry,
+// the aux term's change.  Every point takes the inner loop's step; where the
+// inner loop wraps, a second step of the same form corrects it to the middle
+// loop's step, and where that wraps, a third to the outer loop's.  The
+// division itself runs once per thread of a work item.
+template <bool FLAT, bool GP, class F>
+__device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t item, F &&f) {
     const uint32_t lch = E.lch, gt = E.gt;
     const ItemStart<FLAT> st = item_start<FLAT>(E, K, item);
     const uint32_t lstart = st.lstart;
     const uint32_t lcnt = min(lch, E.box - lstart);
     const uint32_t e1 = E.ext[1], e2 = E.ext[2];
-    const uint32_t c0s = st.c0, c1s = st.c1, c2s = st.c2;
-    uint32_t c0 = c0s, c1 = c1s, c2 = c2s;
+    const bool aux[2] = {E.aux_kind[0] != 0, E.aux_kind[1] != 0};
+    const bool fd[2] = {E.aux_kind[0] == RV_AUX_FLOORDIV, E.aux_kind[1] == RV_AUX_FLOORDIV};
+    const uint32_t dv[2] = {E.aux_mg[0].d, E.aux_mg[1].d};
+    const uint32_t L0s = (uint32_t)E.lo[0] + st.c0, L1s = (uint32_t)E.lo[1] + st.c1, L2s = (uint32_t)E.lo[2] + st.c2;
+    constexpr int NR = GP ? 1 : 3;       // running sums: the location, or the three indices
+    // coefficient v of row r (GP: the flattened location row)
+    auto cf = [&](int r, int v) -> uint32_t {
+        if constexpr (GP) return E.fr[v];
+        else return (uint32_t)E.row[r][v];
+    };
+    auto lpart = [&](CI32 *row) {
+        return (uint32_t)row[C_L0] * L0s + (uint32_t)row[C_L1] * L1s + (uint32_t)row[C_L2] * L2s;
+    };
+    // per step form k (0: outer correction, 1: middle correction, 2: inner
+    // step): the aux splits, and each row's constant
+    uint32_t aq[2][3], ar[2][3], kc[NR][3], jc[2][NR], ts[NR];
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) { aq[x][k] = E.astep[x][k][0]; ar[x][k] = E.astep[x][k][1]; }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const uint32_t x2 = cf(r, C_L2), x1 = cf(r, C_L1) - cf(r, C_L2) * (e2 - 1);
+        const uint32_t x0 = cf(r, C_L0) - cf(r, C_L1) * (e1 - 1) - cf(r, C_L2) * (e2 - 1);
+        kc[r][2] = x2; kc[r][1] = x1 - x2; kc[r][0] = x0 - x1;
+        ts[r] = cf(r, C_L0) * L0s + cf(r, C_L1) * L1s + cf(r, C_L2) * L2s;
+#pragma unroll
+        for (int x = 0; x < 2; x++) {
+            const uint32_t ca = cf(r, C_A0 + x);
+#pragma unroll
+            for (int k = 0; k < 3; k++) kc[r][k] += ca * (fd[x] ? aq[x][k] : ar[x][k]);
+            jc[x][r] = fd[x] ? ca : 0u - ca * dv[x];
+        }
+    }
+    const uint32_t ns[2] = {aux[0] ? lpart(E.row[3]) : 0u, aux[1] ? lpart(E.row[4]) : 0u};
+    uint32_t c0 = st.c0, c1 = st.c1, c2 = st.c2;
     uint32_t gi = 0, li = 0;
     int32_t tx = 0, ty = 0, bx = 0, by = 0;
-    int32_t base[5] = {0, 0, 0, 0, 0};
+    uint32_t t[NR], rm[2] = {0, 0}, qt[2] = {0, 0};
     uint32_t idbase = 0, locbase = 0;
     bool gval = false;
-    const bool aux0 = E.aux_kind[0] != 0, aux1 = E.aux_kind[1] != 0;
+    auto apply = [&](int k) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) t[r] += kc[r][k];
+#pragma unroll
+        for (int x = 0; x < 2; x++) {
+            if (!aux[x]) continue;
+            const uint32_t rr = rm[x] + ar[x][k];
+            const bool cy = rr >= dv[x];
+            rm[x] = cy ? rr - dv[x] : rr;
+            if constexpr (!GP) qt[x] += aq[x][k] + (cy ? 1u : 0u);
+#pragma unroll
+            for (int r = 0; r < NR; r++) t[r] += cy ? jc[x][r] : 0u;
+        }
+    };
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const bool active = gi < gt;
@@ -276,44 +333,51 @@ __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, 
             ty = (int32_t)tyy;
             bx = (int32_t)(blk - byy * K.gdx);
             by = (int32_t)byy;
+            // thread part of a row plus its constant (modulo 2^32; the plan
+            // proved every value the row takes inside int32)
+            auto tpart = [&](int r) {
+                return cf(r, C_TX) * (uint32_t)tx + cf(r, C_TY) * (uint32_t)ty + cf(r, C_BX) * (uint32_t)bx +
+                       cf(r, C_BY) * (uint32_t)by + cf(r, C_C0);
+            };
+            uint32_t a[2] = {0, 0};
 #pragma unroll
-            for (int r = 0; r < 5; r++) {
-                if (r >= 3 && !(r == 3 ? aux0 : aux1)) continue;
-                base[r] = E.row[r][C_TX] * tx + E.row[r][C_TY] * ty + E.row[r][C_BX] * bx +
-                          E.row[r][C_BY] * by + E.row[r][C_C0];
+            for (int x = 0; x < 2; x++) {
+                if (!aux[x]) continue;
+                CI32 *row = E.row[3 + x];
+                const int32_t n = (int32_t)((uint32_t)row[C_TX] * (uint32_t)tx + (uint32_t)row[C_TY] * (uint32_t)ty +
+                                            (uint32_t)row[C_BX] * (uint32_t)bx + (uint32_t)row[C_BY] * (uint32_t)by +
+                                            (uint32_t)row[C_C0] + ns[x]);
+                const int32_t q = fdiv(n, ldm(E.aux_mg[x]));
+                qt[x] = (uint32_t)q;
+                rm[x] = (uint32_t)(n - q * (int32_t)dv[x]);
+                a[x] = fd[x] ? qt[x] : rm[x];
             }
+#pragma unroll
+            for (int r = 0; r < NR; r++) t[r] = tpart(r) + ts[r] + cf(r, C_A0) * a[0] + cf(r, C_A1) * a[1];
             idbase = gg * E.tmul + E.off + lstart;
-            locbase = blk * E.loc_mul + E.loc_base;
+            locbase = blk * E.loc_mul;
         }
         bool ok = false, inb = false;
         uint32_t loc = 0, id = 0;
         if (active) {
-            const int32_t L0 = E.lo[0] + (int32_t)c0, L1 = E.lo[1] + (int32_t)c1, L2 = E.lo[2] + (int32_t)c2;
-            int32_t a0 = 0, a1 = 0;
-            if (aux0) {
-                const int32_t n = base[3] + E.row[3][C_L0] * L0 + E.row[3][C_L1] * L1 + E.row[3][C_L2] * L2;
-                a0 = E.aux_kind[0] == RV_AUX_FLOORDIV ? fdiv(n, ldm(E.aux_mg[0])) : emod(n, ldm(E.aux_mg[0]));
-            }
-            if (aux1) {
-                const int32_t n = base[4] + E.row[4][C_L0] * L0 + E.row[4][C_L1] * L1 + E.row[4][C_L2] * L2;
-                a1 = E.aux_kind[1] == RV_AUX_FLOORDIV ? fdiv(n, ldm(E.aux_mg[1])) : emod(n, ldm(E.aux_mg[1]));
-            }
             ok = gval && li < lcnt;
-            for (uint32_t q = 0; q < E.guard_count; q++) {
-                CI32 *gr = G + (size_t)(E.guard_begin + q) * NC;
-                const int32_t gv = gr[C_TX] * tx + gr[C_TY] * ty + gr[C_BX] * bx + gr[C_BY] * by +
-                                   gr[C_L0] * L0 + gr[C_L1] * L1 + gr[C_L2] * L2 + gr[C_A0] * a0 +
-                                   gr[C_A1] * a1 + gr[C_C0];
-                ok = ok && gv >= 0;
+            if constexpr (GP) {
+                inb = true;
+                loc = locbase + t[0];
+            } else {
+                const int32_t L0 = E.lo[0] + (int32_t)c0, L1 = E.lo[1] + (int32_t)c1, L2 = E.lo[2] + (int32_t)c2;
+                const int32_t a0 = (int32_t)(fd[0] ? qt[0] : rm[0]), a1 = (int32_t)(fd[1] ? qt[1] : rm[1]);
+                for (uint32_t q = 0; q < E.guard_count; q++) {
+                    CI32 *gr = G + (size_t)(E.guard_begin + q) * NC;
+                    const int32_t gv = gr[C_TX] * tx + gr[C_TY] * ty + gr[C_BX] * bx + gr[C_BY] * by +
+                                       gr[C_L0] * L0 + gr[C_L1] * L1 + gr[C_L2] * L2 + gr[C_A0] * a0 +
+                                       gr[C_A1] * a1 + gr[C_C0];
+                    ok = ok && gv >= 0;
+                }
+                inb = t[0] < E.dim[0] && t[1] < E.dim[1] && t[2] < E.dim[2];
+                const uint32_t flat = (t[0] * E.dim[1] + t[1]) * E.dim[2] + t[2];
+                loc = locbase + E.loc_base + (flat << E.wshift);
             }
-            int32_t ix[3];
-#pragma unroll
-            for (int r = 0; r < 3; r++)
-                ix[r] = base[r] + E.row[r][C_L0] * L0 + E.row[r][C_L1] * L1 + E.row[r][C_L2] * L2 +
-                        E.row[r][C_A0] * a0 + E.row[r][C_A1] * a1;
-            inb = (uint32_t)ix[0] < E.dim[0] && (uint32_t)ix[1] < E.dim[1] && (uint32_t)ix[2] < E.dim[2];
-            const uint32_t flat = ((uint32_t)ix[0] * E.dim[1] + (uint32_t)ix[1]) * E.dim[2] + (uint32_t)ix[2];
-            loc = locbase + (flat << E.wshift);
             id = idbase + li;
         }
         f(s, ok, inb, loc, id);
@@ -322,13 +386,26 @@ __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, 
             if (li == lch) {
                 li = 0;
                 gi++;
-                c0 = c0s; c1 = c1s; c2 = c2s;
+                c0 = st.c0; c1 = st.c1; c2 = st.c2;
             } else {
+                apply(2);
                 c2++;
-                if (c2 == e2) { c2 = 0; c1++; if (c1 == e1) { c1 = 0; c0++; } }
+                if (c2 == e2) {
+                    c2 = 0;
+                    c1++;
+                    apply(1);
+                    if (c1 == e1) { c1 = 0; c0++; apply(0); }
+                }
             }
         }
     }
+}
+
+// Evaluate an entry with aux terms or guards (the general path).
+template <bool FLAT, class F>
+__device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t item, F &&f) {
+    if (E.gproven) expand_gen<FLAT, true>(S, E, K, G, item, f);
+    else expand_gen<FLAT, false>(S, E, K, G, item, f);
 }
 
 // Fast path of expand_item for entries without aux terms or guards: the
@@ -749,8 +826,9 @@ __global__ void __launch_bounds__(EXP_WG) k_hist(const DevSub *subs_g, uint32_t 
         if (S.count_only) {
             // a pass without writes: its records and out-of-bounds instances
             // are counted, nothing else (the whole workgroup takes this
-            // branch); with count_only 2 the host adds proven entries' records
-            if (V % 3 == 0 && S.count_only == 2) return;
+            // branch); with count_only 2 the host adds the records of entries
+            // proven in bounds (fast ones, and general ones without guards)
+            if (S.count_only == 2 && (V % 3 == 0 || (V % 3 == 2 && E.gproven))) return;
             uint32_t n = 0;
             const uint32_t klo = S.klo, span = S.khi - S.klo;
             expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {

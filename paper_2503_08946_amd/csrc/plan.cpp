@@ -412,6 +412,60 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                     }
                     if (proven) E.fast = 2u;
                 }
+                if (!fast && box > 0) {
+                    // floor division of a step by d, split into (q mod 2^32, r)
+                    auto split = [](int64_t s, int64_t d, uint32_t *qr) {
+                        int64_t q = s / d, r = s % d;
+                        if (r < 0) { r += d; q -= 1; }
+                        qr[0] = (uint32_t)(uint64_t)q;
+                        qr[1] = (uint32_t)r;
+                    };
+                    const int64_t e1 = E.ext[1], e2 = E.ext[2];
+                    int64_t alo[2] = {0, 0}, ahi[2] = {0, 0};
+                    int64_t vlo[NC] = {0}, vhi[NC] = {0};
+                    vhi[C_TX] = (int64_t)bdx - 1; vhi[C_TY] = (int64_t)bdy - 1;
+                    vhi[C_BX] = (int64_t)gdx - 1; vhi[C_BY] = (int64_t)gdy - 1;
+                    for (int l = 0; l < 3; l++) {
+                        vlo[C_L0 + l] = E.lo[l];
+                        vhi[C_L0 + l] = (int64_t)E.lo[l] + (int64_t)E.ext[l] - 1;
+                    }
+                    auto range = [&](const int32_t *row, int64_t &mn, int64_t &mx) {
+                        mn = mx = row[C_C0];
+                        for (int v = C_TX; v <= C_A1; v++) {
+                            const int64_t cf = row[v];
+                            mn += cf >= 0 ? cf * vlo[v] : cf * vhi[v];
+                            mx += cf >= 0 ? cf * vhi[v] : cf * vlo[v];
+                        }
+                    };
+                    for (int x = 0; x < 2; x++) {
+                        if (E.aux_kind[x] == RV_AUX_NONE) continue;
+                        const int64_t d = ac.aux[x].d;
+                        const int32_t *r = E.row[3 + x];
+                        // the numerator's change when the inner loop steps, and
+                        // the corrections from it to the middle loop's step and
+                        // from that to the outer loop's
+                        const int64_t x2 = r[C_L2], x1 = (int64_t)r[C_L1] - (int64_t)r[C_L2] * (e2 - 1);
+                        const int64_t x0 = (int64_t)r[C_L0] - (int64_t)r[C_L1] * (e1 - 1) - (int64_t)r[C_L2] * (e2 - 1);
+                        split(x0 - x1, d, E.astep[x][0]);
+                        split(x1 - x2, d, E.astep[x][1]);
+                        split(x2, d, E.astep[x][2]);
+                        // value range of the aux term (its numerator uses no aux variable)
+                        int64_t mn, mx;
+                        range(r, mn, mx);
+                        auto fl = [&](int64_t n) { return n >= 0 ? n / d : -((-n + d - 1) / d); };
+                        if (E.aux_kind[x] == RV_AUX_FLOORDIV) { alo[x] = fl(mn); ahi[x] = fl(mx); }
+                        else { alo[x] = 0; ahi[x] = d - 1; }
+                    }
+                    vlo[C_A0] = alo[0]; vhi[C_A0] = ahi[0];
+                    vlo[C_A1] = alo[1]; vhi[C_A1] = ahi[1];
+                    bool proven = E.guard_count == 0;
+                    for (int j = 0; j < 3 && proven; j++) {
+                        int64_t mn, mx;
+                        range(E.row[j], mn, mx);
+                        proven = mn >= 0 && mx < (int64_t)E.dim[j];
+                    }
+                    E.gproven = proven ? 1u : 0u;
+                }
                 // the flattened location row, modulo 2^32: sum over dims of stride * row
                 uint32_t stride = 1;
                 for (int v = 0; v < NC; v++) E.fr[v] = 0;
@@ -674,7 +728,7 @@ static void hbm_part(const rv_kernel &k, const SubPlan &sp, uint32_t &klo, uint3
         const DevEntry &E = k.entries[e];
         if (!(!I.direct || E.loc_mul == 0) || E.box == 0) continue;
         if (E.rw) writes = true;
-        if (E.fast == 2) proven += (uint64_t)E.box * k.kc.nthreads;
+        if (E.fast == 2 || E.gproven) proven += (uint64_t)E.box * k.kc.nthreads;
     }
     count_only = writes ? 0u : 1u;
     static_records = 0;

@@ -154,3 +154,28 @@ def test_plan_warp_barriers_and_strict():
     # a barrier kind outside 0..2
     bad = d.replace(phases=[d.phases[0].__class__(0, 1, 3), d.phases[1]])
     assert rv.validate(bad)[0] == -1
+
+
+def test_plan_proves_aux_indices():
+    """An entry with aux terms and no guards is proven in bounds from the
+    value ranges of its variables and aux terms: n mod d lies in [0, d), and
+    floor(n / d) between the quotients of the numerator's extremes."""
+    def one(idx, aux, dim=64, guards=()):
+        aux = tuple(aux) + (Aux(),) * (2 - len(aux))
+        return _one(rw(0, True, idx, loops=((0, 8),), aux=aux, guards=guards), arrays=((SHARED, (dim,)),))
+    emod = (Aux(AUX_EMOD, 64, aff(3, tx=5, l0=-7)),)
+    assert rv.plan(one(aff(aux0=1), emod)).n_proven_entries == 1
+    # s[aux0 + 1] reaches 64 when aux0 = 63
+    assert rv.plan(one(aff(1, aux0=1), emod)).n_proven_entries == 0
+    # a divisor above the dimension leaves the entry to the per-record test
+    assert rv.plan(one(aff(aux0=1), (Aux(AUX_EMOD, 65, aff(tx=1)),))).n_proven_entries == 0
+    # floor((tx + 8 l0) / 2) over tx in [0, 8), l0 in [0, 8): [0, 31]
+    fl = (Aux(AUX_FLOORDIV, 2, aff(tx=1, l0=8)),)
+    assert rv.plan(one(aff(aux0=1), fl, dim=32)).n_proven_entries == 1
+    assert rv.plan(one(aff(aux0=1), fl, dim=31)).n_proven_entries == 0
+    # guards keep the per-record path
+    assert rv.plan(one(aff(aux0=1), emod, guards=(aff(tx=1),))).n_proven_entries == 0
+    # the batched workload's kernels: every index is n mod dim of its dimension
+    for d in RA.batch_kernels(count=8):
+        info = rv.plan(d)
+        assert info.n_fast_entries == 0 and info.n_proven_entries == info.n_entries
