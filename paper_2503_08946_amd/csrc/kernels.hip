@@ -1679,6 +1679,23 @@ __device__ __forceinline__ uint32_t sub_of_bucket(CSub *subs, uint32_t nsub, uin
     return lo_s;
 }
 
+// A value every lane of the wave holds alike (an LDS word all lanes read),
+// moved to a scalar register so that what it indexes loads on the scalar unit.
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// The pass of bucket b, searching from pass `from` (at or below it) on.
+__device__ __forceinline__ uint32_t sub_from(CSub *subs, uint32_t from, uint32_t nsub, uint32_t b) {
+    uint32_t lo_s = from, hi_s = nsub;
+    if (lo_s + 1 >= hi_s || subs[lo_s + 1].bucket_begin > b) return lo_s;
+    while (hi_s - lo_s > 1) {
+        const uint32_t mid = (lo_s + hi_s) >> 1;
+        if (subs[mid].bucket_begin <= b) lo_s = mid; else hi_s = mid;
+    }
+    return lo_s;
+}
+
 // Unordered unit of an instance id: its thread's warp, or its block (upb = 1,
 // unit size = threads per block).
 __device__ __forceinline__ uint32_t unit_of(uint32_t id, Magic mgM, Magic mg_tpb, uint32_t tpb, Magic mg_unit,
@@ -1787,6 +1804,88 @@ __device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx,
     return tot0 + (total >> 16);
 }
 
+// Sparse buckets (at most WCAP records, no sub-keys) are folded by one wave
+// each, four at a time per workgroup, with wave barriers only.  The fold
+// lists the locations it touches first (the atomic that finds a slot empty),
+// so the judge visits those alone rather than the bucket's whole width; a
+// bit per location marks the conflicts, and a witness's place in location
+// order is the count of marked bits below it.
+constexpr uint32_t WCAP = 64 * FOLD_RPL;
+
+struct WaveTab {
+    uint32_t *mn, *mx, *mnw, *mxw1;
+    uint16_t *touched;      // locations in first-touch order (at most WCAP)
+    uint32_t *nt;           // their count
+    uint32_t *mask;         // TBL bits: the location holds a conflict
+    uint32_t *pre;          // conflicts in the mask words below each word
+};
+
+__device__ __forceinline__ void wave_fold_touch(const Run<64> &r, uint32_t lo, const WaveTab &W) {
+    Seg cur{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
+    uint32_t pk = 0xFFFFu;
+    auto flush = [&](uint32_t k) {
+        if (atomicMin(&W.mn[k], cur.mn) == 0xFFFFFFFFu) W.touched[atomicAdd(W.nt, 1u)] = (uint16_t)k;
+        atomicMax(&W.mx[k], cur.mx);
+        if (cur.mxw1) {
+            atomicMin(&W.mnw[k], cur.mnw);
+            atomicMax(&W.mxw1[k], cur.mxw1);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < FOLD_RPL; j++) {
+        if ((uint32_t)j < r.m) {
+            const uint32_t hi = (uint32_t)(r.x[j] >> 32);
+            const uint32_t k = (hi >> 1) - lo;
+            if (k != pk) {
+                if (pk != 0xFFFFu) flush(pk);
+                cur.mn = 0xFFFFFFFFu; cur.mx = 0; cur.mnw = 0xFFFFFFFFu; cur.mxw1 = 0;
+                pk = k;
+            }
+            seg_add(cur, (uint32_t)r.x[j], hi & 1u);
+        }
+    }
+    if (pk != 0xFFFFu) flush(pk);
+}
+
+// Judge the touched locations of a wave's folded bucket, write its witnesses
+// in location order at wout, leave the tables empty; returns the count.
+__device__ __forceinline__ uint32_t wave_judge(const WaveTab &W, uint32_t lo, Magic mgM, uint32_t *wout) {
+    constexpr uint32_t NW = TBL / 32;
+    static_assert(NW <= 64, "one mask word per lane");
+    const uint32_t ln = lane();
+    wave_sync_lds();
+    const uint32_t nt = *W.nt;
+    for (uint32_t j = ln; j < nt; j += 64) {
+        const uint32_t k = W.touched[j];
+        const Seg e{0u, W.mn[k], W.mx[k], W.mnw[k], W.mxw1[k]};
+        uint32_t sc, sr;
+        if (judge(e, mgM, sc, sr)) atomicOr(&W.mask[k >> 5], 1u << (k & 31));
+    }
+    wave_sync_lds();
+    const uint32_t mw = ln < NW ? W.mask[ln] : 0u;
+    const uint32_t inc = wave_incl_add((uint32_t)__builtin_popcount(mw));
+    if (ln < NW) W.pre[ln] = inc - (uint32_t)__builtin_popcount(mw);
+    const uint32_t total = readlane(inc, 63);
+    wave_sync_lds();
+    for (uint32_t j = ln; j < nt; j += 64) {
+        const uint32_t k = W.touched[j];
+        const Seg e{0u, W.mn[k], W.mx[k], W.mnw[k], W.mxw1[k]};
+        const uint32_t m = W.mask[k >> 5];
+        if ((m >> (k & 31)) & 1u) {
+            uint32_t sc = 0, sr = 0;
+            judge(e, mgM, sc, sr);
+            put_witness(wout, W.pre[k >> 5] + (uint32_t)__builtin_popcount(m & ((1u << (k & 31)) - 1u)), lo + k, e,
+                        sc, sr);
+        }
+        W.mn[k] = 0xFFFFFFFFu; W.mx[k] = 0; W.mnw[k] = 0xFFFFFFFFu; W.mxw1[k] = 0;
+    }
+    wave_sync_lds();
+    if (ln < NW) W.mask[ln] = 0;
+    if (ln == 0) *W.nt = 0;
+    wave_sync_lds();
+    return total;
+}
+
 // The fold deals groups of up to FOLD_GROUP consecutive buckets out
 // cyclically (workgroups of one XCD take adjacent groups of each round),
 // which evens out buckets of different sizes across workgroups; with few
@@ -1804,9 +1903,16 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
                                                   const uint32_t *__restrict__ starts,
                                                   const uint32_t *__restrict__ counts, uint32_t *__restrict__ conf,
                                                   HotArea hot) {
-    __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
-    __shared__ uint32_t l_b[BKT_WG], l_cnt[BKT_WG], l_st[BKT_WG], l_hot[BKT_WG];
+    // four waves' tables (the workgroup's buckets use wave 0's)
+    __shared__ uint32_t wt[BKT_WG / 64][4][TBL];
+    __shared__ uint16_t w_touched[BKT_WG / 64][WCAP];
+    __shared__ uint32_t w_nt[BKT_WG / 64], w_mask[BKT_WG / 64][TBL / 32], w_pre[BKT_WG / 64][TBL / 32];
+    // a group lists at most FOLD_GROUP buckets
+    __shared__ uint32_t l_b[FOLD_GROUP], l_cnt[FOLD_GROUP], l_st[FOLD_GROUP], l_hot[FOLD_GROUP], l_sub[FOLD_GROUP];
+    __shared__ uint32_t v_b[FOLD_GROUP], v_cnt[FOLD_GROUP], v_st[FOLD_GROUP], v_sub[FOLD_GROUP];
+    __shared__ uint32_t p_beg[FOLD_GROUP + 1];
     __shared__ uint32_t red[BKT_WG / 64];
+    uint32_t *const t_mn = wt[0][0], *const t_mx = wt[0][1], *const t_mnw = wt[0][2], *const t_mxw1 = wt[0][3];
     CSub *subs = cptr(subs_g);
     const uint32_t t = threadIdx.x;
     const uint32_t G = gridDim.x;                  // multiple of 8
@@ -1814,31 +1920,68 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
     const uint32_t gsz = GS ? GS : deal_chunk(nbuckets, G, FOLD_GROUP);
     if (r * gsz >= nbuckets) return;
     uint32_t sidx = sub_of_bucket(subs, nsub, r * gsz);   // groups only increase: walk forward
-#pragma unroll
-    for (int k2 = 0; k2 < TBL / BKT_WG; k2++) {
-        const uint32_t k = t + k2 * BKT_WG;
-        t_mn[k] = 0xFFFFFFFFu; t_mx[k] = 0; t_mnw[k] = 0xFFFFFFFFu; t_mxw1[k] = 0;
+    const uint32_t wv = t >> 6;
+    const WaveTab W{wt[wv][0], wt[wv][1], wt[wv][2], wt[wv][3], w_touched[wv], &w_nt[wv], w_mask[wv], w_pre[wv]};
+    for (uint32_t k = t; k < (BKT_WG / 64) * TBL; k += BKT_WG) {
+        const uint32_t q = k / TBL, e = k % TBL;
+        wt[q][0][e] = 0xFFFFFFFFu; wt[q][1][e] = 0; wt[q][2][e] = 0xFFFFFFFFu; wt[q][3][e] = 0;
     }
+    if (t < (BKT_WG / 64) * (TBL / 32)) w_mask[t / (TBL / 32)][t % (TBL / 32)] = 0;
+    if (t < BKT_WG / 64) w_nt[t] = 0;
     for (uint32_t base = r * gsz; base < nbuckets; base += G * gsz) {
-        // --- list this group's non-empty buckets (in order) and the hot ones
+        // --- list this group's non-empty buckets (in order): sparse ones of
+        // passes without sub-keys for the waves, the others for the
+        // workgroup, and the hot ones
         const uint32_t b1 = min(nbuckets, base + gsz);
         const uint32_t mb = base + t;
         const bool inr = t < gsz && mb < b1;
         const uint32_t c = inr ? counts[mb] : 0u;
-        const bool take = c != 0 && c <= FOLD_CAP;
+        // the pass of each bucket: the last pass starting at or below it
+        // (passes without buckets start where the next one does), from the
+        // group's first pass and the starts of the FOLD_GROUP after it
+        sidx = sub_from(subs, sidx, nsub, base);
+        uint32_t ms = sidx;
+        bool nosub = subs[sidx].wshift == 0;
+        if (b1 > subs[sidx].bucket_begin + subs[sidx].nb) {     // the group spans passes
+            if (t <= FOLD_GROUP) p_beg[t] = sidx + t < nsub ? subs[sidx + t].bucket_begin : 0xFFFFFFFFu;
+            __syncthreads();
+            if (inr) {
+                if (mb >= p_beg[FOLD_GROUP]) {
+                    ms = sub_from(subs, sidx + FOLD_GROUP, nsub, mb);    // many passes without buckets
+                } else {
+                    uint32_t lo2 = 0, hi2 = FOLD_GROUP;     // p_beg[lo2] <= mb < p_beg[hi2]
+                    while (hi2 - lo2 > 1) {
+                        const uint32_t mid = (lo2 + hi2) >> 1;
+                        if (p_beg[mid] <= mb) lo2 = mid; else hi2 = mid;
+                    }
+                    ms = sidx + lo2;
+                }
+                nosub = subs[ms].wshift == 0;
+            }
+        }
+        const bool wave = c != 0 && c <= WCAP && nosub;
+        const bool take = c != 0 && c <= FOLD_CAP && !wave;
         const bool is_hot = c > HOT;
         if (c > FOLD_CAP && !is_hot) {                   // medium: k_mid folds it
             const uint32_t slot = atomicAdd(hot.mid_n, 1u);
             if (slot < hot.mid_cap) hot.mid_list[slot] = mb;
         }
-        if (inr && !take) conf[mb] = 0;
-        uint32_t both;     // listed buckets in the low half, hot ones in the high half
-        const uint32_t pos = block_excl_add<BKT_WG>((take ? 1u : 0u) | (is_hot ? 0x10000u : 0u), red, &both);
-        const uint32_t nl = both & 0xFFFFu, nh = both >> 16;
-        if (take) { l_b[pos & 0xFFFFu] = mb; l_cnt[pos & 0xFFFFu] = c; l_st[pos & 0xFFFFu] = starts[mb]; }
+        if (inr && !take && !wave) conf[mb] = 0;
+        uint32_t all;      // fields of 10 bits: workgroup list, hot list, wave list
+        const uint32_t pos = block_excl_add<BKT_WG>((take ? 1u : 0u) | (is_hot ? 1u << 10 : 0u) |
+                                                    (wave ? 1u << 20 : 0u), red, &all);
+        const uint32_t nl = all & 1023u, nh = (all >> 10) & 1023u, nv = all >> 20;
+        if (take) {
+            const uint32_t p = pos & 1023u;
+            l_b[p] = mb; l_cnt[p] = c; l_st[p] = starts[mb]; l_sub[p] = ms;
+        }
+        if (wave) {
+            const uint32_t p = pos >> 20;
+            v_b[p] = mb; v_cnt[p] = c; v_st[p] = starts[mb]; v_sub[p] = ms;
+        }
         if (is_hot) {
             const uint32_t slot = atomicAdd(hot.n, 1u);
-            l_hot[pos >> 16] = slot;
+            l_hot[(pos >> 10) & 1023u] = slot;
             if (slot < hot.cap) { hot.list[slot] = mb; hot.done[slot] = 0; }
         }
         __syncthreads();
@@ -1849,17 +1992,42 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
                 for (uint32_t k = t; k < 4u * TBL; k += BKT_WG) g[k] = (k / TBL) % 2 == 0 ? 0xFFFFFFFFu : 0u;
             }
         }
+        // --- sparse buckets: wave wv folds list entries wv, wv + 4, ...; the
+        // next one's records load while one is folded
+        if (wv < nv) {
+            auto wprocess = [&](uint32_t i, const Run<64> &cur) {
+                CSub &S = subs[uni(v_sub[i])];
+                const uint32_t b = uni(v_b[i]);
+                const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
+                wave_fold_touch(cur, lo, W);
+                const uint32_t total = wave_judge(W, lo, ldm(S.mgM), reinterpret_cast<uint32_t *>(rec + uni(v_st[i])));
+                if (lane() == 0) conf[b] = total;
+            };
+            constexpr uint32_t NWV = BKT_WG / 64;
+            const uint32_t last = wv + (nv - 1 - wv) / NWV * NWV;     // this wave's last entry
+            Run<64> A, B;
+            run_load(A, rec + uni(v_st[wv]), uni(v_cnt[wv]), lane());
+            run_load(B, rec + uni(v_st[min(wv + NWV, last)]), uni(v_cnt[min(wv + NWV, last)]), lane());
+            for (uint32_t i = wv; i < nv; i += 2 * NWV) {
+                wprocess(i, A);
+                const uint32_t ja = min(i + 2 * NWV, last);
+                run_load(A, rec + uni(v_st[ja]), uni(v_cnt[ja]), lane());
+                if (i + NWV < nv) wprocess(i + NWV, B);
+                const uint32_t jb = min(i + 3 * NWV, last);
+                run_load(B, rec + uni(v_st[jb]), uni(v_cnt[jb]), lane());
+            }
+        }
+        if (nv && nl) __syncthreads();      // wave 0's tables serve the workgroup next
         // --- fold the listed buckets; slice 0 of the next one loads meanwhile
         // Two register sets alternate: while bucket i is folded from one, the
         // other already holds (or is loading) bucket i + 1, and set A is
         // reloaded with bucket i + 2 as soon as bucket i is done.  Loads are
         // unconditional (the list index is clamped) so the compiler keeps
         // exactly the other set in flight.
-        auto slice_of = [&](uint32_t j) { return min((uint32_t)(BKT_WG * FOLD_RPL), l_cnt[j]); };
+        auto slice_of = [&](uint32_t j) { return min((uint32_t)(BKT_WG * FOLD_RPL), uni(l_cnt[j])); };
         auto process = [&](uint32_t i, const Run<BKT_WG> &cur) {
-            const uint32_t b = l_b[i], start = l_st[i];
-            while (b >= subs[sidx].bucket_begin + subs[sidx].nb) sidx++;
-            CSub &S = subs[sidx];
+            const uint32_t b = uni(l_b[i]), start = uni(l_st[i]);
+            CSub &S = subs[uni(l_sub[i])];
             const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
             const uint32_t width = min(1u << S.s, S.khi - lo);
             // the tables are empty here: cleared before the first bucket, and
@@ -1872,15 +2040,15 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
         };
         if (nl) {
             Run<BKT_WG> A, B;
-            run_load(A, rec + l_st[0], slice_of(0), t);
-            run_load(B, rec + l_st[min(1u, nl - 1)], slice_of(min(1u, nl - 1)), t);
+            run_load(A, rec + uni(l_st[0]), slice_of(0), t);
+            run_load(B, rec + uni(l_st[min(1u, nl - 1)]), slice_of(min(1u, nl - 1)), t);
             for (uint32_t i = 0; i < nl; i += 2) {
                 process(i, A);
                 const uint32_t ja = min(i + 2, nl - 1);
-                run_load(A, rec + l_st[ja], slice_of(ja), t);
+                run_load(A, rec + uni(l_st[ja]), slice_of(ja), t);
                 if (i + 1 < nl) process(i + 1, B);
                 const uint32_t jb = min(i + 3, nl - 1);
-                run_load(B, rec + l_st[jb], slice_of(jb), t);
+                run_load(B, rec + uni(l_st[jb]), slice_of(jb), t);
             }
         }
         __syncthreads();     // the list is rebuilt for the next group
