@@ -230,9 +230,16 @@ __device__ __forceinline__ ItemStart<FLAT> item_start(CEnt &E, CKer &K, uint32_t
         a.gstep = EXP_WG;
     } else {
         const uint32_t q = li * EXP_WG + threadIdx.x;
-        const uint32_t tg = udiv(q, ldm(E.mg_nl));
         const bool qv = q < E.nq;
-        a.lstart = qv ? (q - tg * nl) * E.lch : 0u;
+        uint32_t tg, lchunk;
+        if (E.cmaj) {       // chunk-major: neighbouring lanes take neighbouring thread groups
+            lchunk = udiv(q, ldm(E.mg_ntg));
+            tg = q - lchunk * E.ntg;
+        } else {
+            tg = udiv(q, ldm(E.mg_nl));
+            lchunk = q - tg * nl;
+        }
+        a.lstart = qv ? lchunk * E.lch : 0u;
         a.g0 = qv ? tg * E.gt : K.nthreads;     // past the last thread: every slot invalid
         a.gstep = 1;
     }
@@ -263,7 +270,8 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
     const uint32_t lstart = st.lstart;
     const uint32_t lcnt = min(lch, E.box - lstart);
     const uint32_t e1 = E.ext[1], e2 = E.ext[2];
-    const bool aux[2] = {E.aux_kind[0] != 0, E.aux_kind[1] != 0};
+    // an absent aux term has d = 1, a zero numerator and zero steps: it
+    // stays 0 and never carries
     const bool fd[2] = {E.aux_kind[0] == RV_AUX_FLOORDIV, E.aux_kind[1] == RV_AUX_FLOORDIV};
     const uint32_t dv[2] = {E.aux_mg[0].d, E.aux_mg[1].d};
     const uint32_t L0s = (uint32_t)E.lo[0] + st.c0, L1s = (uint32_t)E.lo[1] + st.c1, L2s = (uint32_t)E.lo[2] + st.c2;
@@ -297,7 +305,7 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
             jc[x][r] = fd[x] ? ca : 0u - ca * dv[x];
         }
     }
-    const uint32_t ns[2] = {aux[0] ? lpart(E.row[3]) : 0u, aux[1] ? lpart(E.row[4]) : 0u};
+    const uint32_t ns[2] = {lpart(E.row[3]), lpart(E.row[4])};
     uint32_t c0 = st.c0, c1 = st.c1, c2 = st.c2;
     uint32_t gi = 0, li = 0;
     int32_t tx = 0, ty = 0, bx = 0, by = 0;
@@ -309,7 +317,6 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
         for (int r = 0; r < NR; r++) t[r] += kc[r][k];
 #pragma unroll
         for (int x = 0; x < 2; x++) {
-            if (!aux[x]) continue;
             const uint32_t rr = rm[x] + ar[x][k];
             const bool cy = rr >= dv[x];
             rm[x] = cy ? rr - dv[x] : rr;
@@ -339,10 +346,9 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
                 return cf(r, C_TX) * (uint32_t)tx + cf(r, C_TY) * (uint32_t)ty + cf(r, C_BX) * (uint32_t)bx +
                        cf(r, C_BY) * (uint32_t)by + cf(r, C_C0);
             };
-            uint32_t a[2] = {0, 0};
+            uint32_t a[2];
 #pragma unroll
             for (int x = 0; x < 2; x++) {
-                if (!aux[x]) continue;
                 CI32 *row = E.row[3 + x];
                 const int32_t n = (int32_t)((uint32_t)row[C_TX] * (uint32_t)tx + (uint32_t)row[C_TY] * (uint32_t)ty +
                                             (uint32_t)row[C_BX] * (uint32_t)bx + (uint32_t)row[C_BY] * (uint32_t)by +

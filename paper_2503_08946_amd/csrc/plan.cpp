@@ -542,6 +542,9 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                     E.tlin = (E.fast != 0 && E.box == 1 && bdx % E.gt == 0) ? 1u : 0u;
                     if (E.tlin) E.flat = 1;
                     E.nq = E.flat ? (uint32_t)nq : 0u;
+                    E.cmaj = (E.flat && E.fast == 0) ? 1u : 0u;
+                    E.ntg = (uint32_t)ntg;
+                    E.mg_ntg = make_magic((uint32_t)std::max<uint64_t>(ntg, 1));
                 }
                 M += box;
                 k.entries.push_back(E);

@@ -96,6 +96,12 @@ struct DevEntry {
     // of threads still fills the lanes.
     uint32_t flat;
     uint32_t nq;               // flat: thread groups x loop chunks
+    // Flat entries of the general path: chunk-major lanes (lane q takes
+    // thread group q % ntg at loop chunk q / ntg), so the lanes of a wave
+    // mostly share their loop counters and step the loops together.
+    uint32_t cmaj;
+    uint32_t ntg;              // thread groups: ceil(threads / gt)
+    Magic mg_ntg;
     Magic mg_nl, mg_e1, mg_e2; // divisions by n_lchunks, ext[1], ext[2]
     Magic mg_gt;               // division by gt
     // Fast path (no aux terms, no guards): the location as one affine row
