@@ -2261,29 +2261,32 @@ __global__ void k_gather(const DevSub *subs_g, uint32_t nsub, const unsigned lon
 // its records touching HBM.  The workgroup expands every work item of the
 // pass and folds each record into a per-location summary held in an LDS
 // hash table (open addressing on the location key, linear probing, at most
-// half full since a pass has at most SMALL_CAP locations); each lane first
-// merges its consecutive records of one location in registers.  The judge
+// half full: the table has the first power of two of at least twice the
+// pass's instances, 64 to 2 SMALL_CAP slots); each lane first merges its
+// consecutive records of one location in registers.  A slot keeps the
+// smallest id, the largest 2 id + rw and the smallest write id (ids of a
+// small pass are below SMALL_CAP), so two workgroups share a CU.  The judge
 // then scans the table: the pass's conflict count, and the witness of its
 // smallest conflicting location.  Passes are dealt to the persistent
 // workgroups cyclically.
 constexpr uint32_t SMALL_HASH = 2 * SMALL_CAP;
+static_assert(SMALL_HASH == 4096, "small tables hash to at most 12 bits");
 
-__device__ __forceinline__ uint32_t small_slot(uint32_t *keys, uint32_t loc, uint32_t &over) {
-    uint32_t h = (loc * 0x9E3779B1u) >> (32 - 12);        // SMALL_HASH = 4096 slots
-    for (uint32_t n = 0; n < SMALL_HASH; n++) {
+__device__ __forceinline__ uint32_t small_slot(uint32_t *keys, uint32_t loc, uint32_t hb, uint32_t &over) {
+    const uint32_t mask = (1u << hb) - 1u;
+    uint32_t h = (loc * 0x9E3779B1u) >> (32 - hb);
+    for (uint32_t n = 0; n <= mask; n++) {
         const uint32_t k = atomicCAS(&keys[h], 0xFFFFFFFFu, loc);
         if (k == 0xFFFFFFFFu || k == loc) return h;
-        h = (h + 1) & (SMALL_HASH - 1);
+        h = (h + 1) & mask;
     }
     over = 1;
     return 0xFFFFFFFFu;
 }
-static_assert(SMALL_HASH == 4096, "small_slot hashes to 12 bits");
 
 __global__ void __launch_bounds__(BKT_WG) k_small(const DevSub *subs_g, uint32_t nsub,
                                                   SubResult *__restrict__ res) {
-    __shared__ uint32_t keys[SMALL_HASH], t_mn[SMALL_HASH], t_mx[SMALL_HASH], t_mnw[SMALL_HASH],
-        t_mxw1[SMALL_HASH];
+    __shared__ uint32_t keys[SMALL_HASH], t_mn[SMALL_HASH], t_mx2[SMALL_HASH], t_mnw[SMALL_HASH];
     __shared__ uint32_t red[BKT_WG / 64];
     __shared__ uint32_t s_over, s_first;
     __shared__ unsigned long long s_oob;
@@ -2292,9 +2295,14 @@ __global__ void __launch_bounds__(BKT_WG) k_small(const DevSub *subs_g, uint32_t
     for (uint32_t j = blockIdx.x; j < nsub; j += gridDim.x) {
         CSub &S = subs[j];
         CKer &K = *cptr(S.kc);
-        for (uint32_t i = t; i < SMALL_HASH; i += BKT_WG) {
+        // table bits: 2^hb >= 2 x the pass's instances (M per thread)
+        const uint32_t P = S.M * K.nthreads;
+        uint32_t hb = 6;
+        while (hb < 12 && (1u << hb) < 2u * P) hb++;
+        const uint32_t slots = 1u << hb;
+        for (uint32_t i = t; i < slots; i += BKT_WG) {
             keys[i] = 0xFFFFFFFFu;
-            t_mn[i] = 0xFFFFFFFFu; t_mx[i] = 0; t_mnw[i] = 0xFFFFFFFFu; t_mxw1[i] = 0;
+            t_mn[i] = 0xFFFFFFFFu; t_mx2[i] = 0; t_mnw[i] = 0xFFFFFFFFu;
         }
         if (t == 0) { s_over = 0; s_first = 0xFFFFFFFFu; s_oob = ~0ull; }
         __syncthreads();
@@ -2314,8 +2322,11 @@ __global__ void __launch_bounds__(BKT_WG) k_small(const DevSub *subs_g, uint32_t
                     uint32_t pk = 0xFFFFFFFFu;
                     auto flush = [&]() {
                         if (pk == 0xFFFFFFFFu) return;
-                        const uint32_t h = small_slot(keys, pk, s_over);
-                        if (h != 0xFFFFFFFFu) fold(t_mn, t_mx, t_mnw, t_mxw1, h, cur);
+                        const uint32_t h = small_slot(keys, pk, hb, s_over);
+                        if (h == 0xFFFFFFFFu) return;
+                        atomicMin(&t_mn[h], cur.mn);
+                        atomicMax(&t_mx2[h], 2u * cur.mx + (cur.mxw1 == cur.mx + 1u ? 1u : 0u));
+                        if (cur.mxw1) atomicMin(&t_mnw[h], cur.mnw);
                     };
                     expand_v(variant, S, E, K, li, [&](int, bool ok, bool inb, uint32_t loc, uint32_t id) {
                         if (ok && !inb) atomicMin(&s_oob, ((unsigned long long)S.interval << 32) | id);
@@ -2342,22 +2353,29 @@ __global__ void __launch_bounds__(BKT_WG) k_small(const DevSub *subs_g, uint32_t
         }
         uint32_t total_rec;
         block_excl_add<BKT_WG>(nrec, red, &total_rec);      // its barriers also end the folding
-        // --- judge: count, and the smallest conflicting location
+        // --- judge: count, and the smallest conflicting location.  A slot
+        // reads back as a summary whose mxw1 is max write id + 1 when the
+        // largest id writes, 0 without writes, and otherwise a value that is
+        // neither (the judge only tests it against 0 and mx + 1).
+        auto get = [&](uint32_t i) {
+            const uint32_t a = t_mn[i], m2 = t_mx2[i], w = t_mnw[i];
+            const uint32_t mx = m2 >> 1;
+            return Seg{0u, a, mx, w, w == 0xFFFFFFFFu ? 0u : ((m2 & 1u) ? mx + 1u : mx)};
+        };
         const Magic mgM = ldm(S.mgM);
         uint32_t nc = 0;
-        for (uint32_t i = t; i < SMALL_HASH; i += BKT_WG) {
+        for (uint32_t i = t; i < slots; i += BKT_WG) {
             if (keys[i] == 0xFFFFFFFFu) continue;
-            const Seg x{0u, t_mn[i], t_mx[i], t_mnw[i], t_mxw1[i]};
             uint32_t sc, sr;
-            if (judge(x, mgM, sc, sr)) { nc++; atomicMin(&s_first, keys[i]); }
+            if (judge(get(i), mgM, sc, sr)) { nc++; atomicMin(&s_first, keys[i]); }
         }
         uint32_t total;
         block_excl_add<BKT_WG>(nc, red, &total);
         if (total) {
             const uint32_t fl = s_first;
-            for (uint32_t i = t; i < SMALL_HASH; i += BKT_WG) {
+            for (uint32_t i = t; i < slots; i += BKT_WG) {
                 if (keys[i] != fl) continue;
-                const Seg x{0u, t_mn[i], t_mx[i], t_mnw[i], t_mxw1[i]};
+                const Seg x = get(i);
                 uint32_t sc = 0, sr = 0;
                 judge(x, mgM, sc, sr);
                 SubResult &R = res[S.res];
