@@ -259,10 +259,10 @@ __device__ __forceinline__ ItemStart<FLAT> item_start(CEnt &E, CKer &K, uint32_t
 // holds the aux terms' share.  A step moves n by q * d + r (0 <= r < d, split
 // on the host), so n mod d moves by r, less d on a carry, and floor(n / d) by
 // q plus the carry; each row adds a constant for the step and, on a carry,
-// the aux term's change.  Every point takes the inner loop's step; where the
-// inner loop wraps, a second step of the same form corrects it to the middle
-// loop's step, and where that wraps, a third to the outer loop's.  The
-// division itself runs once per thread of a work item.
+// the aux term's change.  A point takes the inner loop's step, or where the
+// inner loop wraps the middle loop's, or where that wraps the outer loop's
+// (each lane picks its own, so lanes at different points cost one step).
+// The division itself runs once per thread of a work item.
 template <bool FLAT, bool GP, class F>
 __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t item, F &&f) {
     const uint32_t lch = E.lch, gt = E.gt;
@@ -295,7 +295,7 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
     for (int r = 0; r < NR; r++) {
         const uint32_t x2 = cf(r, C_L2), x1 = cf(r, C_L1) - cf(r, C_L2) * (e2 - 1);
         const uint32_t x0 = cf(r, C_L0) - cf(r, C_L1) * (e1 - 1) - cf(r, C_L2) * (e2 - 1);
-        kc[r][2] = x2; kc[r][1] = x1 - x2; kc[r][0] = x0 - x1;
+        kc[r][2] = x2; kc[r][1] = x1; kc[r][0] = x0;
         ts[r] = cf(r, C_L0) * L0s + cf(r, C_L1) * L1s + cf(r, C_L2) * L2s;
 #pragma unroll
         for (int x = 0; x < 2; x++) {
@@ -312,15 +312,18 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
     uint32_t t[NR], rm[2] = {0, 0}, qt[2] = {0, 0};
     uint32_t idbase = 0, locbase = 0;
     bool gval = false;
-    auto apply = [&](int k) {
+    // one step of form 0, 1 or 2 (w0: the outer loop advances, else w1: the
+    // middle one, else the inner one)
+    auto apply = [&](bool w0, bool w1) {
+        auto pick = [&](uint32_t v0, uint32_t v1, uint32_t v2) { return w0 ? v0 : w1 ? v1 : v2; };
 #pragma unroll
-        for (int r = 0; r < NR; r++) t[r] += kc[r][k];
+        for (int r = 0; r < NR; r++) t[r] += pick(kc[r][0], kc[r][1], kc[r][2]);
 #pragma unroll
         for (int x = 0; x < 2; x++) {
-            const uint32_t rr = rm[x] + ar[x][k];
+            const uint32_t rr = rm[x] + pick(ar[x][0], ar[x][1], ar[x][2]);
             const bool cy = rr >= dv[x];
             rm[x] = cy ? rr - dv[x] : rr;
-            if constexpr (!GP) qt[x] += aq[x][k] + (cy ? 1u : 0u);
+            if constexpr (!GP) qt[x] += pick(aq[x][0], aq[x][1], aq[x][2]) + (cy ? 1u : 0u);
 #pragma unroll
             for (int r = 0; r < NR; r++) t[r] += cy ? jc[x][r] : 0u;
         }
@@ -394,14 +397,14 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
                 gi++;
                 c0 = st.c0; c1 = st.c1; c2 = st.c2;
             } else {
-                apply(2);
                 c2++;
-                if (c2 == e2) {
-                    c2 = 0;
-                    c1++;
-                    apply(1);
-                    if (c1 == e1) { c1 = 0; c0++; apply(0); }
-                }
+                const bool w1 = c2 == e2;
+                c2 = w1 ? 0u : c2;
+                c1 += w1 ? 1u : 0u;
+                const bool w0 = w1 && c1 == e1;
+                c1 = w0 ? 0u : c1;
+                c0 += w0 ? 1u : 0u;
+                apply(w0, w1);
             }
         }
     }

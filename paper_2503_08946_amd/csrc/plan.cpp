@@ -441,13 +441,12 @@ rv_status plan_kernel(const rv_kernel_desc *d, int target, rv_kernel &k, std::st
                         if (E.aux_kind[x] == RV_AUX_NONE) continue;
                         const int64_t d = ac.aux[x].d;
                         const int32_t *r = E.row[3 + x];
-                        // the numerator's change when the inner loop steps, and
-                        // the corrections from it to the middle loop's step and
-                        // from that to the outer loop's
+                        // the numerator's change when the inner, middle or outer
+                        // loop advances (the inner ones wrapping to their start)
                         const int64_t x2 = r[C_L2], x1 = (int64_t)r[C_L1] - (int64_t)r[C_L2] * (e2 - 1);
                         const int64_t x0 = (int64_t)r[C_L0] - (int64_t)r[C_L1] * (e1 - 1) - (int64_t)r[C_L2] * (e2 - 1);
-                        split(x0 - x1, d, E.astep[x][0]);
-                        split(x1 - x2, d, E.astep[x][1]);
+                        split(x0, d, E.astep[x][0]);
+                        split(x1, d, E.astep[x][1]);
                         split(x2, d, E.astep[x][2]);
                         // value range of the aux term (its numerator uses no aux variable)
                         int64_t mn, mx;

@@ -112,11 +112,10 @@ struct DevEntry {
     uint32_t fast;
     uint32_t ndim;
     uint32_t fr[NC];
-    // General entries (aux terms or guards).  astep[x][k] = (q, r), a
-    // change of aux numerator x written as q * d + r with 0 <= r < d (q
-    // modulo 2^32), so floor(n / d) and n mod d advance with adds and one
-    // carry: k = 2 the inner loop's step, k = 1 the correction from it to
-    // the middle loop's step, k = 0 from that to the outer loop's.  gproven: no
+    // General entries (aux terms or guards).  astep[x][k] = (q, r), the
+    // change of aux numerator x when the outer (k = 0), middle (1) or inner
+    // (2) loop advances, written as q * d + r with 0 <= r < d (q modulo
+    // 2^32), so floor(n / d) and n mod d advance with adds and one carry.  gproven: no
     // guards, and every index stays inside its dimension over the value
     // ranges of the variables and of the aux terms (no per-record test; the
     // location comes from the flattened row, fr[C_A0] and fr[C_A1] included).
