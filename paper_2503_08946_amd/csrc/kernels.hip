@@ -263,7 +263,7 @@ __device__ __forceinline__ ItemStart<FLAT> item_start(CEnt &E, CKer &K, uint32_t
 // inner loop wraps the middle loop's, or where that wraps the outer loop's
 // (each lane picks its own, so lanes at different points cost one step).
 // The division itself runs once per thread of a work item.
-template <bool FLAT, bool GP, class F>
+template <bool FLAT, bool GP, bool AUX, class F>
 __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t item, F &&f) {
     const uint32_t lch = E.lch, gt = E.gt;
     const ItemStart<FLAT> st = item_start<FLAT>(E, K, item);
@@ -276,6 +276,7 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
     const uint32_t dv[2] = {E.aux_mg[0].d, E.aux_mg[1].d};
     const uint32_t L0s = (uint32_t)E.lo[0] + st.c0, L1s = (uint32_t)E.lo[1] + st.c1, L2s = (uint32_t)E.lo[2] + st.c2;
     constexpr int NR = GP ? 1 : 3;       // running sums: the location, or the three indices
+    constexpr int NX = AUX ? 2 : 0;      // aux terms stepped (an entry of guards alone has none)
     // coefficient v of row r (GP: the flattened location row)
     auto cf = [&](int r, int v) -> uint32_t {
         if constexpr (GP) return E.fr[v];
@@ -284,8 +285,8 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
     auto lpart = [&](CI32 *row) {
         return (uint32_t)row[C_L0] * L0s + (uint32_t)row[C_L1] * L1s + (uint32_t)row[C_L2] * L2s;
     };
-    // per step form k (0: outer correction, 1: middle correction, 2: inner
-    // step): the aux splits, and each row's constant
+    // per step form k (the outer (0), middle (1) or inner (2) loop
+    // advances): the aux splits, and each row's constant
     uint32_t aq[2][3], ar[2][3], kc[NR][3], jc[2][NR], ts[NR];
 #pragma unroll
     for (int x = 0; x < 2; x++)
@@ -298,7 +299,7 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
         kc[r][2] = x2; kc[r][1] = x1; kc[r][0] = x0;
         ts[r] = cf(r, C_L0) * L0s + cf(r, C_L1) * L1s + cf(r, C_L2) * L2s;
 #pragma unroll
-        for (int x = 0; x < 2; x++) {
+        for (int x = 0; x < NX; x++) {
             const uint32_t ca = cf(r, C_A0 + x);
 #pragma unroll
             for (int k = 0; k < 3; k++) kc[r][k] += ca * (fd[x] ? aq[x][k] : ar[x][k]);
@@ -319,7 +320,7 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
 #pragma unroll
         for (int r = 0; r < NR; r++) t[r] += pick(kc[r][0], kc[r][1], kc[r][2]);
 #pragma unroll
-        for (int x = 0; x < 2; x++) {
+        for (int x = 0; x < NX; x++) {
             const uint32_t rr = rm[x] + pick(ar[x][0], ar[x][1], ar[x][2]);
             const bool cy = rr >= dv[x];
             rm[x] = cy ? rr - dv[x] : rr;
@@ -349,9 +350,9 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
                 return cf(r, C_TX) * (uint32_t)tx + cf(r, C_TY) * (uint32_t)ty + cf(r, C_BX) * (uint32_t)bx +
                        cf(r, C_BY) * (uint32_t)by + cf(r, C_C0);
             };
-            uint32_t a[2];
+            uint32_t a[2] = {0, 0};
 #pragma unroll
-            for (int x = 0; x < 2; x++) {
+            for (int x = 0; x < NX; x++) {
                 CI32 *row = E.row[3 + x];
                 const int32_t n = (int32_t)((uint32_t)row[C_TX] * (uint32_t)tx + (uint32_t)row[C_TY] * (uint32_t)ty +
                                             (uint32_t)row[C_BX] * (uint32_t)bx + (uint32_t)row[C_BY] * (uint32_t)by +
@@ -413,8 +414,9 @@ __device__ __forceinline__ void expand_gen(CSub &S, CEnt &E, CKer &K, CI32 *G, u
 // Evaluate an entry with aux terms or guards (the general path).
 template <bool FLAT, class F>
 __device__ __forceinline__ void expand_item(CSub &S, CEnt &E, CKer &K, CI32 *G, uint32_t item, F &&f) {
-    if (E.gproven) expand_gen<FLAT, true>(S, E, K, G, item, f);
-    else expand_gen<FLAT, false>(S, E, K, G, item, f);
+    if (E.gproven) expand_gen<FLAT, true, true>(S, E, K, G, item, f);
+    else if (E.aux_kind[0] != 0 || E.aux_kind[1] != 0) expand_gen<FLAT, false, true>(S, E, K, G, item, f);
+    else expand_gen<FLAT, false, false>(S, E, K, G, item, f);
 }
 
 // Fast path of expand_item for entries without aux terms or guards: the
