@@ -289,7 +289,7 @@ struct WorkspaceLayout {
     // hot buckets (more than HOT records): their list, its length, a
     // completion counter and a four-table location summary per entry
     size_t cap_hot = 0;
-    size_t off_hot_n = 0, off_hot_list = 0, off_hot_done = 0, off_hot_tab = 0;
+    size_t off_hot_n = 0, off_hot_list = 0, off_hot_tab = 0;
     // medium buckets (one fold slice < records <= HOT): their list and length
     size_t cap_mid = 0;
     size_t off_mid_n = 0, off_mid_list = 0;
@@ -398,7 +398,7 @@ void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigne
                    const uint32_t *starts, const uint32_t *counts, uint32_t *conf, int debug_sorted,
                    unsigned ncu, hipStream_t st);
 struct HotArea {
-    uint32_t *n, *list, *done, *tab;
+    uint32_t *n, *list, *tab;
     uint32_t cap;
     uint32_t *mid_n, *mid_list;
     uint32_t mid_cap;
