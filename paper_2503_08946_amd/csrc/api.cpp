@@ -92,9 +92,10 @@ struct Lane {
     uint32_t *bsum() const { return reinterpret_cast<uint32_t *>(ws + L.off_bsum); }
     HotArea hot() const {
         return HotArea{reinterpret_cast<uint32_t *>(ws + L.off_hot_n), reinterpret_cast<uint32_t *>(ws + L.off_hot_list),
-                       reinterpret_cast<uint32_t *>(ws + L.off_hot_tab),
+                       reinterpret_cast<uint32_t *>(ws + L.off_hot_sub), reinterpret_cast<uint32_t *>(ws + L.off_hot_tab),
                        (uint32_t)L.cap_hot, reinterpret_cast<uint32_t *>(ws + L.off_mid_n),
-                       reinterpret_cast<uint32_t *>(ws + L.off_mid_list), (uint32_t)L.cap_mid};
+                       reinterpret_cast<uint32_t *>(ws + L.off_mid_list), reinterpret_cast<uint32_t *>(ws + L.off_mid_sub),
+                       (uint32_t)L.cap_mid};
     }
 };
 

@@ -1976,7 +1976,7 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
         const bool is_hot = c > HOT;
         if (c > FOLD_CAP && !is_hot) {                   // medium: k_mid folds it
             const uint32_t slot = atomicAdd(hot.mid_n, 1u);
-            if (slot < hot.mid_cap) hot.mid_list[slot] = mb;
+            if (slot < hot.mid_cap) { hot.mid_list[slot] = mb; hot.mid_sub[slot] = ms; }
         }
         if (inr && !take && !wave) conf[mb] = 0;
         uint32_t all;      // fields of 10 bits: workgroup list, hot list, wave list
@@ -1994,7 +1994,7 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
         if (is_hot) {
             const uint32_t slot = atomicAdd(hot.n, 1u);
             l_hot[(pos >> 10) & 1023u] = slot;
-            if (slot < hot.cap) hot.list[slot] = mb;
+            if (slot < hot.cap) { hot.list[slot] = mb; hot.sub[slot] = ms; }
         }
         __syncthreads();
         for (uint32_t j = 0; j < nh; j++) {     // clear the hot buckets' summaries
@@ -2082,7 +2082,7 @@ __global__ void __launch_bounds__(BKT_WG) k_mid(const DevSub *subs_g, uint32_t n
     for (uint32_t i = blockIdx.x; i < nm; i += gridDim.x) {
         const uint32_t b = hot.mid_list[i];
         const uint32_t cnt = counts[b], start = starts[b];
-        CSub &S = subs[sub_of_bucket(subs, nsub, b)];
+        CSub &S = subs[hot.mid_sub[i]];
         const uint32_t lo = S.klo + ((b - S.bucket_begin) << S.s);
         const uint32_t width = min(1u << S.s, S.khi - lo);
 #pragma unroll
@@ -2115,7 +2115,7 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
                                                  const uint32_t *__restrict__ counts, HotArea hot,
                                                  SubResult *__restrict__ res) {
     __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
-    __shared__ uint32_t h_pre[BKT_WG + 1], h_b[BKT_WG], h_cnt[BKT_WG];
+    __shared__ uint32_t h_pre[BKT_WG + 1], h_b[BKT_WG], h_cnt[BKT_WG], h_sub[BKT_WG];
     __shared__ uint32_t red[BKT_WG / 64];
     CSub *subs = cptr(subs_g);
     const uint32_t t = threadIdx.x;
@@ -2129,12 +2129,12 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
     for (uint32_t base = 0; base < nh; base += BKT_WG) {
         // the group's entries and the prefix of their part counts
         const uint32_t i = base + t;
-        uint32_t b = 0, cnt = 0;
-        if (i < nh) { b = hot.list[i]; cnt = counts[b]; }
+        uint32_t b = 0, cnt = 0, sb = 0;
+        if (i < nh) { b = hot.list[i]; cnt = counts[b]; sb = hot.sub[i]; }
         const uint32_t parts = (cnt + HOT_PART - 1) / HOT_PART;
         uint32_t tot;
         const uint32_t pre = block_excl_add<BKT_WG>(parts, red, &tot);
-        h_pre[t] = pre; h_b[t] = b; h_cnt[t] = cnt;
+        h_pre[t] = pre; h_b[t] = b; h_cnt[t] = cnt; h_sub[t] = sb;
         if (t == 0) h_pre[BKT_WG] = tot;
         __syncthreads();
         // parts u .. u + tot - 1 go to workgroups round-robin
@@ -2148,7 +2148,7 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
             const uint32_t e = lo_e, q = p - h_pre[e];
             const uint32_t bk = h_b[e], bcnt = h_cnt[e];
             const uint32_t start = starts[bk];
-            CSub &S = subs[sub_of_bucket(subs, nsub, bk)];
+            CSub &S = subs[uni(h_sub[e])];
             const uint32_t lo = S.klo + ((bk - S.bucket_begin) << S.s);
             const uint32_t width = min(1u << S.s, S.khi - lo);
 #pragma unroll
@@ -2189,7 +2189,7 @@ __global__ void __launch_bounds__(BKT_WG) k_hot_judge(const DevSub *subs_g, uint
     const uint32_t nh = min(*hot.n, hot.cap);
     for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
         const uint32_t bk = hot.list[j];
-        CSub &S = subs[sub_of_bucket(subs, nsub, bk)];
+        CSub &S = subs[hot.sub[j]];
         const uint32_t lo = S.klo + ((bk - S.bucket_begin) << S.s);
         const uint32_t width = min(1u << S.s, S.khi - lo);
         const uint32_t *g = hot.tab + (size_t)j * 4 * TBL;

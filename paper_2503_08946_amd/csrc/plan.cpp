@@ -656,10 +656,12 @@ WorkspaceLayout layout_workspace(size_t bytes) {
         L.off_bsum = off; off = al(off + scan_bsum_words(BC) * 4);
         L.off_hot_n = off; off = al(off + 4);
         L.off_hot_list = off; off = al(off + H * 4);
+        L.off_hot_sub = off; off = al(off + H * 4);
         L.off_hot_tab = off; off = al(off + H * 4 * TBL * 4);
         const size_t Mc = R / FOLD_CAP + 1;   // at most this many buckets exceed one fold slice
         L.off_mid_n = off; off = al(off + 4);
         L.off_mid_list = off; off = al(off + Mc * 4);
+        L.off_mid_sub = off; off = al(off + Mc * 4);
         L.cap_mid = Mc;
         L.cap_records = R;
         L.cap_buckets = BC;

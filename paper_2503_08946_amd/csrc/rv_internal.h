@@ -289,10 +289,10 @@ struct WorkspaceLayout {
     // hot buckets (more than HOT records): their list, its length, a
     // completion counter and a four-table location summary per entry
     size_t cap_hot = 0;
-    size_t off_hot_n = 0, off_hot_list = 0, off_hot_tab = 0;
+    size_t off_hot_n = 0, off_hot_list = 0, off_hot_sub = 0, off_hot_tab = 0;
     // medium buckets (one fold slice < records <= HOT): their list and length
     size_t cap_mid = 0;
-    size_t off_mid_n = 0, off_mid_list = 0;
+    size_t off_mid_n = 0, off_mid_list = 0, off_mid_sub = 0;
     size_t bytes = 0;
 };
 
@@ -398,9 +398,9 @@ void launch_bucket(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigne
                    const uint32_t *starts, const uint32_t *counts, uint32_t *conf, int debug_sorted,
                    unsigned ncu, hipStream_t st);
 struct HotArea {
-    uint32_t *n, *list, *tab;
+    uint32_t *n, *list, *sub, *tab;     // hot buckets: count, bucket, its pass, merged summaries
     uint32_t cap;
-    uint32_t *mid_n, *mid_list;
+    uint32_t *mid_n, *mid_list, *mid_sub;
     uint32_t mid_cap;
 };
 void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned long long *rec,
