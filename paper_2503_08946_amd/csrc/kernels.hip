@@ -1818,25 +1818,24 @@ __device__ __forceinline__ uint32_t judge_tables(uint32_t *t_mn, uint32_t *t_mx,
 
 // Sparse buckets (at most WCAP records, no sub-keys) are folded by one wave
 // each, four at a time per workgroup, with wave barriers only.  The fold
-// lists the locations it touches first (the atomic that finds a slot empty),
-// so the judge visits those alone rather than the bucket's whole width; a
-// bit per location marks the conflicts, and a witness's place in location
-// order is the count of marked bits below it.
+// also marks each location it touches in a bitmap, so the judge visits the
+// touched locations alone, in location order, rather than the bucket's whole
+// width: 64 at a time, a ballot of the conflicting ones gives each witness
+// its place.
 constexpr uint32_t WCAP = 64 * FOLD_RPL;
 
 struct WaveTab {
     uint32_t *mn, *mx, *mnw, *mxw1;
-    uint16_t *touched;      // locations in first-touch order (at most WCAP)
-    uint32_t *nt;           // their count
-    uint32_t *mask;         // TBL bits: the location holds a conflict
-    uint32_t *pre;          // conflicts in the mask words below each word
+    uint32_t *seen;         // TBL bits: the location was touched
+    uint16_t *touched;      // the touched locations, ascending (at most WCAP)
 };
 
 __device__ __forceinline__ void wave_fold_touch(const Run<64> &r, uint32_t lo, const WaveTab &W) {
     Seg cur{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
     uint32_t pk = 0xFFFFu;
     auto flush = [&](uint32_t k) {
-        if (atomicMin(&W.mn[k], cur.mn) == 0xFFFFFFFFu) W.touched[atomicAdd(W.nt, 1u)] = (uint16_t)k;
+        atomicOr(&W.seen[k >> 5], 1u << (k & 31));
+        atomicMin(&W.mn[k], cur.mn);
         atomicMax(&W.mx[k], cur.mx);
         if (cur.mxw1) {
             atomicMin(&W.mnw[k], cur.mnw);
@@ -1860,40 +1859,44 @@ __device__ __forceinline__ void wave_fold_touch(const Run<64> &r, uint32_t lo, c
 }
 
 // Judge the touched locations of a wave's folded bucket, write its witnesses
-// in location order at wout, leave the tables empty; returns the count.
+// in location order at wout, leave the tables and the bitmap empty; returns
+// the count.
 __device__ __forceinline__ uint32_t wave_judge(const WaveTab &W, uint32_t lo, Magic mgM, uint32_t *wout) {
     constexpr uint32_t NW = TBL / 32;
-    static_assert(NW <= 64, "one mask word per lane");
+    static_assert(NW <= 64, "one bitmap word per lane");
     const uint32_t ln = lane();
     wave_sync_lds();
-    const uint32_t nt = *W.nt;
-    for (uint32_t j = ln; j < nt; j += 64) {
-        const uint32_t k = W.touched[j];
-        const Seg e{0u, W.mn[k], W.mx[k], W.mnw[k], W.mxw1[k]};
-        uint32_t sc, sr;
-        if (judge(e, mgM, sc, sr)) atomicOr(&W.mask[k >> 5], 1u << (k & 31));
-    }
-    wave_sync_lds();
-    const uint32_t mw = ln < NW ? W.mask[ln] : 0u;
-    const uint32_t inc = wave_incl_add((uint32_t)__builtin_popcount(mw));
-    if (ln < NW) W.pre[ln] = inc - (uint32_t)__builtin_popcount(mw);
-    const uint32_t total = readlane(inc, 63);
-    wave_sync_lds();
-    for (uint32_t j = ln; j < nt; j += 64) {
-        const uint32_t k = W.touched[j];
-        const Seg e{0u, W.mn[k], W.mx[k], W.mnw[k], W.mxw1[k]};
-        const uint32_t m = W.mask[k >> 5];
-        if ((m >> (k & 31)) & 1u) {
-            uint32_t sc = 0, sr = 0;
-            judge(e, mgM, sc, sr);
-            put_witness(wout, W.pre[k >> 5] + (uint32_t)__builtin_popcount(m & ((1u << (k & 31)) - 1u)), lo + k, e,
-                        sc, sr);
+    // the touched list: lane l < NW lists the set bits of word l at the
+    // count of set bits in the words before it
+    uint32_t w = ln < NW ? W.seen[ln] : 0u;
+    const uint32_t cnt = (uint32_t)__builtin_popcount(w);
+    const uint32_t inc = wave_incl_add(cnt);
+    const uint32_t nt = readlane(inc, 63);
+    if (ln < NW) {
+        uint32_t at = inc - cnt;
+        while (w) {
+            W.touched[at++] = (uint16_t)(ln * 32u + (uint32_t)__builtin_ctz(w));
+            w &= w - 1u;
         }
-        W.mn[k] = 0xFFFFFFFFu; W.mx[k] = 0; W.mnw[k] = 0xFFFFFFFFu; W.mxw1[k] = 0;
+        W.seen[ln] = 0u;
     }
     wave_sync_lds();
-    if (ln < NW) W.mask[ln] = 0;
-    if (ln == 0) *W.nt = 0;
+    uint32_t total = 0;
+    for (uint32_t j0 = 0; j0 < nt; j0 += 64) {
+        const uint32_t j = j0 + ln;
+        bool c = false;
+        uint32_t k = 0, sc = 0, sr = 0;
+        Seg e{0u, 0u, 0u, 0u, 0u};
+        if (j < nt) {
+            k = W.touched[j];
+            e = Seg{0u, W.mn[k], W.mx[k], W.mnw[k], W.mxw1[k]};
+            W.mn[k] = 0xFFFFFFFFu; W.mx[k] = 0; W.mnw[k] = 0xFFFFFFFFu; W.mxw1[k] = 0;
+            c = judge(e, mgM, sc, sr);
+        }
+        const uint64_t m = __ballot(c);
+        if (c) put_witness(wout, total + mbcnt(m), lo + k, e, sc, sr);
+        total += (uint32_t)__popcll(m);
+    }
     wave_sync_lds();
     return total;
 }
@@ -1918,7 +1921,7 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
     // four waves' tables (the workgroup's buckets use wave 0's)
     __shared__ uint32_t wt[BKT_WG / 64][4][TBL];
     __shared__ uint16_t w_touched[BKT_WG / 64][WCAP];
-    __shared__ uint32_t w_nt[BKT_WG / 64], w_mask[BKT_WG / 64][TBL / 32], w_pre[BKT_WG / 64][TBL / 32];
+    __shared__ uint32_t w_seen[BKT_WG / 64][TBL / 32];
     // a group lists at most FOLD_GROUP buckets
     __shared__ uint32_t l_b[FOLD_GROUP], l_cnt[FOLD_GROUP], l_st[FOLD_GROUP], l_hot[FOLD_GROUP], l_sub[FOLD_GROUP];
     __shared__ uint32_t v_b[FOLD_GROUP], v_cnt[FOLD_GROUP], v_st[FOLD_GROUP], v_sub[FOLD_GROUP];
@@ -1933,13 +1936,12 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
     if (r * gsz >= nbuckets) return;
     uint32_t sidx = sub_of_bucket(subs, nsub, r * gsz);   // groups only increase: walk forward
     const uint32_t wv = t >> 6;
-    const WaveTab W{wt[wv][0], wt[wv][1], wt[wv][2], wt[wv][3], w_touched[wv], &w_nt[wv], w_mask[wv], w_pre[wv]};
+    const WaveTab W{wt[wv][0], wt[wv][1], wt[wv][2], wt[wv][3], w_seen[wv], w_touched[wv]};
     for (uint32_t k = t; k < (BKT_WG / 64) * TBL; k += BKT_WG) {
         const uint32_t q = k / TBL, e = k % TBL;
         wt[q][0][e] = 0xFFFFFFFFu; wt[q][1][e] = 0; wt[q][2][e] = 0xFFFFFFFFu; wt[q][3][e] = 0;
     }
-    if (t < (BKT_WG / 64) * (TBL / 32)) w_mask[t / (TBL / 32)][t % (TBL / 32)] = 0;
-    if (t < BKT_WG / 64) w_nt[t] = 0;
+    if (t < (BKT_WG / 64) * (TBL / 32)) w_seen[t / (TBL / 32)][t % (TBL / 32)] = 0;
     for (uint32_t base = r * gsz; base < nbuckets; base += G * gsz) {
         // --- list this group's non-empty buckets (in order): sparse ones of
         // passes without sub-keys for the waves, the others for the
