@@ -2071,8 +2071,7 @@ __global__ void __launch_bounds__(BKT_WG) k_fold(const DevSub *subs_g, uint32_t 
 
 // Medium buckets (more records than one fold slice, at most HOT): one
 // workgroup per bucket, slice after slice.
-__global__ void __launch_bounds__(BKT_WG) k_mid(const DevSub *subs_g, uint32_t nsub,
-                                                 unsigned long long *__restrict__ rec,
+__global__ void __launch_bounds__(BKT_WG) k_mid(const DevSub *subs_g, unsigned long long *__restrict__ rec,
                                                  const uint32_t *__restrict__ starts,
                                                  const uint32_t *__restrict__ counts, uint32_t *__restrict__ conf,
                                                  HotArea hot) {
@@ -2180,8 +2179,7 @@ __global__ void __launch_bounds__(BKT_WG) k_hot(const DevSub *subs_g, uint32_t n
 }
 
 // Judge each hot bucket from its merged summary: one workgroup per bucket.
-__global__ void __launch_bounds__(BKT_WG) k_hot_judge(const DevSub *subs_g, uint32_t nsub,
-                                                       unsigned long long *__restrict__ rec,
+__global__ void __launch_bounds__(BKT_WG) k_hot_judge(const DevSub *subs_g, unsigned long long *__restrict__ rec,
                                                        const uint32_t *__restrict__ starts,
                                                        uint32_t *__restrict__ conf, HotArea hot) {
     __shared__ uint32_t t_mn[TBL], t_mx[TBL], t_mnw[TBL], t_mxw1[TBL];
@@ -3249,9 +3247,9 @@ void launch_fold(const DevSub *subs, uint32_t nsub, uint64_t nbuckets, unsigned 
     else
         hipLaunchKernelGGL(k_fold<0>, dim3(G), dim3(BKT_WG), 0, st, subs, nsub, (uint32_t)nbuckets, rec, starts,
                            counts, conf, hot);
-    hipLaunchKernelGGL(k_mid, dim3(ncu * occ_mid), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, conf, hot);
+    hipLaunchKernelGGL(k_mid, dim3(ncu * occ_mid), dim3(BKT_WG), 0, st, subs, rec, starts, counts, conf, hot);
     hipLaunchKernelGGL(k_hot, dim3(ncu * occ_hot), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, counts, hot, res);
-    hipLaunchKernelGGL(k_hot_judge, dim3(ncu), dim3(BKT_WG), 0, st, subs, nsub, rec, starts, conf, hot);
+    hipLaunchKernelGGL(k_hot_judge, dim3(ncu), dim3(BKT_WG), 0, st, subs, rec, starts, conf, hot);
 }
 
 void launch_small(const DevSub *subs, uint32_t n, SubResult *res, unsigned ncu, hipStream_t st) {
