@@ -409,3 +409,45 @@ def test_witness_windows(ctx):
     assert [_wkey(w) for w in mid] == [_wkey(w) for w in full[1000:1077]]
     tail = ctx.witnesses(k, 16380, 100)
     assert len(tail) == 4
+
+
+def _read_only(i):
+    # 4,096 global reads, no write: a pass of the HBM pipeline (above the
+    # small-pass threshold) that is counted only and has no buckets
+    b = Builder((64, 1), (16, 1), f"read-only-{i}")
+    g = b.array(GLOBAL, (1024,), "g")
+    b.segment([b.phase([rw(g, False, aff(i, tx=3, bx=5), loops=((0, 4),))], barrier_after=False)])
+    return b.build()
+
+
+def _writer(i):
+    # 3,072 records over a 4M-element array (8,192 buckets, most of them
+    # empty): thread t reads what thread t + 1 writes
+    b = Builder((64, 1), (16, 1), f"writer-{i}")
+    g = b.array(GLOBAL, (1 << 22,), "g")
+    b.segment([b.phase([rw(g, True, aff(i, tx=1024, bx=65536), loops=((0, 2),)),
+                        rw(g, False, aff(1024 + i, tx=1024, bx=65536))], barrier_after=False)])
+    return b.build()
+
+
+def test_batch_groups_spanning_many_passes_without_buckets(ctx):
+    """A batch where more than one fold group's worth of bucket-less passes
+    (read-only kernels, counted only) lies between two kernels with buckets:
+    the fold finds each bucket's pass past its table of the group's next
+    passes.  Every kernel's counts and first witness equal the oracle's."""
+    descs = [_writer(0)] + [_read_only(i) for i in range(80)] + [_writer(1)] + \
+        [_read_only(80 + i) for i in range(3)] + [_writer(2)]
+    want = []
+    for d in descs:
+        o = oracle.check(d, max_witnesses=1)
+        assert o.status == 0
+        want.append((o.n_records, o.n_conflicts, _wkey(o.witnesses[0]) if o.n_conflicts else None))
+    assert all(w[1] > 0 for w, d in zip(want, descs) if d.name.startswith("writer"))
+    ks = [ctx.load(d) for d in descs]
+    try:
+        got = [(r.n_records, r.n_conflicts, _wkey(r.witness) if r.witness is not None else None)
+               for r in ctx.check_batch(ks)]
+        assert got == want
+    finally:
+        for k in ks:
+            k.free()
